@@ -1,0 +1,235 @@
+"""Benchmark: AxLocal throughput (GDOF/s) and roofline fraction on one MI355X.
+
+Workload (one "step" = one application of the element-local Poisson operator with on-the-fly
+trilinear geometric factors, FP64): N = 7 (8^3 GLL nodes per element), E = 32^3 = 32768
+trilinear hexes of the unit cube with interior vertices jittered by +-15 % of h (seed 7),
+X ~ U[-1, 1] (16.8 M local DOFs).  Inputs are resident in HBM before timing; four X/Y pairs
+(1 GiB) rotate so that every step streams from HBM rather than the 256 MB Infinity Cache.
+
+Prints ONE JSON line (rank 0).  Extra fields: the stored-factor baseline on the same mesh (the
+roofline the paper raises), the parallelepiped variant (N = 7, 32^3 sheared cube), FP32, and the
+CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
+PEAK_FP64_TFS = 78.6        # MI355X FP64 vector (= FP64 matrix)
+PEAK_FP32_TFS = 157.3
+
+
+def flops_per_element(N, geom="tri", nrhs=1):
+    """Per-element FLOPs: F_ax (Table 2, Poisson) per column plus F_geo (Table 3): trilinear
+    72 N1 + 45 N1^2 + 80 N1^3, parallelepiped 7 N1^3, stored factors 0."""
+    N1 = N + 1
+    f_ax = 12 * N1**4 + 15 * N1**3
+    f_geo = {"tri": 72 * N1 + 45 * N1**2 + 80 * N1**3, "para": 7 * N1**3, "stored": 0}[geom]
+    return nrhs * f_ax, f_geo
+
+
+def bytes_per_element(N, geom="tri", nrhs=1, fpsize=8):
+    """Algorithmic HBM bytes per element: X read + Y write (nrhs columns) plus the geometry input
+    (24 vertex words, 6 h words, or 6 N1^3 stored factors); D is cache-resident."""
+    N1 = N + 1
+    geo = {"tri": 24 * 8, "para": 6 * 8, "stored": 6 * N1**3 * fpsize}[geom]
+    return 2 * nrhs * N1**3 * fpsize + geo
+
+
+def time_steps(fn, steps, warmup, nbuf):
+    """Warm up, then time `steps` calls (buffer index rotates) with one event pair per call on
+    torch's current stream (the stream every library call is enqueued on)."""
+    import torch
+    for s in range(warmup):
+        fn(s % nbuf)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for s in range(steps):
+        ev[s][0].record()
+        fn(s % nbuf)
+        ev[s][1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = np.array([a.elapsed_time(b) for a, b in ev]) * 1e-3
+    return wall, per
+
+
+def cpu_baseline(mesh, N, X, budget_s=10.0):
+    """The oracle (plain FP64 loops, OpenMP over elements): stored factors from the vertices
+    (Eq. 7) then AxLocal (Algorithm 1), on a bounded sample of the same mesh, repeated until
+    about `budget_s` seconds of CPU time have elapsed."""
+    import oracle
+    xi, w, D = oracle.gll(N)
+    nsamp = min(mesh.E, 4096)
+    V = np.ascontiguousarray(mesh.verts[:nsamp])
+    Xs = np.ascontiguousarray(X[:, :nsamp])
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        G, _, _ = oracle.geom_factors(V, N, xi, w)
+        oracle.ax_local(D, G, Xs)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    dofs = reps * nsamp * (N + 1) ** 3 * X.shape[0]
+    return {"value": dofs / el / 1e9, "unit": "GDOF/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{nsamp} of {mesh.E} elements (first {nsamp}), N={N}, nrhs={X.shape[0]}, "
+                      f"geometric factors + AxLocal, {reps} repetitions in {el:.1f} s"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--N", type=int, default=7)
+    ap.add_argument("--grid", type=int, nargs=3, default=None)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extras", action="store_true", help="only the headline kernel")
+    ap.add_argument("--calib", action="store_true",
+                    help="also run a plain 128 MiB device copy (counter calibration)")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build measures one GPU only; run with --gpus 1 "
+              "(the element-parallel operator shards by element slabs; see DESIGN.md)", file=sys.stderr)
+        return 2
+
+    import torch
+    import paper_2504_07042_amd as ax
+    from paper_2504_07042_amd import meshgen
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    ax.lib()
+    dev = torch.device("cuda:0")
+    N = args.N
+    N1 = N + 1
+    grid = tuple(args.grid) if args.grid else meshgen.grid_for_nodes(N)
+    mesh = meshgen.jittered_hex(*grid, alpha=0.15, seed=N)
+    E = mesh.E
+    NP = N1**3
+    b = ax.Basis(N)
+    NBUF = 4
+    X_host = meshgen.random_nodal(E, N, nrhs=1, seed=N)
+    Xs = [torch.from_numpy(X_host).to(dev) for _ in range(NBUF)]
+    Ys = [torch.empty_like(Xs[0]) for _ in range(NBUF)]
+    V = torch.from_numpy(mesh.verts).to(dev)
+    torch.cuda.synchronize()
+
+    def step(q):
+        ax.ax_local(Xs[q], V, b, ax.AX_TRILINEAR, ax.AX_FP64, out=Ys[q])
+
+    wall, per = time_steps(step, args.steps, args.warmup, NBUF)
+    t_kernel = float(per.mean())
+    dofs = E * NP
+    gdofs = dofs * args.steps / wall / 1e9
+    f_ax, f_geo = flops_per_element(N, "tri")
+    by = bytes_per_element(N, "tri")
+    achieved_tf = (f_ax + f_geo) * E / t_kernel / 1e12
+    achieved_gbs = by * E / t_kernel / 1e9
+    # time-based roofline (Sec. 3.4): T_cmp = (F_ax + F_geo) / P, T_mem = M / B
+    t_cmp = (f_ax + f_geo) * E / (PEAK_FP64_TFS * 1e12)
+    t_mem = by * E / (PEAK_HBM_GBS * 1e9)
+    compute_bound = t_cmp >= t_mem
+    roofline = {
+        "bound": "alu" if compute_bound else "hbm",
+        "achieved": round(achieved_tf if compute_bound else achieved_gbs, 3),
+        "peak": PEAK_FP64_TFS if compute_bound else PEAK_HBM_GBS,
+        "unit": "TFLOP/s" if compute_bound else "GB/s",
+        "frac": round((achieved_tf / PEAK_FP64_TFS) if compute_bound else (achieved_gbs / PEAK_HBM_GBS), 4),
+        "traffic": None,
+        "kernel": "ax_local_kernel<N1=8, trilinear, double>",
+        "per_launch": {"elements": E, "flops_per_element": f_ax + f_geo, "bytes_per_element": by,
+                       "avg_launch_ms": round(t_kernel * 1e3, 4)},
+        "hbm_GBs_achieved": round(achieved_gbs, 1),
+        "R_eff_GDOFs": round(dofs / max(t_cmp, t_mem) / 1e9, 1),
+        "pct_of_R_eff": round(max(t_cmp, t_mem) / t_kernel, 4),
+    }
+
+    out = {
+        "metric": "AxLocal GDOF/s (N=7 trilinear FP64, on-the-fly geometric factors)",
+        "value": round(gdofs, 3),
+        "unit": "GDOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"AxLocal trilinear N={N} E={grid[0]}x{grid[1]}x{grid[2]}={E} jitter 15% seed {N}",
+                   "N": N, "E": E, "local_dofs": dofs, "nrhs": 1, "geometry": "trilinear",
+                   "precision": "fp64"},
+        "roofline": roofline,
+    }
+
+    if not args.no_extras:
+        extras = {}
+        # stored-factor baseline on the same mesh: the roofline the paper raises
+        G, _ = ax.geom_factors(V, b, ax.AX_FP64)
+
+        def step_g(q):
+            ax.ax_local_precomputedG(Xs[q], G, b, ax.AX_FP64, out=Ys[q])
+
+        wall_g, per_g = time_steps(step_g, args.steps, args.warmup, NBUF)
+        byg = bytes_per_element(N, "stored")
+        extras["stored_G_fp64"] = {"GDOFs": round(dofs * args.steps / wall_g / 1e9, 3),
+                                   "hbm_GBs": round(byg * E / per_g.mean() / 1e9, 1),
+                                   "R_orig_GDOFs": round(dofs / (byg * E / (PEAK_HBM_GBS * 1e9)) / 1e9, 1)}
+        extras["speedup_on_the_fly_vs_stored"] = round(wall_g / wall, 3)
+        del G
+        # FP32 on-the-fly on the same mesh
+        X32 = [x.float() for x in Xs]
+        Y32 = [y.float() for y in Ys]
+
+        def step32(q):
+            ax.ax_local(X32[q], V, b, ax.AX_TRILINEAR, ax.AX_FP32, out=Y32[q])
+
+        wall32, _ = time_steps(step32, args.steps, args.warmup, NBUF)
+        extras["trilinear_fp32_GDOFs"] = round(dofs * args.steps / wall32 / 1e9, 3)
+        del X32, Y32
+        # parallelepiped elements (32^3 sheared cube, N = 7)
+        pm, _ = meshgen.parallelepiped_hex(*grid, seed=2)
+        h = ax.parallelepiped_factors(torch.from_numpy(pm.verts).to(dev))
+
+        def step_p(q):
+            ax.ax_local(Xs[q], h, b, ax.AX_PARALLELEPIPED, ax.AX_FP64, out=Ys[q])
+
+        wall_p, per_p = time_steps(step_p, args.steps, args.warmup, NBUF)
+        byp = bytes_per_element(N, "para")
+        extras["parallelepiped_fp64"] = {"GDOFs": round(dofs * args.steps / wall_p / 1e9, 3),
+                                         "hbm_GBs": round(byp * E / per_p.mean() / 1e9, 1)}
+        out["extras"] = extras
+
+    if args.calib:
+        a = torch.empty(16 * 2**20, dtype=torch.float64, device=dev).uniform_()
+        c = torch.empty_like(a)
+        for _ in range(3):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes_each_way"] = a.numel() * 8
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(mesh, N, X_host)
+
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

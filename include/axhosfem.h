@@ -1,0 +1,219 @@
+/*
+ * axhosfem.h - C ABI of the MI355X (gfx950) matrix-free element-local Poisson operator with
+ * on-the-fly geometric factors, after Cao, Sun, Zhang, Li, "Towards a Higher Roofline for
+ * Matrix-Vector Multiplication in Matrix-Free HOSFEM" (arXiv 2504.07042).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - N is the polynomial order, N1 = N + 1 GLL points per direction, 1 <= N <= 15.
+ *  - A local (element-wise) vector holds [nrhs][E][N1^3] values; node [i,j,k] of element e is
+ *    at index i + j*N1 + k*N1^2 (the index rule stated with Algorithm 1, Sec. 2.2).
+ *  - Vertex arrays are double [E][8][3] in the tensor order of the trilinear map (Eq. 8):
+ *    vertex v = a + 2b + 4c sits at reference corner (2a-1, 2b-1, 2c-1).
+ *  - Pointers marked [dev] are device pointers, [host] are host pointers.  Every buffer belongs to
+ *    the caller; the library never frees or keeps a pointer after the call returns.  Host
+ *    arrays are read during the call only (they are copied into kernel arguments).
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Device work is
+ *    enqueued on it and the call returns without synchronising, unless stated otherwise.
+ *  - Every function returns an ax_status and never throws or aborts.  Arguments are validated
+ *    on the host before anything is enqueued; on error nothing is enqueued and
+ *    ax_last_error() describes the problem.  E == 0 (or an empty vector) is a valid no-op.
+ *  - Device buffers must not overlap unless stated otherwise.
+ */
+#ifndef AXHOSFEM_H
+#define AXHOSFEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    AX_OK = 0,
+    AX_ERR_ARG = -1,           /* invalid argument (null pointer, negative size, aliasing ...) */
+    AX_ERR_UNSUPPORTED = -2,   /* valid but not implemented (order, precision, geometry) */
+    AX_ERR_HIP = -3,           /* a HIP runtime call failed; see ax_last_error() */
+    AX_ERR_NOMEM = -4,         /* workspace too small */
+    AX_ERR_NOT_CONVERGED = -5, /* iteration limit reached before the tolerance */
+    AX_ERR_BREAKDOWN = -6      /* CG breakdown: p^T A p <= 0 or a non-finite scalar */
+} ax_status;
+
+/* Geometry of the elements handed to ax_local. */
+enum { AX_TRILINEAR = 0, AX_PARALLELEPIPED = 1 };
+
+/* Arithmetic of a kernel.  AX_FP64: X, Y and G are double.  AX_FP32: X, Y and G are float,
+ * all arithmetic float (vertex differences and per-element geometry set-up in double).
+ * AX_FP16_ACC32: X and Y are float; X and the D-contraction operands are rounded to half and
+ * multiplied on the matrix cores with float accumulation; geometric factors stay float. */
+enum { AX_FP64 = 0, AX_FP32 = 1, AX_FP16_ACC32 = 2 };
+
+/* Message for the last non-OK status returned on the calling thread ("" if none). */
+const char* ax_last_error(void);
+
+/* Library version string. */
+const char* ax_version(void);
+
+/*
+ * ax_gll - GLL points xi[N1], weights w[N1] and the differentiation matrix D[N1*N1] (row-major,
+ * D[i*N1 + j] = pi_j'(xi_i)) of order N (Sec. 2.1, Table 1).  The diagonal of D is minus the
+ * sum of the rest of its row (exactly the closed form in exact arithmetic).  [host] outputs.
+ * Supports 1 <= N <= 31.
+ */
+int ax_gll(int N, double* xi, double* w, double* D);
+
+/*
+ * ax_local - Y = AxLocal(X): the element-local Poisson operator Y_e = D^T G_e D X_e of Eq. (3)
+ * (Lambda0 = I, Lambda1 = 0), applied by sum factorisation as in Algorithm 1, with the six
+ * geometric factors G_e recomputed inside the kernel instead of being read from memory:
+ *   geom == AX_TRILINEAR:      geo = vertices [dev] double [E][8][3]; the factors of Eq. (7)
+ *                              are rebuilt from the trilinear Jacobian (Eq. 9) with the reuse of
+ *                              Sec. 3.3 (Algorithm 2, Eq. 10-12).
+ *   geom == AX_PARALLELEPIPED: geo = h [dev] double [E][6], h = det(J) J^-1 J^-T of the
+ *                              element's constant Jacobian without weights, order
+ *                              00,01,02,11,12,22 (the input of Algorithm 3; see
+ *                              ax_parallelepiped_factors).
+ * D [host] double[N1*N1] (see ax_gll), xi and w [host] double[N1] (xi may be NULL for
+ * AX_PARALLELEPIPED).  X [dev] read, Y [dev] fully overwritten; both [nrhs][E][N1^3] of the
+ * storage type of `prec`; X and Y must not overlap.  The factors are reused across the nrhs
+ * columns (Sec. 4.1).  No NaN checks are made.  Errors: E < 0, nrhs < 1, null pointers,
+ * X == Y -> AX_ERR_ARG; N outside [1,15] or an unknown geom/prec -> AX_ERR_UNSUPPORTED.
+ */
+int ax_local(int64_t E, int N, int geom, const double* geo, const double* D, const double* xi,
+             const double* w, int nrhs, int prec, const void* X, void* Y, void* stream);
+
+/*
+ * ax_local_precomputedG - the same operator with the six factors streamed from memory, the
+ * baseline the paper improves on (Algorithm 1 and Algorithm 4 with getFactors = memory loads).
+ * G [dev] [E][6][N1^3] in order G00,G01,G02,G11,G12,G22, weights included; double for AX_FP64,
+ * float for AX_FP32 and AX_FP16_ACC32.  Other arguments as ax_local.
+ */
+int ax_local_precomputedG(int64_t E, int N, const void* G, const double* D, int nrhs, int prec,
+                          const void* X, void* Y, void* stream);
+
+/*
+ * ax_geom_factors - set-up: write the stored factors of Eq. (7) for trilinear elements,
+ * G [dev] [E][6][N1^3] (double if prec == AX_FP64, float if AX_FP32) and, if gwj is not NULL,
+ * gwj [dev] double [E][N1^3] = w_i w_j w_k det J (the lumped mass, second factor of Eq. 7).
+ * verts [dev] double [E][8][3]; xi, w [host] double[N1].  G may be NULL.
+ */
+int ax_geom_factors(int64_t E, int N, const double* verts, const double* xi, const double* w,
+                    int prec, void* G, double* gwj, void* stream);
+
+/*
+ * ax_parallelepiped_factors - set-up for Algorithm 3: h [dev] double [E][6] = det J J^-1 J^-T
+ * (order 00,01,02,11,12,22, no weights) of each element's constant Jacobian
+ * J = 1/2 [v1 - v0, v2 - v0, v4 - v0] (Eq. 9 for an affine element).  verts [dev] [E][8][3].
+ * The elements must be parallelepipeds; this is not checked.
+ */
+int ax_parallelepiped_factors(int64_t E, const double* verts, double* h, void* stream);
+
+/*
+ * ax_node_coords - physical coordinates of every GLL node, x = sum_v sigma_v(xi_i,xi_j,xi_k) v
+ * (Eq. 8).  XYZ [dev] double [E][3][N1^3].  verts [dev]; xi [host] double[N1].
+ */
+int ax_node_coords(int64_t E, int N, const double* verts, const double* xi, double* XYZ,
+                   void* stream);
+
+/*
+ * Gather-scatter (the binary matrix Q of Sec. 2.1 and the assembly A = Q^T blockdiag(A_e) Q of
+ * Eq. 1).  l2g[l] = global id of local node l (int32, 0 <= l2g[l] < n_global).
+ *
+ * gs_build_csr - [host] the inverse map of l2g in CSR form: the local ids of global node g are
+ * gidx[gptr[g] .. gptr[g+1]-1] in ascending order.  gptr int64 [n_global + 1], gidx int32
+ * [n_local].  Returns AX_ERR_ARG if some l2g entry is out of range.
+ */
+int gs_build_csr(int64_t n_local, int64_t n_global, const int32_t* l2g, int64_t* gptr,
+                 int32_t* gidx);
+
+/* Modes of gs_assemble. */
+enum {
+    GS_QT = 0,  /* out[global] = sum of in[local] over the local copies (ascending local id)   */
+    GS_Q = 1,   /* out[local]  = in[l2g[local]]                                              */
+    GS_QQT = 2  /* out[local]  = (Q Q^T in)[local]: sum over all copies of the node, then copy */
+};
+
+/*
+ * gs_assemble - apply Q^T, Q or Q Q^T to nrhs vectors.  l2g, gptr, gidx [dev] (the CSR of
+ * gs_build_csr); mask [dev] uint8 [n_global] or NULL: where mask[g] != 0 the global value is
+ * set to 0 (homogeneous Dirichlet) in GS_QT output and before the copy-out of GS_QQT.
+ * dtype AX_FP64 (double) or AX_FP32 (float).  in/out [dev] are [nrhs][n_local] or
+ * [nrhs][n_global] as the mode implies.  Sums are taken in ascending local id with no atomics,
+ * so results are deterministic.  in and out must not overlap.
+ */
+int gs_assemble(int64_t n_local, int64_t n_global, const int32_t* l2g, const int64_t* gptr,
+                const int32_t* gidx, const uint8_t* mask, int mode, int nrhs, int dtype,
+                const void* in, void* out, void* stream);
+
+/* A Poisson problem on one mesh: the assembled operator y = mask o Q^T AxLocal(Q x). */
+typedef struct {
+    int64_t E;
+    int N;
+    int geom;              /* AX_TRILINEAR or AX_PARALLELEPIPED                          */
+    const double* geo;     /* [dev] vertices [E][8][3] or h [E][6] (see ax_local)        */
+    const double* D;       /* [host] N1*N1                                               */
+    const double* xi;      /* [host] N1                                                  */
+    const double* w;       /* [host] N1                                                  */
+    int64_t n_global;
+    const int32_t* l2g;    /* [dev] [E*N1^3]                                             */
+    const int64_t* gptr;   /* [dev] [n_global + 1]                                       */
+    const int32_t* gidx;   /* [dev] [E*N1^3]                                             */
+    const uint8_t* mask;   /* [dev] [n_global] Dirichlet mask, or NULL                   */
+} ax_problem;
+
+typedef struct {
+    double rtol;           /* target ||b - A x||_2 / ||b||_2 (true residual, FP64)        */
+    int max_it;            /* iteration limit (plain CG) / inner limit per outer step     */
+    int inner_prec;        /* AX_FP64: plain FP64 CG; AX_FP32 / AX_FP16_ACC32: iterative
+                              refinement with an inner CG in that precision               */
+    double inner_rtol;     /* relative tolerance of each inner solve (refinement only)    */
+    int max_outer;         /* refinement steps limit                                      */
+    void* workspace;       /* [dev] at least cg_workspace_bytes() bytes, 256-B aligned    */
+    size_t workspace_bytes;
+} ax_cg_opts;
+
+typedef struct {
+    int status;            /* ax_status of the solve                                      */
+    int outer_it;          /* refinement steps (1 for plain CG)                           */
+    int inner_it_total;    /* CG iterations summed over all steps                          */
+    double rel_res_true;   /* ||b - A x|| / ||b|| recomputed in FP64 at exit              */
+    double seconds;        /* wall time of the solve                                      */
+} ax_cg_report;
+
+/* cg_workspace_bytes - [host] bytes of device workspace cg_solve needs. */
+int cg_workspace_bytes(const ax_problem* p, int nrhs, const ax_cg_opts* o, size_t* bytes);
+
+/*
+ * cg_solve - solve A x = b (each of nrhs columns independently) by conjugate gradients on the
+ * assembled operator; the iterative solve in which AxLocal is the dominant kernel (Sec. 1,
+ * Sec. 5.6).  b, x [dev] double [nrhs][n_global]; x holds the initial guess on entry (warm
+ * start / resume) and the solution on exit.  Entries of b under the mask must be 0.
+ * inner_prec == AX_FP64 runs plain CG in FP64.  Otherwise mixed-precision iterative refinement:
+ * the outer residual r = b - A x, its norm and the update of x are FP64; each correction
+ * A d = r / ||r|| is solved by an inner CG whose AxLocal runs in inner_prec with float vectors
+ * and FP64-accumulated dot products.  Synchronises `stream` before returning (rep is filled).
+ * Returns AX_OK, AX_ERR_NOT_CONVERGED or AX_ERR_BREAKDOWN (rep->status holds the same).
+ */
+int cg_solve(const ax_problem* p, int nrhs, const double* b, double* x, const ax_cg_opts* o,
+             ax_cg_report* rep, void* stream);
+
+/*
+ * ax_local_batched - apply AxLocal to many independent meshes (uneven E and N) with one
+ * persistent kernel launch that walks a work list of (mesh, element block) items.  meshes
+ * [host] [n_mesh] (only E, N, geom, geo, D, xi, w are read); X[m], Y[m] [dev] local vectors of
+ * mesh m, [nrhs][E_m][N1_m^3].  prec AX_FP64 or AX_FP32.  The work list is built on the host
+ * and uploaded into the caller's workspace [dev] of at least ax_batched_workspace_bytes();
+ * the launch is capturable in a HIP graph once the workspace is filled (see
+ * ax_batched_prepare).
+ */
+int ax_batched_workspace_bytes(int n_mesh, const ax_problem* meshes, size_t* bytes);
+int ax_local_batched(int n_mesh, const ax_problem* meshes, int nrhs, int prec,
+                     const void* const* X, void* const* Y, void* workspace,
+                     size_t workspace_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AXHOSFEM_H */

@@ -1,0 +1,242 @@
+"""MI355X (gfx950) matrix-free element-local Poisson operator with on-the-fly geometric factors
+(after arXiv 2504.07042).
+
+A thin ctypes binding of ``libaxhosfem.so`` (C ABI in ``include/axhosfem.h``).  PyTorch supplies
+device memory and the current HIP stream; every step of the operator runs in the library's HIP
+kernels.  Nothing here falls back to the CPU: if the library is missing, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import meshgen  # noqa: F401  (seeded synthetic inputs)
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(PKG, "libaxhosfem.so")
+
+AX_OK, AX_ERR_ARG, AX_ERR_UNSUPPORTED, AX_ERR_HIP, AX_ERR_NOMEM, AX_ERR_NOT_CONVERGED, AX_ERR_BREAKDOWN = (
+    0, -1, -2, -3, -4, -5, -6)
+AX_TRILINEAR, AX_PARALLELEPIPED = 0, 1
+AX_FP64, AX_FP32, AX_FP16_ACC32 = 0, 1, 2
+GS_QT, GS_Q, GS_QQT = 0, 1, 2
+
+_STATUS = {0: "AX_OK", -1: "AX_ERR_ARG", -2: "AX_ERR_UNSUPPORTED", -3: "AX_ERR_HIP",
+           -4: "AX_ERR_NOMEM", -5: "AX_ERR_NOT_CONVERGED", -6: "AX_ERR_BREAKDOWN"}
+
+
+class AxError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_int = ctypes.c_int
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class AxProblem(ctypes.Structure):
+    _fields_ = [("E", _i64), ("N", _int), ("geom", _int), ("geo", _vp), ("D", _vp), ("xi", _vp),
+                ("w", _vp), ("n_global", _i64), ("l2g", _vp), ("gptr", _vp), ("gidx", _vp),
+                ("mask", _vp)]
+
+
+class AxCgOpts(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("max_it", _int), ("inner_prec", _int),
+                ("inner_rtol", ctypes.c_double), ("max_outer", _int), ("workspace", _vp),
+                ("workspace_bytes", ctypes.c_size_t)]
+
+
+class AxCgReport(ctypes.Structure):
+    _fields_ = [("status", _int), ("outer_it", _int), ("inner_it_total", _int),
+                ("rel_res_true", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+
+_lib = None
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "ax_last_error": (ctypes.c_char_p, []),
+    "ax_version": (ctypes.c_char_p, []),
+    "ax_gll": (_int, [_int, _vp, _vp, _vp]),
+    "ax_local": (_int, [_i64, _int, _int, _vp, _vp, _vp, _vp, _int, _int, _vp, _vp, _vp]),
+    "ax_local_precomputedG": (_int, [_i64, _int, _vp, _vp, _int, _int, _vp, _vp, _vp]),
+    "ax_geom_factors": (_int, [_i64, _int, _vp, _vp, _vp, _int, _vp, _vp, _vp]),
+    "ax_parallelepiped_factors": (_int, [_i64, _vp, _vp, _vp]),
+    "ax_node_coords": (_int, [_i64, _int, _vp, _vp, _vp, _vp]),
+    "gs_build_csr": (_int, [_i64, _i64, _vp, _vp, _vp]),
+    "gs_assemble": (_int, [_i64, _i64, _vp, _vp, _vp, _vp, _int, _int, _int, _vp, _vp, _vp]),
+    "cg_workspace_bytes": (_int, [ctypes.POINTER(AxProblem), _int, ctypes.POINTER(AxCgOpts),
+                                  ctypes.POINTER(ctypes.c_size_t)]),
+    "cg_solve": (_int, [ctypes.POINTER(AxProblem), _int, _vp, _vp, ctypes.POINTER(AxCgOpts),
+                        ctypes.POINTER(AxCgReport), _vp]),
+    "ax_batched_workspace_bytes": (_int, [_int, ctypes.POINTER(AxProblem),
+                                          ctypes.POINTER(ctypes.c_size_t)]),
+    "ax_local_batched": (_int, [_int, ctypes.POINTER(AxProblem), _int, _int, _vp, _vp, _vp,
+                                ctypes.c_size_t, _vp]),
+}
+
+
+def lib():
+    """Load libaxhosfem.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPATH):
+            raise RuntimeError(f"{LIBPATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIBPATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(code: int):
+    if code != AX_OK:
+        raise AxError(code, lib().ax_last_error().decode())
+    return code
+
+
+def _np_ptr(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dptr(t):
+    assert t.is_cuda and t.is_contiguous(), "expected a contiguous device tensor"
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def gll(N: int):
+    """GLL points, weights and differentiation matrix from the library (Table 1)."""
+    N1 = N + 1
+    xi = np.zeros(N1)
+    w = np.zeros(N1)
+    D = np.zeros((N1, N1))
+    _check(lib().ax_gll(N, _np_ptr(xi), _np_ptr(w), _np_ptr(D)))
+    return xi, w, D
+
+
+class Basis:
+    """Host copies of the GLL tables of order N (passed to every kernel call)."""
+
+    def __init__(self, N: int):
+        self.N = N
+        self.xi, self.w, self.D = gll(N)
+        self.xi = np.ascontiguousarray(self.xi)
+        self.w = np.ascontiguousarray(self.w)
+        self.D = np.ascontiguousarray(self.D)
+
+
+def _nrhs(X, E, N):
+    NP = (N + 1) ** 3
+    if X.dim() == 3:
+        assert X.shape[1] == E and X.shape[2] == NP, "X must be [nrhs][E][N1^3]"
+        return X.shape[0]
+    assert X.numel() == E * NP, "X must be [E][N1^3] or [nrhs][E][N1^3]"
+    return 1
+
+
+def _prec_dtype(prec):
+    import torch
+    return torch.float64 if prec == AX_FP64 else torch.float32
+
+
+def ax_local(X, geo, basis: Basis, geom=AX_TRILINEAR, prec=AX_FP64, out=None, stream=None):
+    """Y = AxLocal(X) with on-the-fly factors.  X [nrhs][E][N1^3] (or [E][N1^3]) device tensor;
+    geo: vertices [E][8][3] (trilinear) or h [E][6] (parallelepiped), float64 device."""
+    import torch
+    E = geo.shape[0]
+    nrhs = _nrhs(X, E, basis.N)
+    assert X.dtype == _prec_dtype(prec) and geo.dtype == torch.float64
+    Y = torch.empty_like(X) if out is None else out
+    _check(lib().ax_local(E, basis.N, geom, _dptr(geo), _np_ptr(basis.D), _np_ptr(basis.xi),
+                          _np_ptr(basis.w), nrhs, prec, _dptr(X), _dptr(Y), _stream(stream)))
+    return Y
+
+
+def ax_local_precomputedG(X, G, basis: Basis, prec=AX_FP64, out=None, stream=None):
+    """Y = AxLocal(X) with the six factors read from G [E][6][N1^3]."""
+    import torch
+    E = G.shape[0]
+    nrhs = _nrhs(X, E, basis.N)
+    assert X.dtype == _prec_dtype(prec) and G.dtype == _prec_dtype(prec)
+    Y = torch.empty_like(X) if out is None else out
+    _check(lib().ax_local_precomputedG(E, basis.N, _dptr(G), _np_ptr(basis.D), nrhs, prec,
+                                       _dptr(X), _dptr(Y), _stream(stream)))
+    return Y
+
+
+def geom_factors(verts, basis: Basis, prec=AX_FP64, want_G=True, want_gwj=False, stream=None):
+    """Stored factors G [E][6][N1^3] (Eq. 7) and/or the lumped mass gwj [E][N1^3] (FP64)."""
+    import torch
+    E = verts.shape[0]
+    NP = (basis.N + 1) ** 3
+    G = torch.empty((E, 6, NP), dtype=_prec_dtype(prec), device=verts.device) if want_G else None
+    gwj = torch.empty((E, NP), dtype=torch.float64, device=verts.device) if want_gwj else None
+    _check(lib().ax_geom_factors(E, basis.N, _dptr(verts), _np_ptr(basis.xi), _np_ptr(basis.w), prec,
+                                 _dptr(G) if G is not None else None,
+                                 _dptr(gwj) if gwj is not None else None, _stream(stream)))
+    return G, gwj
+
+
+def parallelepiped_factors(verts, stream=None):
+    import torch
+    h = torch.empty((verts.shape[0], 6), dtype=torch.float64, device=verts.device)
+    _check(lib().ax_parallelepiped_factors(verts.shape[0], _dptr(verts), _dptr(h), _stream(stream)))
+    return h
+
+
+def node_coords(verts, basis: Basis, stream=None):
+    import torch
+    E = verts.shape[0]
+    XYZ = torch.empty((E, 3, (basis.N + 1) ** 3), dtype=torch.float64, device=verts.device)
+    _check(lib().ax_node_coords(E, basis.N, _dptr(verts), _np_ptr(basis.xi), _dptr(XYZ), _stream(stream)))
+    return XYZ
+
+
+def gs_build_csr(l2g: np.ndarray, n_global: int):
+    """Host CSR inverse of l2g (ascending local ids)."""
+    l2g = np.ascontiguousarray(l2g, dtype=np.int32)
+    gptr = np.zeros(n_global + 1, dtype=np.int64)
+    gidx = np.zeros(l2g.size, dtype=np.int32)
+    _check(lib().gs_build_csr(l2g.size, n_global, _np_ptr(l2g), _np_ptr(gptr), _np_ptr(gidx)))
+    return gptr, gidx
+
+
+class GatherScatter:
+    """Device copies of l2g, its CSR inverse and the Dirichlet mask of one mesh."""
+
+    def __init__(self, l2g: np.ndarray, n_global: int, mask=None, device="cuda"):
+        import torch
+        gptr, gidx = gs_build_csr(l2g, n_global)
+        self.n_local = int(l2g.size)
+        self.n_global = int(n_global)
+        self.l2g = torch.from_numpy(np.ascontiguousarray(l2g, dtype=np.int32)).to(device)
+        self.gptr = torch.from_numpy(gptr).to(device)
+        self.gidx = torch.from_numpy(gidx).to(device)
+        self.mask = None if mask is None else torch.from_numpy(np.ascontiguousarray(mask, dtype=np.uint8)).to(device)
+
+    def apply(self, x, mode, out=None, use_mask=True, stream=None):
+        import torch
+        dtype = AX_FP64 if x.dtype == torch.float64 else AX_FP32
+        n_in = self.n_local if mode in (GS_QT, GS_QQT) else self.n_global
+        nrhs = x.numel() // n_in
+        n_out = self.n_global if mode == GS_QT else self.n_local
+        if out is None:
+            out = torch.empty((nrhs, n_out), dtype=x.dtype, device=x.device)
+        m = self.mask if use_mask else None
+        _check(lib().gs_assemble(self.n_local, self.n_global, _dptr(self.l2g), _dptr(self.gptr),
+                                 _dptr(self.gidx), _dptr(m) if m is not None else None, mode, nrhs,
+                                 dtype, _dptr(x), _dptr(out), _stream(stream)))
+        return out

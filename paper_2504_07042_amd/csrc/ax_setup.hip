@@ -1,0 +1,155 @@
+// Set-up kernels: stored geometric factors (Eq. 7) of trilinear elements, the constant factors h
+// of parallelepipeds (input of Algorithm 3), and physical node coordinates (Eq. 8).
+#include "ax_internal.h"
+#include "geom.h"
+
+namespace ax {
+
+struct Nodes {
+    double xi[kMaxN1];
+    double w[kMaxN1];
+};
+
+// One thread per node.  Same per-column invariants as the fused kernel (geom.h).
+template <typename T>
+__global__ void __launch_bounds__(256)
+geom_factors_kernel(int64_t E, int N1, const double* __restrict__ verts, T* __restrict__ G,
+                    double* __restrict__ gwj, const Nodes nd)
+{
+    const int NP = N1 * N1 * N1;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= E * NP) return;
+    const int64_t e = idx / NP;
+    const int l = (int)(idx - e * NP);
+    const int i = l % N1, j = (l / N1) % N1, k = l / (N1 * N1);
+    double V[24];
+    for (int q = 0; q < 24; ++q) V[q] = verts[e * 24 + q];
+    TriCoef tc;
+    tri_prelude(V, nd.xi[i], nd.xi[j], nd.w[i], nd.w[j], tc);
+    double g[6], lam;
+    tri_adj<double>(tc, nd.xi[k], nd.w[k], g, lam);
+    if (G) {
+        T* ge = G + e * 6 * NP + l;
+        for (int q = 0; q < 6; ++q) ge[q * NP] = T(lam * g[q]);
+    }
+    if (gwj) gwj[idx] = nd.w[i] * nd.w[j] * nd.w[k] * tri_det(tc, nd.xi[k]) * (1.0 / 512.0);
+}
+
+// h = det J J^-1 J^-T = adj(J^T J) / det J with J = 1/2 [v1 - v0, v2 - v0, v4 - v0] (columns).
+__global__ void __launch_bounds__(256)
+parallelepiped_kernel(int64_t E, const double* __restrict__ verts, double* __restrict__ h)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    const double* V = verts + e * 24;
+    double c0[3], c1[3], c2[3];
+    for (int q = 0; q < 3; ++q) {
+        c0[q] = 0.5 * (V[3 + q] - V[q]);
+        c1[q] = 0.5 * (V[6 + q] - V[q]);
+        c2[q] = 0.5 * (V[12 + q] - V[q]);
+    }
+    const double K00 = dot3(c0, c0), K11 = dot3(c1, c1), K22 = dot3(c2, c2);
+    const double K01 = dot3(c0, c1), K02 = dot3(c0, c2), K12 = dot3(c1, c2);
+    double x12[3];
+    cross3(c1, c2, x12);
+    const double det = dot3(c0, x12);
+    const double id = 1.0 / det;
+    double* he = h + e * 6;
+    he[0] = (K11 * K22 - K12 * K12) * id;
+    he[1] = (K02 * K12 - K01 * K22) * id;
+    he[2] = (K01 * K12 - K02 * K11) * id;
+    he[3] = (K00 * K22 - K02 * K02) * id;
+    he[4] = (K01 * K02 - K00 * K12) * id;
+    he[5] = (K00 * K11 - K01 * K01) * id;
+}
+
+// x = sum_v sigma_v(xi_i, xi_j, xi_k) V_v, one thread per node, output [E][3][N1^3].
+__global__ void __launch_bounds__(256)
+node_coords_kernel(int64_t E, int N1, const double* __restrict__ verts, double* __restrict__ XYZ,
+                   const Nodes nd)
+{
+    const int NP = N1 * N1 * N1;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= E * NP) return;
+    const int64_t e = idx / NP;
+    const int l = (int)(idx - e * NP);
+    const double r = nd.xi[l % N1], s = nd.xi[(l / N1) % N1], t = nd.xi[l / (N1 * N1)];
+    const double* V = verts + e * 24;
+    const double fr[2] = {0.5 * (1.0 - r), 0.5 * (1.0 + r)};
+    const double fs[2] = {0.5 * (1.0 - s), 0.5 * (1.0 + s)};
+    const double ft[2] = {0.5 * (1.0 - t), 0.5 * (1.0 + t)};
+    for (int q = 0; q < 3; ++q) {
+        double x = 0.0;
+        for (int v = 0; v < 8; ++v) x += fr[v & 1] * fs[(v >> 1) & 1] * ft[v >> 2] * V[v * 3 + q];
+        XYZ[(e * 3 + q) * NP + l] = x;
+    }
+}
+
+static void fill_nodes(Nodes& nd, int N1, const double* xi, const double* w)
+{
+    for (int q = 0; q < kMaxN1; ++q) {
+        nd.xi[q] = (xi && q < N1) ? xi[q] : 0.0;
+        nd.w[q] = (w && q < N1) ? w[q] : 0.0;
+    }
+}
+
+static unsigned grid_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace ax
+
+using namespace ax;
+
+extern "C" int ax_geom_factors(int64_t E, int N, const double* verts, const double* xi,
+                               const double* w, int prec, void* G, double* gwj, void* stream)
+{
+    clear_error();
+    if (E < 0) return fail(AX_ERR_ARG, "E < 0");
+    if (N < 1 || N > 15) return fail(AX_ERR_UNSUPPORTED, "order N=%d outside [1,15]", N);
+    if (prec != AX_FP64 && prec != AX_FP32) return fail(AX_ERR_UNSUPPORTED, "prec must be FP64 or FP32");
+    if (!xi || !w) return fail(AX_ERR_ARG, "xi or w is NULL");
+    if (E == 0) return AX_OK;
+    if (!verts) return fail(AX_ERR_ARG, "verts is NULL");
+    if (!G && !gwj) return AX_OK;
+    const int N1 = N + 1;
+    const int64_t n = E * N1 * N1 * N1;
+    if (grid_for(n, 256) == 0 || n / 256 > 0x7fffffff) return fail(AX_ERR_UNSUPPORTED, "too many nodes");
+    Nodes nd;
+    fill_nodes(nd, N1, xi, w);
+    hipStream_t st = as_stream(stream);
+    if (prec == AX_FP64)
+        hipLaunchKernelGGL(geom_factors_kernel<double>, dim3(grid_for(n, 256)), dim3(256), 0, st, E, N1,
+                           verts, (double*)G, gwj, nd);
+    else
+        hipLaunchKernelGGL(geom_factors_kernel<float>, dim3(grid_for(n, 256)), dim3(256), 0, st, E, N1,
+                           verts, (float*)G, gwj, nd);
+    return hip_check(hipGetLastError(), "ax_geom_factors launch");
+}
+
+extern "C" int ax_parallelepiped_factors(int64_t E, const double* verts, double* h, void* stream)
+{
+    clear_error();
+    if (E < 0) return fail(AX_ERR_ARG, "E < 0");
+    if (E == 0) return AX_OK;
+    if (!verts || !h) return fail(AX_ERR_ARG, "NULL pointer");
+    hipLaunchKernelGGL(parallelepiped_kernel, dim3(grid_for(E, 256)), dim3(256), 0, as_stream(stream),
+                       E, verts, h);
+    return hip_check(hipGetLastError(), "ax_parallelepiped_factors launch");
+}
+
+extern "C" int ax_node_coords(int64_t E, int N, const double* verts, const double* xi, double* XYZ,
+                              void* stream)
+{
+    clear_error();
+    if (E < 0) return fail(AX_ERR_ARG, "E < 0");
+    if (N < 1 || N > 15) return fail(AX_ERR_UNSUPPORTED, "order N=%d outside [1,15]", N);
+    if (!xi) return fail(AX_ERR_ARG, "xi is NULL");
+    if (E == 0) return AX_OK;
+    if (!verts || !XYZ) return fail(AX_ERR_ARG, "NULL pointer");
+    const int N1 = N + 1;
+    const int64_t n = E * N1 * N1 * N1;
+    Nodes nd;
+    fill_nodes(nd, N1, xi, nullptr);
+    hipLaunchKernelGGL(node_coords_kernel, dim3(grid_for(n, 256)), dim3(256), 0, as_stream(stream), E,
+                       N1, verts, XYZ, nd);
+    return hip_check(hipGetLastError(), "ax_node_coords launch");
+}

@@ -1,0 +1,126 @@
+// Device-side geometry of trilinear and parallelepiped hexahedra (internal header).
+//
+// Trilinear map (Eq. 8): x(r,s,t) = sum_v sigma_v(r,s,t) V_v with vertex v = a + 2b + 4c at
+// reference corner (2a-1, 2b-1, 2c-1).  We work with 8J, the Jacobian of Eq. (9) without its
+// factor 1/8, exactly as Algorithm 2 does; its three columns are
+//   col0(s,t) = (A + B) + t (B - A),  A = (1-s) d00 + (1+s) d10,  B = (1-s) d01 + (1+s) d11
+//   col1(r,t) = (A' + B') + t (B' - A'), A' = (1-r) e00 + (1+r) e10, B' = (1-r) e01 + (1+r) e11
+//   col2(r,s) = (1-s)((1-r) f00 + (1+r) f10) + (1+s)((1-r) f01 + (1+r) f11)
+// with the element's edge vectors d (along r), e (along s), f (along t).  These are the common
+// terms E0, E1, F0, F1 and the k-invariant third column of Sec. 3.3 (Eq. 10-11).
+//
+// Going one step further than Algorithm 2, a GPU lane that owns the node column (i, j, :) sees
+// col0 and col1 as affine functions of t = xi_k and col2 as a constant, so every entry of
+// K = (8J)^T (8J) and det(8J) is a polynomial of degree <= 2 in t whose coefficients depend
+// on (i, j) only.  The lane forms those 17 coefficients once per element and then evaluates
+// each node's K and det(8J) with 10 fused multiply-adds instead of the 30 products and sums of
+// forming J, K and det J from scratch.  The factors then follow Eq. (12):
+//   G = w_i w_j w_k det(J) J^{-1} J^{-T} = lambda * adj(K),  lambda = 0.125 w_i w_j w_k / det(8J).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace ax {
+
+struct TriCoef {
+    double q0, q1, q2;  // K00(t) = |col0|^2
+    double p0, p1, p2;  // K11(t) = |col1|^2
+    double k22;         // K22    = |col2|^2
+    double m0, m1, m2;  // K01(t) = col0 . col1
+    double n0, n1;      // K02(t) = col0 . col2
+    double o0, o1;      // K12(t) = col1 . col2
+    double d0, d1, d2;  // det(8J)(t) = col0 . (col1 x col2)
+    double cw;          // 0.125 w_i w_j
+};
+
+__device__ __forceinline__ double dot3(const double* a, const double* b)
+{
+    return fma(a[0], b[0], fma(a[1], b[1], a[2] * b[2]));
+}
+
+__device__ __forceinline__ void cross3(const double* a, const double* b, double* c)
+{
+    c[0] = fma(a[1], b[2], -a[2] * b[1]);
+    c[1] = fma(a[2], b[0], -a[0] * b[2]);
+    c[2] = fma(a[0], b[1], -a[1] * b[0]);
+}
+
+// Columns of 8J for the node column (r, s, :): col0 = a + t b, col1 = c + t d, col2 = u.
+__device__ __forceinline__ void tri_columns(const double* V, double r, double s, double* a, double* b,
+                                            double* c, double* d, double* u)
+{
+    const double r0 = 1.0 - r, r1 = 1.0 + r, s0 = 1.0 - s, s1 = 1.0 + s;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const double d00 = V[3 + q] - V[0 + q], d10 = V[9 + q] - V[6 + q];
+        const double d01 = V[15 + q] - V[12 + q], d11 = V[21 + q] - V[18 + q];
+        const double A = s0 * d00 + s1 * d10, B = s0 * d01 + s1 * d11;
+        a[q] = A + B;
+        b[q] = B - A;
+        const double e00 = V[6 + q] - V[0 + q], e10 = V[9 + q] - V[3 + q];
+        const double e01 = V[18 + q] - V[12 + q], e11 = V[21 + q] - V[15 + q];
+        const double A2 = r0 * e00 + r1 * e10, B2 = r0 * e01 + r1 * e11;
+        c[q] = A2 + B2;
+        d[q] = B2 - A2;
+        const double f00 = V[12 + q] - V[0 + q], f10 = V[15 + q] - V[3 + q];
+        const double f01 = V[18 + q] - V[6 + q], f11 = V[21 + q] - V[9 + q];
+        u[q] = s0 * (r0 * f00 + r1 * f10) + s1 * (r0 * f01 + r1 * f11);
+    }
+}
+
+__device__ __forceinline__ void tri_prelude(const double* V, double r, double s, double wi, double wj,
+                                            TriCoef& k)
+{
+    double a[3], b[3], c[3], d[3], u[3];
+    tri_columns(V, r, s, a, b, c, d, u);
+    k.q0 = dot3(a, a);
+    k.q1 = 2.0 * dot3(a, b);
+    k.q2 = dot3(b, b);
+    k.p0 = dot3(c, c);
+    k.p1 = 2.0 * dot3(c, d);
+    k.p2 = dot3(d, d);
+    k.k22 = dot3(u, u);
+    k.m0 = dot3(a, c);
+    k.m1 = dot3(a, d) + dot3(b, c);
+    k.m2 = dot3(b, d);
+    k.n0 = dot3(a, u);
+    k.n1 = dot3(b, u);
+    k.o0 = dot3(c, u);
+    k.o1 = dot3(d, u);
+    double cu[3], du[3];
+    cross3(c, u, cu);
+    cross3(d, u, du);
+    k.d0 = dot3(a, cu);
+    k.d1 = dot3(a, du) + dot3(b, cu);
+    k.d2 = dot3(b, du);
+    k.cw = 0.125 * wi * wj;
+}
+
+// Unscaled factors at node t = xi_k: g[6] = adj(K) and lam = 0.125 w_i w_j w_k / det(8J), so
+// that the geometric factors of Eq. (7) are lam * g (Eq. 12).
+template <typename R>
+__device__ __forceinline__ void tri_adj(const TriCoef& k, R t, R wk, R* g, R& lam)
+{
+    const R K00 = fma(fma(R(k.q2), t, R(k.q1)), t, R(k.q0));
+    const R K11 = fma(fma(R(k.p2), t, R(k.p1)), t, R(k.p0));
+    const R K22 = R(k.k22);
+    const R K01 = fma(fma(R(k.m2), t, R(k.m1)), t, R(k.m0));
+    const R K02 = fma(R(k.n1), t, R(k.n0));
+    const R K12 = fma(R(k.o1), t, R(k.o0));
+    const R det = fma(fma(R(k.d2), t, R(k.d1)), t, R(k.d0));
+    lam = R(k.cw) * wk / det;
+    g[0] = fma(K11, K22, -K12 * K12);
+    g[1] = fma(K02, K12, -K01 * K22);
+    g[2] = fma(K01, K12, -K02 * K11);
+    g[3] = fma(K00, K22, -K02 * K02);
+    g[4] = fma(K01, K02, -K00 * K12);
+    g[5] = fma(K00, K11, -K01 * K01);
+}
+
+// det(8J) at node t (for the lumped mass w det J = w det(8J) / 512).
+__device__ __forceinline__ double tri_det(const TriCoef& k, double t)
+{
+    return fma(fma(k.d2, t, k.d1), t, k.d0);
+}
+
+}  // namespace ax
