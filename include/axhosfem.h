@@ -169,8 +169,9 @@ typedef struct {
                               refinement with an inner CG in that precision               */
     double inner_rtol;     /* relative tolerance of each inner solve (refinement only)    */
     int max_outer;         /* refinement steps limit                                      */
-    void* workspace;       /* [dev] at least cg_workspace_bytes() bytes, 256-B aligned    */
+    void* workspace;       /* [dev] at least cg_workspace_bytes() bytes                   */
     size_t workspace_bytes;
+    int use_graph;         /* 1: capture the CG iteration block in a HIP graph and replay it */
 } ax_cg_opts;
 
 typedef struct {
@@ -192,25 +193,59 @@ int cg_workspace_bytes(const ax_problem* p, int nrhs, const ax_cg_opts* o, size_
  * inner_prec == AX_FP64 runs plain CG in FP64.  Otherwise mixed-precision iterative refinement:
  * the outer residual r = b - A x, its norm and the update of x are FP64; each correction
  * A d = r / ||r|| is solved by an inner CG whose AxLocal runs in inner_prec with float vectors
- * and FP64-accumulated dot products.  Synchronises `stream` before returning (rep is filled).
+ * and FP64-accumulated dot products.  All scalars stay on the device; the host polls the
+ * convergence flags every 8 iterations, and with use_graph those 8 iterations are captured once
+ * in a HIP graph and replayed.  The work runs on a private stream of the calling thread after
+ * `stream` has been synchronised, and both are synchronised before returning (rep is filled).
  * Returns AX_OK, AX_ERR_NOT_CONVERGED or AX_ERR_BREAKDOWN (rep->status holds the same).
  */
 int cg_solve(const ax_problem* p, int nrhs, const double* b, double* x, const ax_cg_opts* o,
              ax_cg_report* rep, void* stream);
 
 /*
- * ax_local_batched - apply AxLocal to many independent meshes (uneven E and N) with one
- * persistent kernel launch that walks a work list of (mesh, element block) items.  meshes
- * [host] [n_mesh] (only E, N, geom, geo, D, xi, w are read); X[m], Y[m] [dev] local vectors of
- * mesh m, [nrhs][E_m][N1_m^3].  prec AX_FP64 or AX_FP32.  The work list is built on the host
- * and uploaded into the caller's workspace [dev] of at least ax_batched_workspace_bytes();
- * the launch is capturable in a HIP graph once the workspace is filled (see
- * ax_batched_prepare).
+ * Batched AxLocal over many independent trilinear meshes of uneven E and order N (1 <= N <= 9),
+ * each with nrhs columns, in ONE persistent kernel launch (the n_col / multi-column reuse of
+ * Sec. 4.1 extended to many meshes).  Only E, N, geom (must be AX_TRILINEAR), geo, D, xi, w of
+ * each ax_problem are read; D must be a GLL differentiation matrix (centro-antisymmetric).
+ *
+ * ax_batched_workspace_bytes - [host] device workspace needed for this set of meshes.
+ * ax_batched_prepare - [host, synchronous] build the work list of (mesh, element group) items
+ *   (ordered by decreasing cost) and upload it, the per-mesh pointers X[m], Y[m] ([dev] local
+ *   vectors [nrhs][E_m][N1_m^3], double for AX_FP64, float for AX_FP32; column c of mesh m
+ *   starts at X[m] + c * col_stride[m] (col_stride may be NULL: E_m * N1_m^3)) and the GLL tables into
+ *   `workspace` [dev]; fills the host `plan`.  The workspace must stay untouched while it is
+ *   in use; X/Y pointers are baked in (re-prepare to change them).
+ * ax_local_batched - enqueue the single persistent launch described by plan + workspace.  It
+ *   reads nothing from the host beyond `plan`, so it can be captured in a HIP graph and replayed.
  */
+typedef struct {
+    int64_t n_items;  /* work items (element groups) over all meshes */
+    int nrhs;
+    int prec;         /* AX_FP64 or AX_FP32 */
+    size_t bytes;     /* workspace bytes in use */
+} ax_batch_plan;
+
 int ax_batched_workspace_bytes(int n_mesh, const ax_problem* meshes, size_t* bytes);
-int ax_local_batched(int n_mesh, const ax_problem* meshes, int nrhs, int prec,
-                     const void* const* X, void* const* Y, void* workspace,
-                     size_t workspace_bytes, void* stream);
+int ax_batched_prepare(int n_mesh, const ax_problem* meshes, int nrhs, int prec, const void* const* X,
+                       void* const* Y, const int64_t* col_stride, void* workspace, size_t workspace_bytes,
+                       ax_batch_plan* plan);
+int ax_local_batched(const ax_batch_plan* plan, const void* workspace, void* stream);
+
+/*
+ * cg_solve_batched - CG (or mixed-precision refinement, inner_prec AX_FP32) on many independent
+ * trilinear meshes at once: the meshes' global numberings are concatenated by the caller into
+ * one index space of n_global nodes (l2g maps the concatenated local vectors, mesh after mesh,
+ * to it; gptr/gidx its CSR inverse; mask its Dirichlet nodes), so the union operator is block
+ * diagonal.  Each CG step applies the union operator with ONE batched persistent AxLocal launch
+ * between two gather-scatter kernels.  Each of the nrhs columns runs its own CG over the union
+ * (one alpha and beta per column).  b, x [dev] double [nrhs][n_global].  Other conventions and
+ * return values as cg_solve.
+ */
+int cg_batched_workspace_bytes(int n_mesh, const ax_problem* meshes, int64_t n_global, int nrhs,
+                               const ax_cg_opts* o, size_t* bytes);
+int cg_solve_batched(int n_mesh, const ax_problem* meshes, int64_t n_global, const int32_t* l2g,
+                     const int64_t* gptr, const int32_t* gidx, const uint8_t* mask, int nrhs,
+                     const double* b, double* x, const ax_cg_opts* o, ax_cg_report* rep, void* stream);
 
 #ifdef __cplusplus
 }

@@ -48,7 +48,11 @@ class AxProblem(ctypes.Structure):
 class AxCgOpts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("max_it", _int), ("inner_prec", _int),
                 ("inner_rtol", ctypes.c_double), ("max_outer", _int), ("workspace", _vp),
-                ("workspace_bytes", ctypes.c_size_t)]
+                ("workspace_bytes", ctypes.c_size_t), ("use_graph", _int)]
+
+
+class AxBatchPlan(ctypes.Structure):
+    _fields_ = [("n_items", _i64), ("nrhs", _int), ("prec", _int), ("bytes", ctypes.c_size_t)]
 
 
 class AxCgReport(ctypes.Structure):
@@ -76,8 +80,13 @@ _SIGS = {
                         ctypes.POINTER(AxCgReport), _vp]),
     "ax_batched_workspace_bytes": (_int, [_int, ctypes.POINTER(AxProblem),
                                           ctypes.POINTER(ctypes.c_size_t)]),
-    "ax_local_batched": (_int, [_int, ctypes.POINTER(AxProblem), _int, _int, _vp, _vp, _vp,
-                                ctypes.c_size_t, _vp]),
+    "ax_batched_prepare": (_int, [_int, ctypes.POINTER(AxProblem), _int, _int, _vp, _vp, _vp, _vp,
+                                  ctypes.c_size_t, ctypes.c_void_p]),
+    "ax_local_batched": (_int, [ctypes.c_void_p, _vp, _vp]),
+    "cg_batched_workspace_bytes": (_int, [_int, ctypes.POINTER(AxProblem), _i64, _int, ctypes.POINTER(AxCgOpts),
+                                          ctypes.POINTER(ctypes.c_size_t)]),
+    "cg_solve_batched": (_int, [_int, ctypes.POINTER(AxProblem), _i64, _vp, _vp, _vp, _vp, _int, _vp, _vp,
+                                ctypes.POINTER(AxCgOpts), ctypes.POINTER(AxCgReport), _vp]),
 }
 
 
@@ -240,3 +249,118 @@ class GatherScatter:
                                  _dptr(self.gidx), _dptr(m) if m is not None else None, mode, nrhs,
                                  dtype, _dptr(x), _dptr(out), _stream(stream)))
         return out
+
+
+class Problem:
+    """A Poisson problem on one mesh held on the device: geometry, GLL tables and the
+    gather-scatter maps (the ax_problem of the C ABI)."""
+
+    def __init__(self, geo, basis: Basis, gs: GatherScatter, geom=AX_TRILINEAR):
+        self.geo = geo
+        self.basis = basis
+        self.gs = gs
+        self.geom = geom
+        self.E = geo.shape[0]
+
+    def c_struct(self) -> AxProblem:
+        b = self.basis
+        gs = self.gs
+        return AxProblem(self.E, b.N, self.geom, self.geo.data_ptr(), b.D.ctypes.data, b.xi.ctypes.data,
+                         b.w.ctypes.data, gs.n_global, gs.l2g.data_ptr(), gs.gptr.data_ptr(),
+                         gs.gidx.data_ptr(), gs.mask.data_ptr() if gs.mask is not None else None)
+
+    def apply(self, x, prec=AX_FP64, stream=None):
+        """y = mask o Q^T AxLocal(Q x) on global vectors [nrhs][n_global]."""
+        import torch
+        xl = self.gs.apply(x, GS_Q, stream=stream)
+        xl = xl.view(xl.shape[0], self.E, -1)
+        if self.geom == AX_TRILINEAR:
+            yl = ax_local(xl, self.geo, self.basis, AX_TRILINEAR, prec, stream=stream)
+        else:
+            yl = ax_local(xl, self.geo, self.basis, AX_PARALLELEPIPED, prec, stream=stream)
+        return self.gs.apply(yl.view(yl.shape[0], -1), GS_QT, stream=stream)
+
+
+def cg_solve(prob: Problem, b, x=None, rtol=1e-10, max_it=20000, inner_prec=AX_FP64, inner_rtol=1e-6,
+             max_outer=50, use_graph=True, stream=None):
+    """Solve A x = b by CG (inner_prec = AX_FP64) or mixed-precision iterative refinement.
+    b [nrhs][n_global] float64 device.  Returns (x, report dict); raises AxError only on
+    argument or launch errors (non-convergence and breakdown are reported in the dict)."""
+    import torch
+    nrhs = b.shape[0] if b.dim() == 2 else 1
+    if x is None:
+        x = torch.zeros_like(b)
+    p = prob.c_struct()
+    opts = AxCgOpts(rtol, max_it, inner_prec, inner_rtol, max_outer, None, 0, 1 if use_graph else 0)
+    nbytes = ctypes.c_size_t()
+    _check(lib().cg_workspace_bytes(ctypes.byref(p), nrhs, ctypes.byref(opts), ctypes.byref(nbytes)))
+    ws = torch.empty(nbytes.value, dtype=torch.uint8, device=b.device)
+    opts.workspace = ws.data_ptr()
+    opts.workspace_bytes = nbytes.value
+    rep = AxCgReport()
+    code = lib().cg_solve(ctypes.byref(p), nrhs, _dptr(b), _dptr(x), ctypes.byref(opts), ctypes.byref(rep),
+                          _stream(stream))
+    if code not in (AX_OK, AX_ERR_NOT_CONVERGED, AX_ERR_BREAKDOWN):
+        _check(code)
+    return x, {"status": _STATUS.get(code, code), "outer_it": rep.outer_it, "iterations": rep.inner_it_total,
+               "rel_res_true": rep.rel_res_true, "seconds": rep.seconds}
+
+
+class BatchedAxLocal:
+    """AxLocal over many trilinear meshes (uneven E and N <= 9) in one persistent launch.
+
+    meshes: list of (verts [E][8][3] float64 device tensor, Basis); X, Y: lists of device
+    tensors [nrhs][E][N1^3] (float64 for AX_FP64, float32 for AX_FP32).  The work list and the
+    X/Y pointers are uploaded once; launch() enqueues the single kernel (graph-capturable)."""
+
+    def __init__(self, meshes, X, Y, prec=AX_FP64, device="cuda"):
+        import torch
+        n = len(meshes)
+        self._keep = (meshes, X, Y)
+        self.probs = (AxProblem * max(n, 1))()
+        for q, (verts, basis) in enumerate(meshes):
+            self.probs[q] = AxProblem(verts.shape[0], basis.N, AX_TRILINEAR, verts.data_ptr(), basis.D.ctypes.data,
+                                      basis.xi.ctypes.data, basis.w.ctypes.data, 0, None, None, None, None)
+        nrhs = X[0].shape[0] if n else 1
+        nbytes = ctypes.c_size_t()
+        _check(lib().ax_batched_workspace_bytes(n, self.probs, ctypes.byref(nbytes)))
+        self.ws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=device)
+        xs = (ctypes.c_void_p * max(n, 1))(*[x.data_ptr() for x in X])
+        ys = (ctypes.c_void_p * max(n, 1))(*[y.data_ptr() for y in Y])
+        self.plan = AxBatchPlan()
+        _check(lib().ax_batched_prepare(n, self.probs, nrhs, prec, ctypes.cast(xs, ctypes.c_void_p),
+                                        ctypes.cast(ys, ctypes.c_void_p), None, _dptr(self.ws), nbytes.value,
+                                        ctypes.byref(self.plan)))
+
+    def launch(self, stream=None):
+        _check(lib().ax_local_batched(ctypes.byref(self.plan), _dptr(self.ws), _stream(stream)))
+
+
+def cg_solve_batched(meshes, gs: GatherScatter, b, x=None, rtol=1e-10, max_it=20000, inner_prec=AX_FP64,
+                     inner_rtol=1e-6, max_outer=50, use_graph=True, stream=None):
+    """CG / mixed refinement over the union of many trilinear meshes (block-diagonal system).
+    meshes: list of (verts device tensor, Basis) in the order of the concatenated local vectors;
+    gs: gather-scatter of the concatenated numbering; b [nrhs][n_global] float64 device."""
+    import torch
+    n = len(meshes)
+    probs = (AxProblem * n)()
+    for q, (verts, basis) in enumerate(meshes):
+        probs[q] = AxProblem(verts.shape[0], basis.N, AX_TRILINEAR, verts.data_ptr(), basis.D.ctypes.data,
+                             basis.xi.ctypes.data, basis.w.ctypes.data, 0, None, None, None, None)
+    nrhs = b.shape[0] if b.dim() == 2 else 1
+    if x is None:
+        x = torch.zeros_like(b)
+    opts = AxCgOpts(rtol, max_it, inner_prec, inner_rtol, max_outer, None, 0, 1 if use_graph else 0)
+    nbytes = ctypes.c_size_t()
+    _check(lib().cg_batched_workspace_bytes(n, probs, gs.n_global, nrhs, ctypes.byref(opts), ctypes.byref(nbytes)))
+    ws = torch.empty(nbytes.value, dtype=torch.uint8, device=b.device)
+    opts.workspace = ws.data_ptr()
+    opts.workspace_bytes = nbytes.value
+    rep = AxCgReport()
+    code = lib().cg_solve_batched(n, probs, gs.n_global, _dptr(gs.l2g), _dptr(gs.gptr), _dptr(gs.gidx),
+                                  _dptr(gs.mask) if gs.mask is not None else None, nrhs, _dptr(b), _dptr(x),
+                                  ctypes.byref(opts), ctypes.byref(rep), _stream(stream))
+    if code not in (AX_OK, AX_ERR_NOT_CONVERGED, AX_ERR_BREAKDOWN):
+        _check(code)
+    return x, {"status": _STATUS.get(code, code), "outer_it": rep.outer_it, "iterations": rep.inner_it_total,
+               "rel_res_true": rep.rel_res_true, "seconds": rep.seconds}

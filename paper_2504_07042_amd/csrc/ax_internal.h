@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdarg>
+#include <cmath>
 #include <cstdint>
 #include <cstdio>
 #include <string>
@@ -47,6 +48,13 @@ inline int hip_check(hipError_t e, const char* what)
 template <typename T>
 struct Basis {
     T D[kMaxN1 * kMaxN1];  // D[a * N1 + n]
+    // Even-odd split of a centro-antisymmetric D (D[N-a][N-n] = -D[a][n]), H = N1 / 2:
+    //   P[a][n] = (D[a][n] + D[a][N-n]) / 2,  M[a][n] = (D[a][n] - D[a][N-n]) / 2  (a, n < H)
+    //   Cm[a] = D[a][H], Rm[n] = D[H][n]  (middle column / row, odd N1 only)
+    T P[(kMaxN1 / 2) * (kMaxN1 / 2)];
+    T M[(kMaxN1 / 2) * (kMaxN1 / 2)];
+    T Cm[kMaxN1 / 2];
+    T Rm[kMaxN1 / 2];
     double xi[kMaxN1];
     double w[kMaxN1];
 };
@@ -64,6 +72,33 @@ inline void fill_basis(Basis<T>& b, int N1, const double* D, const double* xi, c
         if (xi) b.xi[q] = xi[q];
         if (w) b.w[q] = w[q];
     }
+    const int H = N1 / 2, N = N1 - 1;
+    for (int q = 0; q < (kMaxN1 / 2) * (kMaxN1 / 2); ++q) b.P[q] = b.M[q] = T(0);
+    for (int q = 0; q < kMaxN1 / 2; ++q) b.Cm[q] = b.Rm[q] = T(0);
+    for (int a = 0; a < H; ++a)
+        for (int n = 0; n < H; ++n) {
+            b.P[a * H + n] = T(0.5 * (D[a * N1 + n] + D[a * N1 + (N - n)]));
+            b.M[a * H + n] = T(0.5 * (D[a * N1 + n] - D[a * N1 + (N - n)]));
+        }
+    if (N1 % 2)
+        for (int a = 0; a < H; ++a) {
+            b.Cm[a] = T(D[a * N1 + H]);
+            b.Rm[a] = T(D[H * N1 + a]);
+        }
+}
+
+// True if D is centro-antisymmetric (D[N-a][N-n] = -D[a][n]) to within rounding, which every
+// GLL differentiation matrix is; the kernels then use the even-odd split above.
+inline bool centro_antisymmetric(int N1, const double* D)
+{
+    double mx = 0.0, dev = 0.0;
+    for (int q = 0; q < N1 * N1; ++q) mx = mx > fabs(D[q]) ? mx : fabs(D[q]);
+    for (int a = 0; a < N1; ++a)
+        for (int n = 0; n < N1; ++n) {
+            const double d = fabs(D[a * N1 + n] + D[(N1 - 1 - a) * N1 + (N1 - 1 - n)]);
+            dev = dev > d ? dev : d;
+        }
+    return dev <= 1e-13 * mx;
 }
 
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }

@@ -1,0 +1,94 @@
+// Element-level building blocks shared by the AxLocal kernels (internal header): work-group
+// shapes per order and the one-dimensional D-contractions.
+#pragma once
+
+#include "ax_internal.h"
+
+namespace ax {
+
+enum { GEO_TRI = 0, GEO_PARA = 1, GEO_STORED = 2 };
+
+// Tuning knobs (compile-time): waves per SIMD the register allocation targets for N1 <= 8, and
+// how many times the resident capacity the persistent grid is.
+#ifndef AX_MINW_SMALL
+#define AX_MINW_SMALL 4
+#endif
+#ifndef AX_PERSIST_MULT
+#define AX_PERSIST_MULT 2
+#endif
+
+template <int N1>
+struct Shape {
+    static constexpr int NT = N1 * N1;                        // lanes per element
+    static constexpr int SJ = (N1 % 2 == 0) ? N1 + 1 : N1;    // LDS row stride (odd)
+    static constexpr int SK = N1 * SJ;                        // LDS slice stride
+    static constexpr int FS = N1 * SK;                        // LDS words per field
+    static constexpr int NP = N1 * N1 * N1;                   // nodes per element
+    // elements per work-group: fill (nearly) whole waves while keeping LDS modest
+    static constexpr int EPB = N1 == 2 ? 16 : N1 == 3 ? 7 : N1 == 4 ? 4 : N1 == 5 ? 5
+                             : N1 == 6 ? 7 : N1 == 7 ? 5 : N1 == 9 ? 3 : N1 == 10 ? 3
+                             : N1 == 11 ? 2 : 1;
+    static constexpr int BLOCK = ((EPB * NT + 63) / 64) * 64;
+    static constexpr int SLOTS = (BLOCK + NT - 1) / NT;
+    // waves per SIMD the register allocation must allow (latency hiding for the X/Y streams)
+    static constexpr int MINW = N1 <= 8 ? AX_MINW_SMALL : 2;
+};
+
+// out[a] = sum_n D[a][n] in[n]   (TRANS: out[a] = sum_n D[n][a] in[n])
+template <int N1, bool TRANS, typename T>
+__device__ __forceinline__ void contract_full(const Basis<T>& bs, const T* in, T* out)
+{
+#pragma unroll
+    for (int a = 0; a < N1; ++a) {
+        T acc = T(0);
+#pragma unroll
+        for (int n = 0; n < N1; ++n) acc = fma(TRANS ? bs.D[n * N1 + a] : bs.D[a * N1 + n], in[n], acc);
+        out[a] = acc;
+    }
+}
+
+// The same contraction for a centro-antisymmetric D by its even-odd split (H = N1/2 squared
+// blocks P and M, see Basis): with ue[n] = in[n] + in[N-n], uo[n] = in[n] - in[N-n],
+//   e[a] = sum_n P[a][n] ue[n],  o[a] = sum_n M[a][n] uo[n],  out[a] = e + o,  out[N-a] = o - e.
+// D^T is centro-antisymmetric too, with blocks M^T and P^T.  2 H^2 FMAs instead of N1^2, and
+// half as many distinct coefficients (they stay in scalar registers).
+template <int N1, bool TRANS, typename T>
+__device__ __forceinline__ void contract_eo(const Basis<T>& bs, const T* in, T* out)
+{
+    constexpr int H = N1 / 2, N = N1 - 1;
+    T ue[H], uo[H];
+#pragma unroll
+    for (int n = 0; n < H; ++n) {
+        ue[n] = in[n] + in[N - n];
+        uo[n] = in[n] - in[N - n];
+    }
+#pragma unroll
+    for (int a = 0; a < H; ++a) {
+        T e = T(0), o = T(0);
+#pragma unroll
+        for (int n = 0; n < H; ++n) {
+            e = fma(TRANS ? bs.M[n * H + a] : bs.P[a * H + n], ue[n], e);
+            o = fma(TRANS ? bs.P[n * H + a] : bs.M[a * H + n], uo[n], o);
+        }
+        if constexpr (N1 % 2 == 1) e = fma(TRANS ? bs.Rm[a] : bs.Cm[a], in[H], e);
+        out[a] = e + o;
+        out[N - a] = o - e;
+    }
+    if constexpr (N1 % 2 == 1) {
+        T m = T(0);
+#pragma unroll
+        for (int n = 0; n < H; ++n) m = fma(TRANS ? bs.Cm[n] : bs.Rm[n], uo[n], m);
+        out[H] = m;
+    }
+}
+
+template <int N1, bool TRANS, bool EO, typename T>
+__device__ __forceinline__ void contract(const Basis<T>& bs, const T* in, T* out)
+{
+    if constexpr (EO)
+        contract_eo<N1, TRANS>(bs, in, out);
+    else
+        contract_full<N1, TRANS>(bs, in, out);
+}
+
+}  // namespace ax

@@ -17,106 +17,147 @@
 //   * The FP64 matrix cores of gfx950 run at the same rate as FP64 FMA on the vector unit and do
 //     not overlap with it, so the FP64 contractions stay on the vector unit.
 #include "ax_internal.h"
+#include "ax_kernels.h"
 #include "geom.h"
 
 namespace ax {
 
-enum { GEO_TRI = 0, GEO_PARA = 1, GEO_STORED = 2 };
-
-template <int N1>
-struct Shape {
-    static constexpr int NT = N1 * N1;                        // lanes per element
-    static constexpr int SJ = (N1 % 2 == 0) ? N1 + 1 : N1;    // LDS row stride (odd)
-    static constexpr int SK = N1 * SJ;                        // LDS slice stride
-    static constexpr int FS = N1 * SK;                        // LDS words per field
-    static constexpr int NP = N1 * N1 * N1;                   // nodes per element
-    // elements per work-group: fill (nearly) whole waves while keeping LDS modest
-    static constexpr int EPB = N1 == 2 ? 16 : N1 == 3 ? 7 : N1 == 4 ? 4 : N1 == 5 ? 5
-                             : N1 == 6 ? 7 : N1 == 7 ? 5 : N1 == 9 ? 3 : N1 == 10 ? 3
-                             : N1 == 11 ? 2 : 1;
-    static constexpr int BLOCK = ((EPB * NT + 63) / 64) * 64;
-    static constexpr int SLOTS = (BLOCK + NT - 1) / NT;
-};
-
-// out[a] = sum_n D[a][n] in[n]   (TRANS: out[a] = sum_n D[n][a] in[n])
-template <int N1, bool TRANS, typename T>
-__device__ __forceinline__ void contract(const T* __restrict__ D, const T* in, T* out)
-{
-#pragma unroll
-    for (int a = 0; a < N1; ++a) {
-        T acc = T(0);
-#pragma unroll
-        for (int n = 0; n < N1; ++n) acc = fma(TRANS ? D[n * N1 + a] : D[a * N1 + n], in[n], acc);
-        out[a] = acc;
-    }
-}
-
-template <int N1, int GEO, typename T>
-__global__ void __launch_bounds__(Shape<N1>::BLOCK)
+template <int N1, int GEO, bool EO, typename T>
+__global__ void __launch_bounds__(Shape<N1>::BLOCK, Shape<N1>::MINW)
 ax_local_kernel(int64_t E, int nrhs, const double* __restrict__ geo, const T* __restrict__ Gs,
                 const T* __restrict__ X, T* __restrict__ Y, const Basis<T> bs)
 {
     using S = Shape<N1>;
     constexpr int NT = S::NT, SJ = S::SJ, SK = S::SK, FS = S::FS, NP = S::NP, EPB = S::EPB;
-    __shared__ T smem[S::SLOTS * 3 * FS];
+    constexpr int BLOCK = S::BLOCK;
+    constexpr int NV = (GEO == GEO_TRI) ? 24 : 0;                // vertex words per element
+    constexpr int VPT = (EPB * NV + BLOCK - 1) / BLOCK;          // vertex words per thread
+    __shared__ T smem[S::SLOTS * 2 * FS];
+    __shared__ double svert[(GEO == GEO_TRI) ? EPB * 24 : 1];
 
     const int tid = threadIdx.x;
     const int slot = (S::SLOTS == 1) ? 0 : tid / NT;
     const int lane = tid - slot * NT;
-    const int64_t e0 = (int64_t)blockIdx.x * EPB;          // uniform across the work-group
-    const int64_t e = (EPB == 1) ? e0 : e0 + slot;
-    const bool active = (slot < EPB) && (e < E);
-    T* __restrict__ A = smem + slot * 3 * FS;
+    T* __restrict__ A = smem + slot * 2 * FS;
     T* __restrict__ B = A + FS;
-    T* __restrict__ C = B + FS;
+    const int i = lane % N1, j = lane / N1;    // home lane: node column (i, j, :)
+    const int pa = lane % N1, pb = lane / N1;  // pencil lane: (j,k) for r, (i,k) for s
+    const int64_t nblk = (E + EPB - 1) / EPB;
 
-    const int i = lane % N1, j = lane / N1;   // home lane: node column (i, j, :)
-    const int pa = lane % N1, pb = lane / N1; // pencil lane: (j,k) for r, (i,k) for s
-
-    // per-element geometry invariants of the home column
-    TriCoef tc;
-    double h[6];
-    if constexpr (GEO == GEO_TRI) {
-        double V[24];
-        const double* Ve = geo + (active ? e : 0) * 24;
+    // Items are (element group, column) pairs walked in order; each work-group strides over the
+    // element groups.  The next item's X (and vertices) are fetched into registers while the
+    // current one is computed, so HBM latency overlaps with the contraction work.
+    int64_t eb = blockIdx.x;
+    int c = 0;
+    auto x_base = [&](int64_t ebq, int cq, bool& act) -> int64_t {
+        const int64_t eq = ebq * EPB + slot;
+        act = (ebq < nblk) && (slot < EPB) && (eq < E);
+        return ((int64_t)cq * E + (act ? eq : 0)) * NP;
+    };
+    T xr[N1];
+    double vr[VPT > 0 ? VPT : 1];
+    {
+        bool act;
+        const int64_t b0 = x_base(eb, c, act);
 #pragma unroll
-        for (int q = 0; q < 24; ++q) V[q] = Ve[q];
-        tri_prelude(V, bs.xi[i], bs.xi[j], bs.w[i], bs.w[j], tc);
-    } else if constexpr (GEO == GEO_PARA) {
-        const double* he = geo + (active ? e : 0) * 6;
-        const double wij = bs.w[i] * bs.w[j];
+        for (int k = 0; k < N1; ++k) xr[k] = act ? X[b0 + i + j * N1 + k * NT] : T(0);
+        if constexpr (GEO == GEO_TRI) {
 #pragma unroll
-        for (int q = 0; q < 6; ++q) h[q] = he[q] * wij;
+            for (int q = 0; q < VPT; ++q) {
+                const int idx = tid + q * BLOCK;
+                const int64_t off = eb * EPB * 24 + idx;
+                vr[q] = (idx < EPB * 24 && eb < nblk && off < E * 24) ? geo[off] : 0.0;
+            }
+        }
     }
 
-    for (int c = 0; c < nrhs; ++c) {
-        const int64_t base = ((int64_t)c * E + (active ? e : 0)) * NP;
-        T xr[N1], x2[N1];
+    TriCoef tc;
+    double h[6];
+    while (eb < nblk) {
+        bool active;
+        const int64_t base = x_base(eb, c, active);
+        const int64_t e = eb * EPB + slot;
+        if constexpr (GEO == GEO_PARA) {
+            if (c == 0) {
+                const double* he = geo + (active ? e : 0) * 6;
+                const double wij = bs.w[i] * bs.w[j];
 #pragma unroll
-        for (int k = 0; k < N1; ++k) xr[k] = active ? X[base + i + j * N1 + k * NT] : T(0);
+                for (int q = 0; q < 6; ++q) h[q] = he[q] * wij;
+            }
+        }
+        // P0: stage X (and the vertices), prefetch the next item, t-contraction in registers
 #pragma unroll
         for (int k = 0; k < N1; ++k) A[k * SK + j * SJ + i] = xr[k];
-        contract<N1, false>(bs.D, xr, x2);  // x2 = D_t x (home column)
+        if constexpr (GEO == GEO_TRI) {
+            if (c == 0) {
+#pragma unroll
+                for (int q = 0; q < VPT; ++q) {
+                    const int idx = tid + q * BLOCK;
+                    if (idx < EPB * 24) svert[idx] = vr[q];
+                }
+            }
+        }
+        const bool last_col = (c + 1 == nrhs);
+        const int64_t eb_n = last_col ? eb + gridDim.x : eb;
+        const int c_n = last_col ? 0 : c + 1;
+        T xn[N1];
+        {
+            bool act_n;
+            const int64_t bn = x_base(eb_n, c_n, act_n);
+            // inactive lanes re-read a valid line of the current element and discard it, which
+            // keeps the loads free of per-load branches
+            const T* src = X + (act_n ? bn : base) + i + j * N1;
+#pragma unroll
+            for (int k = 0; k < N1; ++k) xn[k] = src[k * NT];
+            if (!act_n) {
+#pragma unroll
+                for (int k = 0; k < N1; ++k) xn[k] = T(0);
+            }
+            if constexpr (GEO == GEO_TRI) {
+                if (last_col) {
+#pragma unroll
+                    for (int q = 0; q < VPT; ++q) {
+                        const int idx = tid + q * BLOCK;
+                        const int64_t off = eb_n * EPB * 24 + idx;
+                        vr[q] = (idx < EPB * 24 && eb_n < nblk && off < E * 24) ? geo[off] : 0.0;
+                    }
+                }
+            }
+        }
+        T x2[N1];
+        contract<N1, false, EO>(bs, xr, x2);  // x2 = D_t x
         __syncthreads();
+        // P1: r-pencils (j,k) -> x0 in B; s-pencils (i,k) -> x1 held in registers
+        T o1[N1];
         {
             T p[N1], o[N1];
 #pragma unroll
             for (int n = 0; n < N1; ++n) p[n] = A[pb * SK + pa * SJ + n];
-            contract<N1, false>(bs.D, p, o);  // x0 = D_r x along i, pencil (j,k) = (pa,pb)
+            contract<N1, false, EO>(bs, p, o);
 #pragma unroll
             for (int a = 0; a < N1; ++a) B[pb * SK + pa * SJ + a] = o[a];
 #pragma unroll
             for (int n = 0; n < N1; ++n) p[n] = A[pb * SK + n * SJ + pa];
-            contract<N1, false>(bs.D, p, o);  // x1 = D_s x along j, pencil (i,k) = (pa,pb)
-#pragma unroll
-            for (int a = 0; a < N1; ++a) C[pb * SK + a * SJ + pa] = o[a];
+            contract<N1, false, EO>(bs, p, o1);
         }
         __syncthreads();
+        // P2: x1 -> A; per-element geometry invariants of the home column from the staged vertices
+#pragma unroll
+        for (int a = 0; a < N1; ++a) A[pb * SK + a * SJ + pa] = o1[a];
+        if constexpr (GEO == GEO_TRI) {
+            if (c == 0) {
+                const double* sv = svert + (slot < EPB ? slot : 0) * 24;
+                tri_prelude([&](int v, int q) { return sv[v * 3 + q]; }, bs.xi[i], bs.xi[j], bs.w[i],
+                            bs.w[j], tc);
+            }
+        }
+        __syncthreads();
+        // P3: pointwise factors at the home column; r -> B, s -> A, t stays in registers
         T tt[N1];
 #pragma unroll
         for (int k = 0; k < N1; ++k) {
             const int l = k * SK + j * SJ + i;
-            T x0 = B[l], x1 = C[l], xx2 = x2[k];
+            T x0 = B[l], x1 = A[l], xx2 = x2[k];
             T g[6];
             if constexpr (GEO == GEO_TRI) {
                 T lam;
@@ -134,35 +175,55 @@ ax_local_kernel(int64_t E, int nrhs, const double* __restrict__ geo, const T* __
                 for (int q = 0; q < 6; ++q) g[q] = active ? ge[q * NP] : T(0);
             }
             B[l] = fma(g[0], x0, fma(g[1], x1, g[2] * xx2));
-            C[l] = fma(g[1], x0, fma(g[3], x1, g[4] * xx2));
+            A[l] = fma(g[1], x0, fma(g[3], x1, g[4] * xx2));
             tt[k] = fma(g[2], x0, fma(g[4], x1, g[5] * xx2));
         }
         T y2[N1];
-        contract<N1, true>(bs.D, tt, y2);  // D_t^T t (home column)
+        contract<N1, true, EO>(bs, tt, y2);  // D_t^T t
         __syncthreads();
+        // P4: D_r^T r in place on the r-pencils; D_s^T s into registers
         {
             T p[N1], o[N1];
 #pragma unroll
             for (int n = 0; n < N1; ++n) p[n] = B[pb * SK + pa * SJ + n];
-            contract<N1, true>(bs.D, p, o);  // D_r^T r along i
+            contract<N1, true, EO>(bs, p, o);
 #pragma unroll
-            for (int a = 0; a < N1; ++a) A[pb * SK + pa * SJ + a] = o[a];
+            for (int a = 0; a < N1; ++a) B[pb * SK + pa * SJ + a] = o[a];
+#pragma unroll
+            for (int n = 0; n < N1; ++n) p[n] = A[pb * SK + n * SJ + pa];
+            contract<N1, true, EO>(bs, p, o1);
         }
         __syncthreads();
-        {
-            T p[N1], o[N1];
+        // P5: add D_s^T s on the s-pencils
 #pragma unroll
-            for (int n = 0; n < N1; ++n) p[n] = C[pb * SK + n * SJ + pa];
-            contract<N1, true>(bs.D, p, o);  // D_s^T s along j
-#pragma unroll
-            for (int a = 0; a < N1; ++a) A[pb * SK + a * SJ + pa] += o[a];
-        }
+        for (int a = 0; a < N1; ++a) B[pb * SK + a * SJ + pa] += o1[a];
         __syncthreads();
+        // P6: Y = (D_r^T r + D_s^T s) + D_t^T t
         if (active) {
 #pragma unroll
-            for (int k = 0; k < N1; ++k) Y[base + i + j * N1 + k * NT] = A[k * SK + j * SJ + i] + y2[k];
+            for (int k = 0; k < N1; ++k) Y[base + i + j * N1 + k * NT] = B[k * SK + j * SJ + i] + y2[k];
         }
+#pragma unroll
+        for (int k = 0; k < N1; ++k) xr[k] = xn[k];
+        eb = eb_n;
+        c = c_n;
     }
+}
+
+template <int N1, int GEO, typename T>
+static int64_t persistent_groups()
+{
+    static int64_t g = 0;
+    if (g == 0) {
+        int dev = 0, cus = 256, per = 0;
+        hipGetDevice(&dev);
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, ax_local_kernel<N1, GEO, true, T>,
+                                                         Shape<N1>::BLOCK, 0) != hipSuccess || per < 1)
+            per = 1;
+        g = (int64_t)cus * per * AX_PERSIST_MULT;
+    }
+    return g;
 }
 
 template <int N1, int GEO, typename T>
@@ -172,10 +233,16 @@ static int launch_n1(int64_t E, int nrhs, const double* geo, const T* Gs, const 
     using S = Shape<N1>;
     Basis<T> bs;
     fill_basis(bs, N1, D, xi, w);
-    const int64_t blocks = (E + S::EPB - 1) / S::EPB;
-    if (blocks > 0x7fffffff) return fail(AX_ERR_UNSUPPORTED, "too many elements for one launch");
-    hipLaunchKernelGGL((ax_local_kernel<N1, GEO, T>), dim3((unsigned)blocks), dim3(S::BLOCK), 0, st,
-                       E, nrhs, geo, Gs, X, Y, bs);
+    const int64_t nblk = (E + S::EPB - 1) / S::EPB;
+    // persistent work-groups: enough to fill every CU several times over, never more than the
+    // number of element groups
+    const int64_t blocks = nblk < persistent_groups<N1, GEO, T>() ? nblk : persistent_groups<N1, GEO, T>();
+    if (centro_antisymmetric(N1, D))
+        hipLaunchKernelGGL((ax_local_kernel<N1, GEO, true, T>), dim3((unsigned)blocks), dim3(S::BLOCK), 0,
+                           st, E, nrhs, geo, Gs, X, Y, bs);
+    else
+        hipLaunchKernelGGL((ax_local_kernel<N1, GEO, false, T>), dim3((unsigned)blocks), dim3(S::BLOCK), 0,
+                           st, E, nrhs, geo, Gs, X, Y, bs);
     return hip_check(hipGetLastError(), "ax_local launch");
 }
 

@@ -22,10 +22,9 @@ geom_factors_kernel(int64_t E, int N1, const double* __restrict__ verts, T* __re
     const int64_t e = idx / NP;
     const int l = (int)(idx - e * NP);
     const int i = l % N1, j = (l / N1) % N1, k = l / (N1 * N1);
-    double V[24];
-    for (int q = 0; q < 24; ++q) V[q] = verts[e * 24 + q];
+    const double* Ve = verts + e * 24;
     TriCoef tc;
-    tri_prelude(V, nd.xi[i], nd.xi[j], nd.w[i], nd.w[j], tc);
+    tri_prelude([&](int v, int q) { return Ve[v * 3 + q]; }, nd.xi[i], nd.xi[j], nd.w[i], nd.w[j], tc);
     double g[6], lam;
     tri_adj<double>(tc, nd.xi[k], nd.w[k], g, lam);
     if (G) {

@@ -1,16 +1,366 @@
-// Batched persistent AxLocal over many meshes (placeholder; implemented in a later step).
-#include "ax_internal.h"
+// Batched AxLocal: many independent trilinear meshes of uneven size and order (each with nrhs
+// columns) in ONE persistent kernel launch that walks a work list of (mesh, element group)
+// items.  The list is built on the host, ordered by decreasing cost and dealt round-robin to
+// the resident work-groups (longest-processing-time first), so uneven meshes balance without
+// atomics; the launch reads everything from the caller's workspace and is therefore capturable
+// in a HIP graph and replayable.
+//
+// Per item the work is the trilinear on-the-fly operator of ax_local (geometric factors of
+// Sec. 3.3 / Algorithm 2, contractions of Algorithm 1), with a 256-thread work-group shape that
+// is the same for every order so that one kernel serves all of them (orders N = 1..9).
+#include <algorithm>
+#include <cstring>
+#include <vector>
 
-extern "C" int ax_batched_workspace_bytes(int, const ax_problem*, size_t* bytes)
+#include "ax_internal.h"
+#include "ax_kernels.h"
+#include "geom.h"
+
+namespace ax {
+
+constexpr int kBBlock = 256;
+constexpr int kBMaxN1 = 10;
+
+template <int N1>
+struct BShape {
+    static constexpr int NT = N1 * N1;
+    static constexpr int EPB = kBBlock / NT > 64 ? 64 : kBBlock / NT;
+    static constexpr int SJ = Shape<N1>::SJ, SK = Shape<N1>::SK, FS = Shape<N1>::FS, NP = Shape<N1>::NP;
+    template <typename T>
+    static constexpr size_t lds_bytes() { return (size_t)EPB * 2 * FS * sizeof(T) + (size_t)EPB * 24 * 8; }
+};
+
+template <typename T>
+constexpr size_t bmax_lds()
 {
-    ax::clear_error();
-    if (bytes) *bytes = 0;
-    return ax::fail(AX_ERR_UNSUPPORTED, "batched AxLocal not available yet");
+    size_t m = 0;
+    m = std::max(m, BShape<2>::lds_bytes<T>());
+    m = std::max(m, BShape<3>::lds_bytes<T>());
+    m = std::max(m, BShape<4>::lds_bytes<T>());
+    m = std::max(m, BShape<5>::lds_bytes<T>());
+    m = std::max(m, BShape<6>::lds_bytes<T>());
+    m = std::max(m, BShape<7>::lds_bytes<T>());
+    m = std::max(m, BShape<8>::lds_bytes<T>());
+    m = std::max(m, BShape<9>::lds_bytes<T>());
+    m = std::max(m, BShape<10>::lds_bytes<T>());
+    return m;
 }
 
-extern "C" int ax_local_batched(int, const ax_problem*, int, int, const void* const*, void* const*,
-                                void*, size_t, void*)
+struct BMesh {
+    int64_t E;
+    int64_t ld;  // stride between columns of X and Y (elements)
+    const double* verts;
+    const void* X;
+    void* Y;
+    int N1;
+    int pad;
+};
+
+struct BItem {
+    int mesh;
+    int eb;  // element group within the mesh
+};
+
+struct BHeader {
+    int n_mesh, n_items, nrhs, prec;
+    int64_t off_mesh, off_items, off_basis;
+    int64_t bytes;
+    int ready;
+    int pad;
+};
+
+template <int N1, typename T>
+__device__ void batched_item(const BMesh& m, int64_t eb, int nrhs, const Basis<T>& bs, char* lds)
 {
-    ax::clear_error();
-    return ax::fail(AX_ERR_UNSUPPORTED, "batched AxLocal not available yet");
+    using S = BShape<N1>;
+    constexpr int NT = S::NT, EPB = S::EPB, SJ = S::SJ, SK = S::SK, FS = S::FS, NP = S::NP;
+    T* smem = reinterpret_cast<T*>(lds);
+    double* svert = reinterpret_cast<double*>(lds + (size_t)EPB * 2 * FS * sizeof(T));
+    const int tid = threadIdx.x;
+    const int slot = tid / NT;
+    const int lane = tid - slot * NT;
+    const bool inslot = slot < EPB;
+    const int64_t e = eb * EPB + slot;
+    const bool active = inslot && e < m.E;
+    T* A = smem + (inslot ? slot : 0) * 2 * FS;
+    T* B = A + FS;
+    const int i = lane % N1, j = lane / N1;
+    const int pa = i, pb = j;
+    const T* X = reinterpret_cast<const T*>(m.X);
+    T* Y = reinterpret_cast<T*>(m.Y);
+
+    for (int q = tid; q < EPB * 24; q += kBBlock) {
+        const int64_t off = eb * EPB * 24 + q;
+        svert[q] = off < m.E * 24 ? m.verts[off] : 0.0;
+    }
+    __syncthreads();
+    TriCoef tc;
+    if (inslot) {
+        const double* sv = svert + slot * 24;
+        tri_prelude([&](int v, int q) { return sv[v * 3 + q]; }, bs.xi[i], bs.xi[j], bs.w[i], bs.w[j], tc);
+    }
+    for (int c = 0; c < nrhs; ++c) {
+        const int64_t base = (int64_t)c * m.ld + (active ? e : 0) * NP;
+        T xr[N1], x2[N1];
+#pragma unroll
+        for (int k = 0; k < N1; ++k) xr[k] = active ? X[base + i + j * N1 + k * NT] : T(0);
+        if (inslot) {
+#pragma unroll
+            for (int k = 0; k < N1; ++k) A[k * SK + j * SJ + i] = xr[k];
+        }
+        contract<N1, false, true>(bs, xr, x2);
+        __syncthreads();
+        T o1[N1];
+        if (inslot) {
+            T p[N1], o[N1];
+#pragma unroll
+            for (int n = 0; n < N1; ++n) p[n] = A[pb * SK + pa * SJ + n];
+            contract<N1, false, true>(bs, p, o);
+#pragma unroll
+            for (int a = 0; a < N1; ++a) B[pb * SK + pa * SJ + a] = o[a];
+#pragma unroll
+            for (int n = 0; n < N1; ++n) p[n] = A[pb * SK + n * SJ + pa];
+            contract<N1, false, true>(bs, p, o1);
+        }
+        __syncthreads();
+        if (inslot) {
+#pragma unroll
+            for (int a = 0; a < N1; ++a) A[pb * SK + a * SJ + pa] = o1[a];
+        }
+        __syncthreads();
+        T tt[N1];
+        if (inslot) {
+#pragma unroll
+            for (int k = 0; k < N1; ++k) {
+                const int l = k * SK + j * SJ + i;
+                T x0 = B[l], x1 = A[l], xx2 = x2[k];
+                T g[6], lam;
+                tri_adj<T>(tc, T(bs.xi[k]), T(bs.w[k]), g, lam);
+                x0 *= lam;
+                x1 *= lam;
+                xx2 *= lam;
+                B[l] = fma(g[0], x0, fma(g[1], x1, g[2] * xx2));
+                A[l] = fma(g[1], x0, fma(g[3], x1, g[4] * xx2));
+                tt[k] = fma(g[2], x0, fma(g[4], x1, g[5] * xx2));
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < N1; ++k) tt[k] = T(0);
+        }
+        T y2[N1];
+        contract<N1, true, true>(bs, tt, y2);
+        __syncthreads();
+        if (inslot) {
+            T p[N1], o[N1];
+#pragma unroll
+            for (int n = 0; n < N1; ++n) p[n] = B[pb * SK + pa * SJ + n];
+            contract<N1, true, true>(bs, p, o);
+#pragma unroll
+            for (int a = 0; a < N1; ++a) B[pb * SK + pa * SJ + a] = o[a];
+#pragma unroll
+            for (int n = 0; n < N1; ++n) p[n] = A[pb * SK + n * SJ + pa];
+            contract<N1, true, true>(bs, p, o1);
+        }
+        __syncthreads();
+        if (inslot) {
+#pragma unroll
+            for (int a = 0; a < N1; ++a) B[pb * SK + a * SJ + pa] += o1[a];
+        }
+        __syncthreads();
+        if (active) {
+#pragma unroll
+            for (int k = 0; k < N1; ++k) Y[base + i + j * N1 + k * NT] = B[k * SK + j * SJ + i] + y2[k];
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBBlock, 2)
+batched_kernel(const char* __restrict__ ws)
+{
+    __shared__ __attribute__((aligned(16))) char lds[bmax_lds<T>()];
+    const BHeader* hd = reinterpret_cast<const BHeader*>(ws);
+    const BMesh* meshes = reinterpret_cast<const BMesh*>(ws + hd->off_mesh);
+    const BItem* items = reinterpret_cast<const BItem*>(ws + hd->off_items);
+    const Basis<T>* bases = reinterpret_cast<const Basis<T>*>(ws + hd->off_basis);
+    const int n_items = hd->n_items, nrhs = hd->nrhs;
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const BItem item = items[it];
+        const BMesh m = meshes[item.mesh];
+        const Basis<T>& bs = bases[m.N1 - 2];
+        switch (m.N1) {
+        case 2: batched_item<2, T>(m, item.eb, nrhs, bs, lds); break;
+        case 3: batched_item<3, T>(m, item.eb, nrhs, bs, lds); break;
+        case 4: batched_item<4, T>(m, item.eb, nrhs, bs, lds); break;
+        case 5: batched_item<5, T>(m, item.eb, nrhs, bs, lds); break;
+        case 6: batched_item<6, T>(m, item.eb, nrhs, bs, lds); break;
+        case 7: batched_item<7, T>(m, item.eb, nrhs, bs, lds); break;
+        case 8: batched_item<8, T>(m, item.eb, nrhs, bs, lds); break;
+        case 9: batched_item<9, T>(m, item.eb, nrhs, bs, lds); break;
+        default: batched_item<10, T>(m, item.eb, nrhs, bs, lds); break;
+        }
+    }
+}
+
+static int epb_of(int N1)
+{
+    switch (N1) {
+    case 2: return BShape<2>::EPB;
+    case 3: return BShape<3>::EPB;
+    case 4: return BShape<4>::EPB;
+    case 5: return BShape<5>::EPB;
+    case 6: return BShape<6>::EPB;
+    case 7: return BShape<7>::EPB;
+    case 8: return BShape<8>::EPB;
+    case 9: return BShape<9>::EPB;
+    default: return BShape<10>::EPB;
+    }
+}
+
+static int64_t n_items_of(int n_mesh, const ax_problem* meshes)
+{
+    int64_t n = 0;
+    for (int q = 0; q < n_mesh; ++q) {
+        const int e = epb_of(meshes[q].N + 1);
+        n += (meshes[q].E + e - 1) / e;
+    }
+    return n;
+}
+
+static void layout(int n_mesh, int64_t n_items, BHeader& h)
+{
+    auto up = [](int64_t v) { return (v + 255) & ~int64_t(255); };
+    h.off_mesh = up(sizeof(BHeader));
+    h.off_items = up(h.off_mesh + (int64_t)n_mesh * sizeof(BMesh));
+    h.off_basis = up(h.off_items + n_items * (int64_t)sizeof(BItem));
+    h.bytes = h.off_basis + 9 * (int64_t)std::max(sizeof(Basis<double>), sizeof(Basis<float>));
+}
+
+static int check_meshes(int n_mesh, const ax_problem* meshes)
+{
+    if (n_mesh < 0) return fail(AX_ERR_ARG, "n_mesh < 0");
+    if (n_mesh > 0 && !meshes) return fail(AX_ERR_ARG, "meshes is NULL");
+    for (int q = 0; q < n_mesh; ++q) {
+        const ax_problem& p = meshes[q];
+        if (p.E < 0) return fail(AX_ERR_ARG, "mesh %d: E < 0", q);
+        if (p.N < 1 || p.N > 9) return fail(AX_ERR_UNSUPPORTED, "mesh %d: batched orders are 1..9 (N=%d)", q, p.N);
+        if (p.geom != AX_TRILINEAR) return fail(AX_ERR_UNSUPPORTED, "mesh %d: batched path is trilinear", q);
+        if (p.E > 0 && (!p.geo || !p.D || !p.xi || !p.w)) return fail(AX_ERR_ARG, "mesh %d: NULL array", q);
+        if (p.E > 0 && !centro_antisymmetric(p.N + 1, p.D))
+            return fail(AX_ERR_UNSUPPORTED, "mesh %d: D must be a GLL differentiation matrix", q);
+        if ((int64_t)((p.E + epb_of(p.N + 1) - 1) / epb_of(p.N + 1)) > 0x7fffffff)
+            return fail(AX_ERR_UNSUPPORTED, "mesh %d too large", q);
+    }
+    return AX_OK;
+}
+
+}  // namespace ax
+
+using namespace ax;
+
+extern "C" int ax_batched_workspace_bytes(int n_mesh, const ax_problem* meshes, size_t* bytes)
+{
+    clear_error();
+    AX_TRY(check_meshes(n_mesh, meshes));
+    if (!bytes) return fail(AX_ERR_ARG, "bytes is NULL");
+    BHeader h{};
+    layout(n_mesh, n_items_of(n_mesh, meshes), h);
+    *bytes = (size_t)h.bytes;
+    return AX_OK;
+}
+
+extern "C" int ax_batched_prepare(int n_mesh, const ax_problem* meshes, int nrhs, int prec,
+                                  const void* const* X, void* const* Y, const int64_t* col_stride,
+                                  void* workspace, size_t workspace_bytes, ax_batch_plan* plan)
+{
+    clear_error();
+    if (!plan) return fail(AX_ERR_ARG, "plan is NULL");
+    std::memset(plan, 0, sizeof(*plan));
+    AX_TRY(check_meshes(n_mesh, meshes));
+    if (nrhs < 1) return fail(AX_ERR_ARG, "nrhs < 1");
+    if (prec != AX_FP64 && prec != AX_FP32) return fail(AX_ERR_UNSUPPORTED, "batched precision must be FP64 or FP32");
+    if (!workspace) return fail(AX_ERR_ARG, "workspace is NULL");
+    if (n_mesh > 0 && (!X || !Y)) return fail(AX_ERR_ARG, "X or Y is NULL");
+    for (int q = 0; q < n_mesh; ++q) {
+        if (meshes[q].E > 0 && (!X[q] || !Y[q])) return fail(AX_ERR_ARG, "mesh %d: X or Y is NULL", q);
+        if (meshes[q].E > 0 && X[q] == Y[q]) return fail(AX_ERR_ARG, "mesh %d: X and Y alias", q);
+    }
+    const int64_t n_items = n_items_of(n_mesh, meshes);
+    BHeader h{};
+    layout(n_mesh, n_items, h);
+    if ((size_t)h.bytes > workspace_bytes) return fail(AX_ERR_NOMEM, "workspace of %lld bytes needed", (long long)h.bytes);
+    h.n_mesh = n_mesh;
+    h.n_items = (int)n_items;
+    h.nrhs = nrhs;
+    h.prec = prec;
+    h.ready = 1;
+    std::vector<char> host((size_t)h.bytes, 0);
+    std::vector<BMesh> bm(n_mesh);
+    for (int q = 0; q < n_mesh; ++q) {
+        const int64_t np = (int64_t)(meshes[q].N + 1) * (meshes[q].N + 1) * (meshes[q].N + 1);
+        const int64_t ld = col_stride ? col_stride[q] : meshes[q].E * np;
+        if (ld < meshes[q].E * np) return fail(AX_ERR_ARG, "mesh %d: column stride below E*N1^3", q);
+        bm[q] = BMesh{meshes[q].E, ld, meshes[q].geo, X[q], Y[q], meshes[q].N + 1, 0};
+    }
+    // items, longest first: cost of a group ~ EPB * N1^4 (the contraction work)
+    std::vector<BItem> items;
+    items.reserve((size_t)n_items);
+    std::vector<std::pair<double, int>> order(n_mesh);
+    for (int q = 0; q < n_mesh; ++q) {
+        const double n1 = meshes[q].N + 1;
+        order[q] = {-(double)epb_of(meshes[q].N + 1) * n1 * n1 * n1 * n1, q};
+    }
+    std::stable_sort(order.begin(), order.end());
+    for (auto& o : order) {
+        const int q = o.second;
+        const int e = epb_of(meshes[q].N + 1);
+        const int64_t groups = (meshes[q].E + e - 1) / e;
+        for (int64_t g = 0; g < groups; ++g) items.push_back(BItem{q, (int)g});
+    }
+    std::memcpy(host.data(), &h, sizeof(h));
+    if (n_mesh) std::memcpy(host.data() + h.off_mesh, bm.data(), sizeof(BMesh) * n_mesh);
+    if (n_items) std::memcpy(host.data() + h.off_items, items.data(), sizeof(BItem) * n_items);
+    // GLL tables of every order used, indexed by N1 - 2
+    for (int q = 0; q < n_mesh; ++q) {
+        const int N1 = meshes[q].N + 1;
+        if (prec == AX_FP64) {
+            Basis<double> b;
+            fill_basis(b, N1, meshes[q].D, meshes[q].xi, meshes[q].w);
+            std::memcpy(host.data() + h.off_basis + (N1 - 2) * sizeof(Basis<double>), &b, sizeof(b));
+        } else {
+            Basis<float> b;
+            fill_basis(b, N1, meshes[q].D, meshes[q].xi, meshes[q].w);
+            std::memcpy(host.data() + h.off_basis + (N1 - 2) * sizeof(Basis<float>), &b, sizeof(b));
+        }
+    }
+    AX_TRY(hip_check(hipMemcpy(workspace, host.data(), (size_t)h.bytes, hipMemcpyHostToDevice),
+                     "batched workspace upload"));
+    plan->n_items = n_items;
+    plan->nrhs = nrhs;
+    plan->prec = prec;
+    plan->bytes = (size_t)h.bytes;
+    return AX_OK;
+}
+
+extern "C" int ax_local_batched(const ax_batch_plan* plan, const void* workspace, void* stream)
+{
+    clear_error();
+    if (!plan || !workspace) return fail(AX_ERR_ARG, "plan or workspace is NULL");
+    if (plan->prec != AX_FP64 && plan->prec != AX_FP32) return fail(AX_ERR_ARG, "plan was not filled by ax_batched_prepare");
+    if (plan->n_items == 0) return AX_OK;
+    int dev = 0, cus = 256, per = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    hipStream_t st = as_stream(stream);
+    if (plan->prec == AX_FP64) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_kernel<double>, kBBlock, 0) != hipSuccess || per < 1) per = 1;
+        const int grid = (int)std::min<int64_t>(plan->n_items, (int64_t)cus * per);
+        hipLaunchKernelGGL(batched_kernel<double>, dim3(grid), dim3(kBBlock), 0, st, (const char*)workspace);
+    } else {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_kernel<float>, kBBlock, 0) != hipSuccess || per < 1) per = 1;
+        const int grid = (int)std::min<int64_t>(plan->n_items, (int64_t)cus * per);
+        hipLaunchKernelGGL(batched_kernel<float>, dim3(grid), dim3(kBBlock), 0, st, (const char*)workspace);
+    }
+    return hip_check(hipGetLastError(), "batched launch");
 }

@@ -1,16 +1,680 @@
-// Conjugate gradients on the assembled operator (placeholder; implemented below in a later step).
+// Conjugate gradients on the assembled operator A = mask o Q^T AxLocal(Q .) (Eq. 1), the
+// iterative solve whose dominant kernel is AxLocal (Sec. 1), plus mixed-precision iterative
+// refinement: FP64 outer residual, norm and update; inner CG with a reduced-precision AxLocal,
+// float vectors and FP64-accumulated dot products.
+//
+// Every scalar of the iteration (alpha, beta, |r|^2) lives on the device; the host only polls
+// the convergence flags every few iterations.  Dot products are two-stage reductions with a
+// fixed grid and a fixed combination order, so a solve is bitwise reproducible.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <type_traits>
+#include <vector>
+
 #include "ax_internal.h"
 
-extern "C" int cg_workspace_bytes(const ax_problem*, int, const ax_cg_opts*, size_t* bytes)
+namespace ax {
+
+int gs_apply(int64_t n_local, int64_t n_global, const int32_t* l2g, const int64_t* gptr,
+             const int32_t* gidx, const uint8_t* mask, int mode, int nrhs, int dtype, const void* in,
+             void* out, hipStream_t st);
+
+constexpr int kRedBlocks = 512;  // partial sums per dot product and column
+constexpr int kRedThreads = 256;
+constexpr int kPoll = 8;         // iterations between host convergence checks
+
+// Per-column scalar state of one CG (device).
+struct CgScal {
+    double rr;      // r . r
+    double alpha;
+    double beta;
+    double tol2;    // (rtol * |b|)^2 target on r . r
+    int converged;  // 1 once r . r <= tol2
+    int breakdown;  // 1 on p^T A p <= 0 or a non-finite scalar
+    int iters;
+    int pad;
+};
+
+template <typename TA, typename TB>
+__global__ void __launch_bounds__(kRedThreads)
+dot_partial_kernel(const TA* __restrict__ a, const TB* __restrict__ b, int64_t n,
+                   double* __restrict__ partials)
 {
-    ax::clear_error();
-    if (bytes) *bytes = 0;
-    return ax::fail(AX_ERR_UNSUPPORTED, "cg_solve not available yet");
+    const int c = blockIdx.y;
+    a += (int64_t)c * n;
+    b += (int64_t)c * n;
+    double s = 0.0;
+    for (int64_t q = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * kRedThreads)
+        s = fma((double)a[q], (double)b[q], s);
+    __shared__ double red[kRedThreads];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = kRedThreads / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[c * kRedBlocks + blockIdx.x] = red[0];
 }
 
-extern "C" int cg_solve(const ax_problem*, int, const double*, double*, const ax_cg_opts*,
-                        ax_cg_report*, void*)
+__device__ double block_sum_partials(const double* partials)
 {
-    ax::clear_error();
-    return ax::fail(AX_ERR_UNSUPPORTED, "cg_solve not available yet");
+    __shared__ double red[kRedThreads];
+    double s = 0.0;
+    for (int q = threadIdx.x; q < kRedBlocks; q += kRedThreads) s += partials[q];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = kRedThreads / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    return red[0];
+}
+
+// mode 0: rr = sum (initial), converged if rr <= tol2.   mode 1: alpha = rr / sum (= p.Ap).
+// mode 2: rr_new = sum; beta = rr_new / rr; rr = rr_new; converged test.
+__global__ void __launch_bounds__(kRedThreads)
+cg_scalar_kernel(const double* __restrict__ partials, CgScal* __restrict__ sc, int mode)
+{
+    const int c = blockIdx.x;
+    const double s = block_sum_partials(partials + c * kRedBlocks);
+    if (threadIdx.x != 0) return;
+    CgScal& q = sc[c];
+    if (mode == 0) {
+        q.rr = s;
+        q.converged = (s <= q.tol2) ? 1 : 0;
+        q.breakdown = isfinite(s) ? 0 : 1;
+        q.iters = 0;
+        q.alpha = q.beta = 0.0;
+    } else if (mode == 1) {
+        if (q.converged || q.breakdown) {
+            q.alpha = 0.0;
+        } else if (!(s > 0.0) || !isfinite(s)) {
+            q.breakdown = 1;
+            q.alpha = 0.0;
+        } else {
+            q.alpha = q.rr / s;
+        }
+    } else {
+        if (q.converged || q.breakdown) {
+            q.beta = 0.0;
+        } else {
+            q.beta = s / q.rr;
+            q.rr = s;
+            q.iters += 1;
+            if (!isfinite(s)) q.breakdown = 1;
+            else if (s <= q.tol2) q.converged = 1;
+        }
+    }
+}
+
+// x += alpha p; r -= alpha Ap
+template <typename TX, typename T>
+__global__ void __launch_bounds__(256)
+cg_update_kernel(TX* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
+                 const T* __restrict__ Ap, const CgScal* __restrict__ sc, int64_t n)
+{
+    const int c = blockIdx.y;
+    const double al = sc[c].alpha;
+    if (al == 0.0) return;
+    const int64_t o = (int64_t)c * n;
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (int64_t)gridDim.x * 256) {
+        x[o + q] = (TX)((double)x[o + q] + al * (double)p[o + q]);
+        r[o + q] = (T)((double)r[o + q] - al * (double)Ap[o + q]);
+    }
+}
+
+// p = r + beta p
+template <typename T>
+__global__ void __launch_bounds__(256)
+cg_dir_kernel(T* __restrict__ p, const T* __restrict__ r, const CgScal* __restrict__ sc, int64_t n)
+{
+    const int c = blockIdx.y;
+    if (sc[c].converged || sc[c].breakdown) return;
+    const double be = sc[c].beta;
+    const int64_t o = (int64_t)c * n;
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (int64_t)gridDim.x * 256)
+        p[o + q] = (T)((double)r[o + q] + be * (double)p[o + q]);
+}
+
+// r = b - Ax (FP64), also zeroes entries under the mask of r
+__global__ void __launch_bounds__(256)
+residual_kernel(double* __restrict__ r, const double* __restrict__ b, const double* __restrict__ Ax,
+                int64_t n)
+{
+    const int64_t o = (int64_t)blockIdx.y * n;
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (int64_t)gridDim.x * 256)
+        r[o + q] = b[o + q] - Ax[o + q];
+}
+
+// dst(float) = src(double) * scale[c]; scale = 1 / |r| from the scalar state
+__global__ void __launch_bounds__(256)
+scale_to_f32_kernel(float* __restrict__ dst, const double* __restrict__ src,
+                    const CgScal* __restrict__ sc, int64_t n)
+{
+    const int c = blockIdx.y;
+    const double nr = sqrt(sc[c].rr);
+    const double s = nr > 0.0 ? 1.0 / nr : 0.0;
+    const int64_t o = (int64_t)c * n;
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (int64_t)gridDim.x * 256)
+        dst[o + q] = (float)(src[o + q] * s);
+}
+
+// x += |r| d (FP64 update with the float correction)
+__global__ void __launch_bounds__(256)
+ir_update_kernel(double* __restrict__ x, const float* __restrict__ d, const CgScal* __restrict__ sc,
+                 int64_t n)
+{
+    const int c = blockIdx.y;
+    const double nr = sqrt(sc[c].rr);
+    const int64_t o = (int64_t)c * n;
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (int64_t)gridDim.x * 256)
+        x[o + q] += nr * (double)d[o + q];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+copy_kernel(T* __restrict__ dst, const T* __restrict__ src, int64_t n)
+{
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (int64_t)gridDim.x * 256)
+        dst[q] = src[q];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) zero_kernel(T* __restrict__ dst, int64_t n)
+{
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (int64_t)gridDim.x * 256)
+        dst[q] = T(0);
+}
+
+__global__ void set_tol_kernel(CgScal* sc, const double* __restrict__ partials, double rtol)
+{
+    const int c = blockIdx.x;
+    const double bb = block_sum_partials(partials + c * kRedBlocks);
+    if (threadIdx.x == 0) {
+        sc[c].tol2 = rtol * rtol * bb;
+        sc[c].converged = 0;
+        sc[c].breakdown = 0;
+    }
+}
+
+static unsigned vgrid(int64_t n)
+{
+    const int64_t b = (n + 255) / 256;
+    return (unsigned)(b < 8192 ? (b > 0 ? b : 1) : 8192);
+}
+
+// Device workspace carve-up (256-byte aligned pieces).
+struct Carver {
+    char* p;
+    size_t used = 0, cap;
+    template <typename T>
+    T* take(size_t count)
+    {
+        size_t off = (used + 255) & ~size_t(255);
+        used = off + count * sizeof(T);
+        return (p && used <= cap) ? reinterpret_cast<T*>(p + off) : nullptr;
+    }
+};
+
+struct CgWork {
+    double *r, *p, *Ap;            // FP64 global vectors [nrhs][ng]
+    double *pl, *wl;               // FP64 local vectors [nrhs][nl]
+    float *b32, *r32, *p32, *Ap32, *d32; // inner global vectors
+    float *pl32, *wl32;            // inner local vectors
+    double* partials;              // [nrhs][kRedBlocks]
+    CgScal *sc, *sc_in;            // outer / inner scalar state [nrhs]
+};
+
+static void carve(Carver& cv, int64_t nl, int64_t ng, int nrhs, bool mixed, CgWork& w)
+{
+    w.r = cv.take<double>(ng * nrhs);
+    w.p = cv.take<double>(ng * nrhs);
+    w.Ap = cv.take<double>(ng * nrhs);
+    w.pl = cv.take<double>(nl * nrhs);
+    w.wl = cv.take<double>(nl * nrhs);
+    if (mixed) {
+        w.b32 = cv.take<float>(ng * nrhs);
+        w.r32 = cv.take<float>(ng * nrhs);
+        w.p32 = cv.take<float>(ng * nrhs);
+        w.Ap32 = cv.take<float>(ng * nrhs);
+        w.d32 = cv.take<float>(ng * nrhs);
+        w.pl32 = cv.take<float>(nl * nrhs);
+        w.wl32 = cv.take<float>(nl * nrhs);
+    } else {
+        w.b32 = w.r32 = w.p32 = w.Ap32 = w.d32 = w.pl32 = w.wl32 = nullptr;
+    }
+    w.partials = cv.take<double>((size_t)kRedBlocks * nrhs);
+    w.sc = cv.take<CgScal>(nrhs);
+    w.sc_in = cv.take<CgScal>(nrhs);
+}
+
+// The assembled operator y = mask o Q^T AxLocal(Q x) over one mesh (ax_local) or over the
+// union of many meshes (one batched persistent launch whose X/Y pointers are the local work
+// vectors; the union gather-scatter then assembles every mesh at once).
+struct Operator {
+    int64_t n_local = 0, n_global = 0;
+    const int32_t* l2g = nullptr;
+    const int64_t* gptr = nullptr;
+    const int32_t* gidx = nullptr;
+    const uint8_t* mask = nullptr;
+    const ax_problem* p = nullptr;  // single mesh
+    const ax_batch_plan* plan64 = nullptr;
+    const void* ws64 = nullptr;
+    const ax_batch_plan* plan32 = nullptr;
+    const void* ws32 = nullptr;
+};
+
+template <typename T>
+static int apply_op(const Operator& op, int nrhs, int prec, const T* x, T* y, T* xl, T* yl, hipStream_t st)
+{
+    const int dt = sizeof(T) == 8 ? AX_FP64 : AX_FP32;
+    AX_TRY(gs_apply(op.n_local, op.n_global, op.l2g, op.gptr, op.gidx, nullptr, GS_Q, nrhs, dt, x, xl, st));
+    if (op.p) {
+        const ax_problem& pb = *op.p;
+        AX_TRY(ax_local(pb.E, pb.N, pb.geom, pb.geo, pb.D, pb.xi, pb.w, nrhs, prec, xl, yl, st));
+    } else if (sizeof(T) == 8) {
+        AX_TRY(ax_local_batched(op.plan64, op.ws64, st));
+    } else {
+        AX_TRY(ax_local_batched(op.plan32, op.ws32, st));
+    }
+    AX_TRY(gs_apply(op.n_local, op.n_global, op.l2g, op.gptr, op.gidx, op.mask, GS_QT, nrhs, dt, yl, y, st));
+    return AX_OK;
+}
+
+template <typename TA, typename TB>
+static int dot(const TA* a, const TB* b, int64_t n, int nrhs, double* partials, hipStream_t st)
+{
+    hipLaunchKernelGGL((dot_partial_kernel<TA, TB>), dim3(kRedBlocks, nrhs), dim3(kRedThreads), 0, st, a,
+                       b, n, partials);
+    return hip_check(hipGetLastError(), "dot");
+}
+
+static int scal(const double* partials, CgScal* sc, int mode, int nrhs, hipStream_t st)
+{
+    hipLaunchKernelGGL(cg_scalar_kernel, dim3(nrhs), dim3(kRedThreads), 0, st, partials, sc, mode);
+    return hip_check(hipGetLastError(), "cg scalar");
+}
+
+// Host view of the scalar state (synchronises the stream).
+static int poll(const CgScal* sc, int nrhs, std::vector<CgScal>& h, hipStream_t st)
+{
+    h.resize(nrhs);
+    AX_TRY(hip_check(hipMemcpyAsync(h.data(), sc, sizeof(CgScal) * nrhs, hipMemcpyDeviceToHost, st),
+                     "poll copy"));
+    return hip_check(hipStreamSynchronize(st), "poll sync");
+}
+
+// One block of kPoll CG iterations (device scalars only: capturable).
+template <typename TX, typename T>
+static int cg_block(const Operator& op, int nrhs, int prec, TX* x, T* r, T* p, T* Ap, T* pl, T* wl,
+                    double* partials, CgScal* sc, int count, hipStream_t st)
+{
+    const int64_t ng = op.n_global;
+    const dim3 g(vgrid(ng), nrhs);
+    for (int q = 0; q < count; ++q) {
+        AX_TRY(apply_op<T>(op, nrhs, prec, p, Ap, pl, wl, st));
+        AX_TRY(dot(p, Ap, ng, nrhs, partials, st));
+        AX_TRY(scal(partials, sc, 1, nrhs, st));
+        hipLaunchKernelGGL((cg_update_kernel<TX, T>), g, dim3(256), 0, st, x, r, p, Ap, sc, ng);
+        AX_TRY(dot(r, r, ng, nrhs, partials, st));
+        AX_TRY(scal(partials, sc, 2, nrhs, st));
+        hipLaunchKernelGGL(cg_dir_kernel<T>, g, dim3(256), 0, st, p, r, sc, ng);
+    }
+    return hip_check(hipGetLastError(), "cg iteration");
+}
+
+// A captured kPoll-iteration block, reused while the buffers stay the same.
+struct GraphCache {
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    ~GraphCache()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
+// Plain CG in precision T on A_T x = b (x holds the initial guess unless x_zero).  `iters` gets
+// the largest iteration count over the columns.  Returns AX_OK (all converged),
+// AX_ERR_NOT_CONVERGED or AX_ERR_BREAKDOWN.
+template <typename TX, typename T>
+static int cg_core(const Operator& op, int nrhs, int prec, const T* b, TX* x, T* r, T* p, T* Ap,
+                   T* pl, T* wl, double* partials, CgScal* sc, double rtol, int max_it, bool x_zero,
+                   GraphCache* gc, int& iters, hipStream_t st)
+{
+    const int64_t ng = op.n_global;
+    const dim3 g(vgrid(ng), nrhs);
+    AX_TRY(dot(b, b, ng, nrhs, partials, st));
+    hipLaunchKernelGGL(set_tol_kernel, dim3(nrhs), dim3(kRedThreads), 0, st, sc, partials, rtol);
+    if (x_zero) {
+        hipLaunchKernelGGL(copy_kernel<T>, dim3(vgrid(ng * nrhs)), dim3(256), 0, st, r, b, ng * nrhs);
+    } else {
+        if constexpr (std::is_same<T, double>::value && std::is_same<TX, double>::value) {
+            AX_TRY(apply_op<T>(op, nrhs, prec, (const T*)x, Ap, pl, wl, st));
+            hipLaunchKernelGGL(residual_kernel, g, dim3(256), 0, st, (double*)r, (const double*)b,
+                               (const double*)Ap, ng);
+        } else {
+            return fail(AX_ERR_ARG, "internal: warm start needs FP64 vectors");
+        }
+    }
+    hipLaunchKernelGGL(copy_kernel<T>, dim3(vgrid(ng * nrhs)), dim3(256), 0, st, p, r, ng * nrhs);
+    AX_TRY(dot(r, r, ng, nrhs, partials, st));
+    AX_TRY(scal(partials, sc, 0, nrhs, st));
+    std::vector<CgScal> h;
+    int it = 0;
+    for (;;) {
+        AX_TRY(poll(sc, nrhs, h, st));
+        bool all = true, brk = false;
+        iters = 0;
+        for (int c = 0; c < nrhs; ++c) {
+            all = all && h[c].converged;
+            brk = brk || h[c].breakdown;
+            iters = iters > h[c].iters ? iters : h[c].iters;
+        }
+        if (brk) return fail(AX_ERR_BREAKDOWN, "CG breakdown (p^T A p <= 0 or non-finite)");
+        if (all) return AX_OK;
+        if (it >= max_it) return fail(AX_ERR_NOT_CONVERGED, "CG reached %d iterations", max_it);
+        const int count = (max_it - it) < kPoll ? (max_it - it) : kPoll;
+        if (gc && count == kPoll) {
+            if (!gc->exec) {
+                AX_TRY(hip_check(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed), "begin capture"));
+                const int s = cg_block<TX, T>(op, nrhs, prec, x, r, p, Ap, pl, wl, partials, sc, kPoll, st);
+                hipGraph_t graph = nullptr;
+                const hipError_t ec = hipStreamEndCapture(st, &graph);
+                if (s != AX_OK) {
+                    if (graph) (void)hipGraphDestroy(graph);
+                    return s;
+                }
+                AX_TRY(hip_check(ec, "end capture"));
+                gc->graph = graph;
+                AX_TRY(hip_check(hipGraphInstantiate(&gc->exec, graph, nullptr, nullptr, 0), "graph instantiate"));
+            }
+            AX_TRY(hip_check(hipGraphLaunch(gc->exec, st), "graph launch"));
+        } else {
+            AX_TRY((cg_block<TX, T>(op, nrhs, prec, x, r, p, Ap, pl, wl, partials, sc, count, st)));
+        }
+        it += count;
+    }
+}
+
+static int validate(const ax_problem* p, int nrhs, const ax_cg_opts* o)
+{
+    if (!p || !o) return fail(AX_ERR_ARG, "NULL problem or options");
+    if (nrhs < 1) return fail(AX_ERR_ARG, "nrhs < 1");
+    if (p->E < 0 || p->n_global < 0) return fail(AX_ERR_ARG, "negative size");
+    if (p->N < 1 || p->N > 15) return fail(AX_ERR_UNSUPPORTED, "order N=%d outside [1,15]", p->N);
+    if (p->geom != AX_TRILINEAR && p->geom != AX_PARALLELEPIPED) return fail(AX_ERR_UNSUPPORTED, "geometry");
+    if (o->inner_prec != AX_FP64 && o->inner_prec != AX_FP32 && o->inner_prec != AX_FP16_ACC32)
+        return fail(AX_ERR_UNSUPPORTED, "inner precision %d", o->inner_prec);
+    if (!(o->rtol > 0.0)) return fail(AX_ERR_ARG, "rtol must be > 0");
+    if (o->max_it < 1) return fail(AX_ERR_ARG, "max_it < 1");
+    if (o->inner_prec != AX_FP64 && (!(o->inner_rtol > 0.0) || o->max_outer < 1))
+        return fail(AX_ERR_ARG, "refinement needs inner_rtol > 0 and max_outer >= 1");
+    if (p->E > 0 && (!p->geo || !p->D || !p->w || !p->l2g || !p->gptr || !p->gidx))
+        return fail(AX_ERR_ARG, "NULL problem array");
+    if (p->geom == AX_TRILINEAR && !p->xi) return fail(AX_ERR_ARG, "xi is NULL");
+    return AX_OK;
+}
+
+// Shared driver of cg_solve and cg_solve_batched.
+static int solve(const Operator& op, int64_t nl, int nrhs, const double* b, double* x, const ax_cg_opts* o,
+                 ax_cg_report* rep, CgWork& w, hipStream_t st)
+{
+    const int64_t ng = op.n_global;
+    const dim3 g(vgrid(ng), nrhs);
+    const bool mixed = o->inner_prec != AX_FP64;
+    int status = AX_OK;
+    std::vector<CgScal> h;
+    GraphCache gc64, gc32;
+    const bool graphs = o->use_graph != 0;
+
+    auto true_residual = [&](double& worst) -> int {
+        AX_TRY(apply_op<double>(op, nrhs, AX_FP64, x, w.Ap, w.pl, w.wl, st));
+        hipLaunchKernelGGL(residual_kernel, g, dim3(256), 0, st, w.r, b, w.Ap, ng);
+        AX_TRY(dot(b, b, ng, nrhs, w.partials, st));
+        hipLaunchKernelGGL(set_tol_kernel, dim3(nrhs), dim3(kRedThreads), 0, st, w.sc, w.partials, 1.0);
+        AX_TRY(dot(w.r, w.r, ng, nrhs, w.partials, st));
+        AX_TRY(scal(w.partials, w.sc, 0, nrhs, st));
+        AX_TRY(poll(w.sc, nrhs, h, st));
+        worst = 0.0;
+        for (int c = 0; c < nrhs; ++c) {
+            const double rel = h[c].tol2 > 0 ? std::sqrt(h[c].rr / h[c].tol2) : std::sqrt(h[c].rr);
+            worst = worst > rel ? worst : rel;
+        }
+        return AX_OK;
+    };
+
+    if (!mixed) {
+        int total = 0;
+        double worst = 0.0;
+        for (int restart = 0; restart < 4; ++restart) {
+            int it = 0;
+            status = cg_core<double, double>(op, nrhs, AX_FP64, b, x, w.r, w.p, w.Ap, w.pl, w.wl, w.partials, w.sc,
+                                             o->rtol, o->max_it - total, false, graphs ? &gc64 : nullptr, it, st);
+            total += it;
+            if (status == AX_ERR_BREAKDOWN) break;
+            if (status != AX_OK && status != AX_ERR_NOT_CONVERGED) return status;
+            AX_TRY(true_residual(worst));
+            if (worst <= o->rtol || total >= o->max_it) break;
+        }
+        rep->outer_it = 1;
+        rep->inner_it_total = total;
+        rep->rel_res_true = worst;
+        if (status == AX_OK && worst > o->rtol) status = AX_ERR_NOT_CONVERGED;
+    } else {
+        int total = 0, outer = 0;
+        double worst = 0.0;
+        for (outer = 0; outer < o->max_outer; ++outer) {
+            AX_TRY(true_residual(worst));
+            if (worst <= o->rtol) break;
+            hipLaunchKernelGGL(scale_to_f32_kernel, g, dim3(256), 0, st, w.b32, w.r, w.sc, ng);
+            hipLaunchKernelGGL(zero_kernel<float>, dim3(vgrid(ng * nrhs)), dim3(256), 0, st, w.d32, ng * nrhs);
+            int it = 0;
+            const int s = cg_core<float, float>(op, nrhs, o->inner_prec, w.b32, w.d32, w.r32, w.p32, w.Ap32,
+                                                w.pl32, w.wl32, w.partials, w.sc_in, o->inner_rtol, o->max_it,
+                                                true, graphs ? &gc32 : nullptr, it, st);
+            // an inner solve that stops on its iteration limit or breaks down still yields a
+            // useful correction; only launch errors abort
+            if (s != AX_OK && s != AX_ERR_NOT_CONVERGED && s != AX_ERR_BREAKDOWN) return s;
+            clear_error();
+            total += it;
+            hipLaunchKernelGGL(ir_update_kernel, g, dim3(256), 0, st, x, w.d32, w.sc, ng);
+            AX_TRY(hip_check(hipGetLastError(), "refinement update"));
+        }
+        if (outer == o->max_outer) AX_TRY(true_residual(worst));
+        rep->outer_it = outer;
+        rep->inner_it_total = total;
+        rep->rel_res_true = worst;
+        status = worst <= o->rtol ? AX_OK : AX_ERR_NOT_CONVERGED;
+    }
+    (void)nl;
+    return status;
+}
+
+// The solver runs on a private non-blocking stream of the calling thread (a HIP graph cannot be
+// captured on the null stream); the caller's stream is synchronised before and after.
+static int private_stream(hipStream_t& s)
+{
+    static thread_local hipStream_t ps = nullptr;
+    if (!ps) AX_TRY(hip_check(hipStreamCreateWithFlags(&ps, hipStreamNonBlocking), "stream create"));
+    s = ps;
+    return AX_OK;
+}
+
+static int finish(int status, ax_cg_report* rep, const std::chrono::steady_clock::time_point& t0,
+                  hipStream_t st, hipStream_t caller)
+{
+    AX_TRY(hip_check(hipStreamSynchronize(st), "cg sync"));
+    AX_TRY(hip_check(hipStreamSynchronize(caller), "cg sync"));
+    rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    rep->status = status;
+    if (status != AX_OK && ax_last_error()[0] == '\0')
+        set_error("cg_solve: relative residual %.3e above the target", rep->rel_res_true);
+    return status;
+}
+
+}  // namespace ax
+
+using namespace ax;
+
+extern "C" int cg_workspace_bytes(const ax_problem* p, int nrhs, const ax_cg_opts* o, size_t* bytes)
+{
+    clear_error();
+    AX_TRY(validate(p, nrhs, o));
+    if (!bytes) return fail(AX_ERR_ARG, "bytes is NULL");
+    const int N1 = p->N + 1;
+    Carver cv{nullptr, 0, 0};
+    CgWork w;
+    carve(cv, p->E * N1 * N1 * N1, p->n_global, nrhs, o->inner_prec != AX_FP64, w);
+    *bytes = cv.used + 256;
+    return AX_OK;
+}
+
+extern "C" int cg_solve(const ax_problem* p, int nrhs, const double* b, double* x, const ax_cg_opts* o,
+                        ax_cg_report* rep, void* stream)
+{
+    clear_error();
+    AX_TRY(validate(p, nrhs, o));
+    if (!rep) return fail(AX_ERR_ARG, "report is NULL");
+    std::memset(rep, 0, sizeof(*rep));
+    if (p->n_global == 0) return AX_OK;
+    if (!b || !x) return fail(AX_ERR_ARG, "b or x is NULL");
+    size_t need = 0;
+    AX_TRY(cg_workspace_bytes(p, nrhs, o, &need));
+    if (!o->workspace || o->workspace_bytes < need)
+        return fail(AX_ERR_NOMEM, "workspace of %zu bytes needed", need);
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t caller = as_stream(stream), st = nullptr;
+    AX_TRY(private_stream(st));
+    AX_TRY(hip_check(hipStreamSynchronize(caller), "cg sync"));
+    const int N1 = p->N + 1;
+    const int64_t nl = p->E * N1 * N1 * N1;
+    Carver cv{(char*)(((uintptr_t)o->workspace + 255) & ~uintptr_t(255)), 0, o->workspace_bytes - 256};
+    CgWork w;
+    carve(cv, nl, p->n_global, nrhs, o->inner_prec != AX_FP64, w);
+    Operator op;
+    op.n_local = nl;
+    op.n_global = p->n_global;
+    op.l2g = p->l2g;
+    op.gptr = p->gptr;
+    op.gidx = p->gidx;
+    op.mask = p->mask;
+    op.p = p;
+    const int status = solve(op, nl, nrhs, b, x, o, rep, w, st);
+    if (status != AX_OK && status != AX_ERR_NOT_CONVERGED && status != AX_ERR_BREAKDOWN) {
+        (void)hipStreamSynchronize(st);
+        return status;
+    }
+    return finish(status, rep, t0, st, caller);
+}
+
+static int batched_sizes(int n_mesh, const ax_problem* meshes, int64_t& nl, std::vector<int64_t>& lbase)
+{
+    nl = 0;
+    lbase.resize(n_mesh);
+    for (int q = 0; q < n_mesh; ++q) {
+        const int64_t N1 = meshes[q].N + 1;
+        lbase[q] = nl;
+        nl += meshes[q].E * N1 * N1 * N1;
+    }
+    return AX_OK;
+}
+
+static int validate_batched(int n_mesh, const ax_problem* meshes, int64_t n_global, int nrhs, const ax_cg_opts* o)
+{
+    if (n_mesh < 1 || !meshes) return fail(AX_ERR_ARG, "no meshes");
+    if (!o) return fail(AX_ERR_ARG, "NULL options");
+    if (o->inner_prec == AX_FP16_ACC32) return fail(AX_ERR_UNSUPPORTED, "batched refinement supports FP32 inner solves");
+    ax_problem u = meshes[0];
+    u.n_global = n_global;
+    u.l2g = reinterpret_cast<const int32_t*>(1);
+    u.gptr = reinterpret_cast<const int64_t*>(1);
+    u.gidx = reinterpret_cast<const int32_t*>(1);
+    AX_TRY(validate(&u, nrhs, o));
+    size_t bytes = 0;
+    return ax_batched_workspace_bytes(n_mesh, meshes, &bytes);
+}
+
+extern "C" int cg_batched_workspace_bytes(int n_mesh, const ax_problem* meshes, int64_t n_global, int nrhs,
+                                          const ax_cg_opts* o, size_t* bytes)
+{
+    clear_error();
+    AX_TRY(validate_batched(n_mesh, meshes, n_global, nrhs, o));
+    if (!bytes) return fail(AX_ERR_ARG, "bytes is NULL");
+    int64_t nl;
+    std::vector<int64_t> lbase;
+    batched_sizes(n_mesh, meshes, nl, lbase);
+    Carver cv{nullptr, 0, 0};
+    CgWork w;
+    carve(cv, nl, n_global, nrhs, o->inner_prec != AX_FP64, w);
+    size_t bw = 0;
+    AX_TRY(ax_batched_workspace_bytes(n_mesh, meshes, &bw));
+    *bytes = cv.used + 2 * ((bw + 255) & ~size_t(255)) + 512;
+    return AX_OK;
+}
+
+extern "C" int cg_solve_batched(int n_mesh, const ax_problem* meshes, int64_t n_global, const int32_t* l2g,
+                                const int64_t* gptr, const int32_t* gidx, const uint8_t* mask, int nrhs,
+                                const double* b, double* x, const ax_cg_opts* o, ax_cg_report* rep, void* stream)
+{
+    clear_error();
+    AX_TRY(validate_batched(n_mesh, meshes, n_global, nrhs, o));
+    if (!rep) return fail(AX_ERR_ARG, "report is NULL");
+    std::memset(rep, 0, sizeof(*rep));
+    if (!l2g || !gptr || !gidx || !b || !x) return fail(AX_ERR_ARG, "NULL array");
+    size_t need = 0;
+    AX_TRY(cg_batched_workspace_bytes(n_mesh, meshes, n_global, nrhs, o, &need));
+    if (!o->workspace || o->workspace_bytes < need)
+        return fail(AX_ERR_NOMEM, "workspace of %zu bytes needed", need);
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t caller = as_stream(stream), st = nullptr;
+    AX_TRY(private_stream(st));
+    AX_TRY(hip_check(hipStreamSynchronize(caller), "cg sync"));
+    int64_t nl;
+    std::vector<int64_t> lbase;
+    batched_sizes(n_mesh, meshes, nl, lbase);
+    Carver cv{(char*)(((uintptr_t)o->workspace + 255) & ~uintptr_t(255)), 0, o->workspace_bytes - 256};
+    CgWork w;
+    const bool mixed = o->inner_prec != AX_FP64;
+    carve(cv, nl, n_global, nrhs, mixed, w);
+    size_t bw = 0;
+    AX_TRY(ax_batched_workspace_bytes(n_mesh, meshes, &bw));
+    char* ws64 = cv.take<char>(bw);
+    char* ws32 = cv.take<char>(bw);
+    // the batched launches read and write the solver's local work vectors (columns n_local apart)
+    std::vector<const void*> xs(n_mesh);
+    std::vector<void*> ys(n_mesh);
+    std::vector<int64_t> ld(n_mesh, nl);
+    ax_batch_plan plan64{}, plan32{};
+    for (int q = 0; q < n_mesh; ++q) {
+        xs[q] = w.pl + lbase[q];
+        ys[q] = w.wl + lbase[q];
+    }
+    AX_TRY(ax_batched_prepare(n_mesh, meshes, nrhs, AX_FP64, xs.data(), ys.data(), ld.data(), ws64, bw, &plan64));
+    if (mixed) {
+        for (int q = 0; q < n_mesh; ++q) {
+            xs[q] = w.pl32 + lbase[q];
+            ys[q] = w.wl32 + lbase[q];
+        }
+        AX_TRY(ax_batched_prepare(n_mesh, meshes, nrhs, AX_FP32, xs.data(), ys.data(), ld.data(), ws32, bw, &plan32));
+    }
+    Operator op;
+    op.n_local = nl;
+    op.n_global = n_global;
+    op.l2g = l2g;
+    op.gptr = gptr;
+    op.gidx = gidx;
+    op.mask = mask;
+    op.plan64 = &plan64;
+    op.ws64 = ws64;
+    op.plan32 = &plan32;
+    op.ws32 = ws32;
+    const int status = solve(op, nl, nrhs, b, x, o, rep, w, st);
+    if (status != AX_OK && status != AX_ERR_NOT_CONVERGED && status != AX_ERR_BREAKDOWN) {
+        (void)hipStreamSynchronize(st);
+        return status;
+    }
+    return finish(status, rep, t0, st, caller);
 }

@@ -46,30 +46,32 @@ __device__ __forceinline__ void cross3(const double* a, const double* b, double*
 }
 
 // Columns of 8J for the node column (r, s, :): col0 = a + t b, col1 = c + t d, col2 = u.
-__device__ __forceinline__ void tri_columns(const double* V, double r, double s, double* a, double* b,
-                                            double* c, double* d, double* u)
+// V(v, q) returns coordinate q of vertex v; it is called one coordinate at a time so that only
+// eight vertex words need to be live at once.
+template <typename VF>
+__device__ __forceinline__ void tri_columns(VF V, double r, double s, double* a, double* b, double* c,
+                                            double* d, double* u)
 {
     const double r0 = 1.0 - r, r1 = 1.0 + r, s0 = 1.0 - s, s1 = 1.0 + s;
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-        const double d00 = V[3 + q] - V[0 + q], d10 = V[9 + q] - V[6 + q];
-        const double d01 = V[15 + q] - V[12 + q], d11 = V[21 + q] - V[18 + q];
+        const double v0 = V(0, q), v1 = V(1, q), v2 = V(2, q), v3 = V(3, q);
+        const double v4 = V(4, q), v5 = V(5, q), v6 = V(6, q), v7 = V(7, q);
+        const double d00 = v1 - v0, d10 = v3 - v2, d01 = v5 - v4, d11 = v7 - v6;   // along r
         const double A = s0 * d00 + s1 * d10, B = s0 * d01 + s1 * d11;
         a[q] = A + B;
         b[q] = B - A;
-        const double e00 = V[6 + q] - V[0 + q], e10 = V[9 + q] - V[3 + q];
-        const double e01 = V[18 + q] - V[12 + q], e11 = V[21 + q] - V[15 + q];
+        const double e00 = v2 - v0, e10 = v3 - v1, e01 = v6 - v4, e11 = v7 - v5;   // along s
         const double A2 = r0 * e00 + r1 * e10, B2 = r0 * e01 + r1 * e11;
         c[q] = A2 + B2;
         d[q] = B2 - A2;
-        const double f00 = V[12 + q] - V[0 + q], f10 = V[15 + q] - V[3 + q];
-        const double f01 = V[18 + q] - V[6 + q], f11 = V[21 + q] - V[9 + q];
+        const double f00 = v4 - v0, f10 = v5 - v1, f01 = v6 - v2, f11 = v7 - v3;   // along t
         u[q] = s0 * (r0 * f00 + r1 * f10) + s1 * (r0 * f01 + r1 * f11);
     }
 }
 
-__device__ __forceinline__ void tri_prelude(const double* V, double r, double s, double wi, double wj,
-                                            TriCoef& k)
+template <typename VF>
+__device__ __forceinline__ void tri_prelude(VF V, double r, double s, double wi, double wj, TriCoef& k)
 {
     double a[3], b[3], c[3], d[3], u[3];
     tri_columns(V, r, s, a, b, c, d, u);
@@ -96,6 +98,22 @@ __device__ __forceinline__ void tri_prelude(const double* V, double r, double s,
     k.cw = 0.125 * wi * wj;
 }
 
+// 1/x: the hardware reciprocal estimate refined by two Newton-Raphson steps
+// r <- r + r (1 - x r), each of which squares the relative error (well below one ulp after two).
+__device__ __forceinline__ double recip(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return r;
+}
+
+__device__ __forceinline__ float recip(float x)
+{
+    float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
 // Unscaled factors at node t = xi_k: g[6] = adj(K) and lam = 0.125 w_i w_j w_k / det(8J), so
 // that the geometric factors of Eq. (7) are lam * g (Eq. 12).
 template <typename R>
@@ -108,7 +126,7 @@ __device__ __forceinline__ void tri_adj(const TriCoef& k, R t, R wk, R* g, R& la
     const R K02 = fma(R(k.n1), t, R(k.n0));
     const R K12 = fma(R(k.o1), t, R(k.o0));
     const R det = fma(fma(R(k.d2), t, R(k.d1)), t, R(k.d0));
-    lam = R(k.cw) * wk / det;
+    lam = R(k.cw) * wk * recip(det);
     g[0] = fma(K11, K22, -K12 * K12);
     g[1] = fma(K02, K12, -K01 * K22);
     g[2] = fma(K01, K12, -K02 * K11);

@@ -214,3 +214,19 @@ def batch_specs(n_mesh: int = 64, e_lo: int = 512, e_hi: int = 32768,
         nz = max(1, int(round(E / (nx * ny))))
         out.append(BatchSpec(N, nx, ny, nz, seed * 1000 + m))
     return out
+
+
+def concat_numbering(parts):
+    """Concatenate per-mesh numberings [(l2g, n_global, mask), ...] into one index space (mesh
+    after mesh, global ids offset by the preceding meshes' node counts).  Returns
+    (l2g, n_global, mask, local_offsets, global_offsets)."""
+    l2gs, masks, loff, goff = [], [], [0], [0]
+    for l2g, ng, mask in parts:
+        l2gs.append(l2g.astype(np.int64) + goff[-1])
+        masks.append(mask)
+        loff.append(loff[-1] + l2g.size)
+        goff.append(goff[-1] + ng)
+    if goff[-1] >= 2**31:
+        raise ValueError("union node count exceeds int32")
+    return (np.concatenate(l2gs).astype(np.int32), goff[-1], np.concatenate(masks),
+            np.array(loff), np.array(goff))

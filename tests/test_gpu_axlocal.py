@@ -163,3 +163,55 @@ def test_full_size_sampled(ax, N, geom):
     sub = meshgen.HexMesh(len(sample), 1, 1, m.verts[sample])
     Yref, env, _ = _oracle_ref(sub, N, X[:, sample])
     check_fp64(Y.cpu().numpy()[:, sample], Yref, env)
+
+
+def _fp16_bound(N, kappa, env, envmax):
+    """Half-precision operands (X, D, r/s/t each rounded once, plus D^T): about 6 u16 relative on
+    the envelope, the float arithmetic of the FP32 kernel, and an absolute term for values that
+    land in half's subnormal range after the per-element power-of-two scaling."""
+    u16 = 2.0**-11
+    return (6 * u16 + fp32_bound(N, kappa)) * env + 16 * (N + 1) * 2.0**-24 * envmax
+
+
+@pytest.mark.parametrize("geom", ["tri", "para", "stored"])
+def test_fp16_mfma(ax, geom):
+    import torch
+    N = 7
+    if geom == "para":
+        m, _ = meshgen.parallelepiped_hex(3, 2, 2, seed=5)
+    else:
+        m = meshgen.jittered_hex(3, 2, 2, alpha=0.15, seed=21)
+    X32 = meshgen.random_nodal(m.E, N, nrhs=2, seed=3).astype(np.float32)
+    X = X32.astype(np.float64)
+    xi, w, D = oracle.gll(N)
+    G, _, _ = oracle.geom_factors(m.verts, N, xi, w)
+    Yref = oracle.ax_local(D, G, X)
+    env = oracle.ax_envelope(D, G, X)
+    Xmax = np.abs(X).max(axis=2, keepdims=True) * np.ones_like(X)
+    envmax = oracle.ax_envelope(D, G, Xmax)
+    b = ax.Basis(N)
+    v = _dev(m.verts)
+    Xd = torch.from_numpy(X32).cuda()
+    if geom == "tri":
+        Y = ax.ax_local(Xd, v, b, ax.AX_TRILINEAR, ax.AX_FP16_ACC32)
+    elif geom == "para":
+        Y = ax.ax_local(Xd, ax.parallelepiped_factors(v), b, ax.AX_PARALLELEPIPED, ax.AX_FP16_ACC32)
+    else:
+        G32, _ = ax.geom_factors(v, b, ax.AX_FP32)
+        Y = ax.ax_local_precomputedG(Xd, G32, b, ax.AX_FP16_ACC32)
+    kappa = max_cond_j(m.verts, N)
+    d = np.abs(Y.cpu().numpy().astype(np.float64) - Yref)
+    bound = _fp16_bound(N, kappa, env, envmax)
+    assert np.all(d <= bound), float((d / bound).max())
+    # and it is genuinely half precision: clearly worse than the FP32 kernel would be
+    assert np.linalg.norm(d) / np.linalg.norm(Yref) < 1e-2
+
+
+def test_fp16_other_orders_unsupported(ax):
+    import torch
+    b = ax.Basis(5)
+    m = meshgen.jittered_hex(1, 1, 1)
+    X = torch.zeros((1, 1, 216), dtype=torch.float32, device="cuda")
+    with pytest.raises(ax.AxError) as ei:
+        ax.ax_local(X, _dev(m.verts), b, ax.AX_TRILINEAR, ax.AX_FP16_ACC32)
+    assert ei.value.code == ax.AX_ERR_UNSUPPORTED
