@@ -88,6 +88,54 @@ def cpu_baseline(mesh, N, X, budget_s=10.0):
                       f"geometric factors + AxLocal, {reps} repetitions in {el:.1f} s"}
 
 
+def cg_solves(ax, meshgen, dev, N=7, grid=(32, 32, 32), rtol=1e-10, check_with_oracle=True):
+    """-Lap u = f on the unit cube (homogeneous Dirichlet), N = 7, 32^3 trilinear hexes with
+    +-10 % jitter (seed 4), f from u = sin(pi x) sin(pi y) sin(pi z).  Time to a true relative
+    residual of 1e-10: plain FP64 CG against mixed-precision refinement with an FP32 and an FP16
+    (matrix-core) inner AxLocal."""
+    import torch
+    m = meshgen.jittered_hex(*grid, alpha=0.10, seed=4)
+    l2g, ng, mask = meshgen.global_numbering(*grid, N)
+    b = ax.Basis(N)
+    gs = ax.GatherScatter(l2g, ng, mask)
+    V = torch.from_numpy(m.verts).to(dev)
+    prob = ax.Problem(V, b, gs)
+    # right-hand side b = mask o Q^T (w det J o f) (lumped mass) at the physical nodes
+    XYZ = ax.node_coords(V, b)
+    _, gwj = ax.geom_factors(V, b, want_G=False, want_gwj=True)
+    f = 3 * np.pi**2 * torch.sin(np.pi * XYZ[:, 0]) * torch.sin(np.pi * XYZ[:, 1]) * torch.sin(np.pi * XYZ[:, 2])
+    rhs = gs.apply((gwj * f).reshape(1, -1).contiguous(), ax.GS_QT)
+    torch.cuda.synchronize()
+    res = {"workload": f"Poisson N={N} E={grid[0]}x{grid[1]}x{grid[2]} jitter 10% seed 4, global DOFs {ng}",
+           "rtol": rtol}
+    runs = [("fp64", dict(inner_prec=ax.AX_FP64)),
+            ("mixed_fp32", dict(inner_prec=ax.AX_FP32, inner_rtol=1e-5)),
+            ("mixed_fp16", dict(inner_prec=ax.AX_FP16_ACC32, inner_rtol=1e-2))]
+    sols = {}
+    for name, kw in runs:
+        x, rep = ax.cg_solve(prob, rhs, rtol=rtol, max_it=40000, max_outer=60, **kw)
+        res[name] = {k: (round(v, 4) if isinstance(v, float) and k == "seconds" else v) for k, v in rep.items()}
+        sols[name] = x
+    t64 = res["fp64"]["seconds"]
+    for name in ("mixed_fp32", "mixed_fp16"):
+        res[name]["speedup_vs_fp64"] = round(t64 / res[name]["seconds"], 3) if res[name]["seconds"] > 0 else None
+    ug = torch.zeros(ng, dtype=torch.float64, device=dev)
+    u = torch.sin(np.pi * XYZ[:, 0]) * torch.sin(np.pi * XYZ[:, 1]) * torch.sin(np.pi * XYZ[:, 2])
+    ug[gs.l2g.long()] = u.reshape(-1)
+    res["max_nodal_error_fp64"] = float((sols["fp64"][0] - ug).abs().max())
+    if check_with_oracle:
+        import oracle
+        xi, w, D = oracle.gll(N)
+        G, _, _ = oracle.geom_factors(m.verts, N, xi, w)
+        bh = rhs[0].cpu().numpy()
+        for name in sols:
+            xh = sols[name][0].cpu().numpy()
+            r = bh - oracle.apply_A(N, D, G, l2g, ng, mask, xh)
+            res[name]["oracle_rel_res"] = float(np.linalg.norm(r) / np.linalg.norm(bh))
+        del G
+    return res
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,6 +147,7 @@ def main(argv=None):
     ap.add_argument("--no-extras", action="store_true", help="only the headline kernel")
     ap.add_argument("--calib", action="store_true",
                     help="also run a plain 128 MiB device copy (counter calibration)")
+    ap.add_argument("--no-cg", action="store_true", help="skip the CG / mixed-precision solves")
     args = ap.parse_args(argv)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -215,6 +264,9 @@ def main(argv=None):
         extras["parallelepiped_fp64"] = {"GDOFs": round(dofs * args.steps / wall_p / 1e9, 3),
                                          "hbm_GBs": round(byp * E / per_p.mean() / 1e9, 1)}
         out["extras"] = extras
+
+    if not args.no_cg:
+        out["cg"] = cg_solves(ax, meshgen, dev, check_with_oracle=not args.no_cpu)
 
     if args.calib:
         a = torch.empty(16 * 2**20, dtype=torch.float64, device=dev).uniform_()

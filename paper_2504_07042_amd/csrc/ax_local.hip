@@ -34,6 +34,9 @@ ax_local_kernel(int64_t E, int nrhs, const double* __restrict__ geo, const T* __
     constexpr int VPT = (EPB * NV + BLOCK - 1) / BLOCK;          // vertex words per thread
     __shared__ T smem[S::SLOTS * 2 * FS];
     __shared__ double svert[(GEO == GEO_TRI) ? EPB * 24 : 1];
+    // (xi_k, w_k) pairs: read per node from LDS rather than held in scalar registers, which
+    // leaves the scalar file to the contraction coefficients
+    __shared__ double sxw[2 * N1];
 
     const int tid = threadIdx.x;
     const int slot = (S::SLOTS == 1) ? 0 : tid / NT;
@@ -43,6 +46,7 @@ ax_local_kernel(int64_t E, int nrhs, const double* __restrict__ geo, const T* __
     const int i = lane % N1, j = lane / N1;    // home lane: node column (i, j, :)
     const int pa = lane % N1, pb = lane / N1;  // pencil lane: (j,k) for r, (i,k) for s
     const int64_t nblk = (E + EPB - 1) / EPB;
+    if (tid < 2 * N1) sxw[tid] = (tid & 1) ? bs.w[tid >> 1] : bs.xi[tid >> 1];
 
     // Items are (element group, column) pairs walked in order; each work-group strides over the
     // element groups.  The next item's X (and vertices) are fetched into registers while the
@@ -161,12 +165,12 @@ ax_local_kernel(int64_t E, int nrhs, const double* __restrict__ geo, const T* __
             T g[6];
             if constexpr (GEO == GEO_TRI) {
                 T lam;
-                tri_adj<T>(tc, T(bs.xi[k]), T(bs.w[k]), g, lam);
+                tri_adj<T>(tc, T(sxw[2 * k]), T(sxw[2 * k + 1]), g, lam);
                 x0 *= lam;
                 x1 *= lam;
                 xx2 *= lam;
             } else if constexpr (GEO == GEO_PARA) {
-                const T wk = T(bs.w[k]);
+                const T wk = T(sxw[2 * k + 1]);
 #pragma unroll
                 for (int q = 0; q < 6; ++q) g[q] = T(h[q]) * wk;
             } else {
