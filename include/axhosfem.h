@@ -84,6 +84,19 @@ int ax_local(int64_t E, int N, int geom, const double* geo, const double* D, con
              const double* w, int nrhs, int prec, const void* X, void* Y, void* stream);
 
 /*
+ * ax_tune_set / ax_tune_get - [host] launch tuning of the AxLocal kernels for one
+ * (order N, geometry kind, precision): geom_kind AX_TRILINEAR, AX_PARALLELEPIPED or
+ * AX_STORED_G (ax_local_precomputedG); prec AX_FP64 or AX_FP32.  epb_alt 0 selects the default
+ * elements per work-group, 1 the alternative shape (see elems_per_group); grid_mult sets the
+ * persistent grid to grid_mult times the resident work-group capacity (1..64).  The setting is
+ * process-wide and applies to launches enqueued after the call; results do not depend on it.
+ * Written by the autotuner from its cache (paper_2504_07042_amd/autotune.py).
+ */
+enum { AX_STORED_G = 2 };
+int ax_tune_set(int N, int geom_kind, int prec, int epb_alt, int grid_mult);
+int ax_tune_get(int N, int geom_kind, int prec, int* epb_alt, int* grid_mult, int* elems_per_group);
+
+/*
  * ax_local_precomputedG - the same operator with the six factors streamed from memory, the
  * baseline the paper improves on (Algorithm 1 and Algorithm 4 with getFactors = memory loads).
  * G [dev] [E][6][N1^3] in order G00,G01,G02,G11,G12,G22, weights included; double for AX_FP64,

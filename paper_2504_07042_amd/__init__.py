@@ -19,7 +19,7 @@ LIBPATH = os.path.join(PKG, "libaxhosfem.so")
 
 AX_OK, AX_ERR_ARG, AX_ERR_UNSUPPORTED, AX_ERR_HIP, AX_ERR_NOMEM, AX_ERR_NOT_CONVERGED, AX_ERR_BREAKDOWN = (
     0, -1, -2, -3, -4, -5, -6)
-AX_TRILINEAR, AX_PARALLELEPIPED = 0, 1
+AX_TRILINEAR, AX_PARALLELEPIPED, AX_STORED_G = 0, 1, 2
 AX_FP64, AX_FP32, AX_FP16_ACC32 = 0, 1, 2
 GS_QT, GS_Q, GS_QQT = 0, 1, 2
 
@@ -67,6 +67,8 @@ _SIGS = {
     "ax_last_error": (ctypes.c_char_p, []),
     "ax_version": (ctypes.c_char_p, []),
     "ax_gll": (_int, [_int, _vp, _vp, _vp]),
+    "ax_tune_set": (_int, [_int, _int, _int, _int, _int]),
+    "ax_tune_get": (_int, [_int, _int, _int, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_int)]),
     "ax_local": (_int, [_i64, _int, _int, _vp, _vp, _vp, _vp, _int, _int, _vp, _vp, _vp]),
     "ax_local_precomputedG": (_int, [_i64, _int, _vp, _vp, _int, _int, _vp, _vp, _vp]),
     "ax_geom_factors": (_int, [_i64, _int, _vp, _vp, _vp, _int, _vp, _vp, _vp]),
@@ -102,6 +104,9 @@ def lib():
             f.restype = res
             f.argtypes = args
         _lib = L
+        # launch shapes picked by the autotuner for this architecture, if a cache exists
+        from . import autotune
+        autotune.load()
     return _lib
 
 

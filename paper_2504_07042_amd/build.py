@@ -23,8 +23,8 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include")]
 
-SOURCES = ["ax_common.cpp", "ax_local.hip", "ax_local_f16.hip", "ax_setup.hip", "gs.hip",
-           "cg.hip", "batched.hip"]
+SOURCES = ["ax_common.cpp", "ax_local.hip", "ax_local_f64.hip", "ax_local_f32.hip", "ax_local_f16.hip",
+           "ax_setup.hip", "gs.hip", "cg.hip", "batched.hip"]
 
 
 def _compile(src: str) -> str:

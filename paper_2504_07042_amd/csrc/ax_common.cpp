@@ -3,6 +3,7 @@
 #include <cstring>
 
 #include "ax_internal.h"
+#include "ax_kernels.h"
 
 namespace ax {
 
@@ -39,9 +40,67 @@ static void legendre(int n, double x, double& L, double& dL)
     dL = dp;
 }
 
+// Process-wide launch tuning table (filled by ax_tune_set, e.g. from the autotuner's cache).
+static TuneEntry g_tune[kMaxN1 + 1][3][2];
+static bool g_tune_init = false;
+
+static void tune_init()
+{
+    if (g_tune_init) return;
+    for (auto& a : g_tune)
+        for (auto& b : a)
+            for (auto& c : b) c = TuneEntry{0, 2};
+    g_tune_init = true;
+}
+
+TuneEntry tune_get(int N1, int geo_kind, int prec)
+{
+    tune_init();
+    if (N1 < 2 || N1 > kMaxN1 || geo_kind < 0 || geo_kind > 2 || prec < 0 || prec > 1) return TuneEntry{0, 2};
+    return g_tune[N1][geo_kind][prec];
+}
+
+static int epb_of(int N1, bool alt)
+{
+    switch (N1) {
+#define AX_E(n) \
+    case n: return alt ? Shape<n>::EPB_ALT : Shape<n>::EPB;
+        AX_E(2) AX_E(3) AX_E(4) AX_E(5) AX_E(6) AX_E(7) AX_E(8) AX_E(9) AX_E(10) AX_E(11) AX_E(12) AX_E(13)
+        AX_E(14) AX_E(15) AX_E(16)
+#undef AX_E
+    default: return 1;
+    }
+}
+
 }  // namespace ax
 
 using namespace ax;
+
+extern "C" int ax_tune_set(int N, int geom_kind, int prec, int epb_alt, int grid_mult)
+{
+    clear_error();
+    if (N < 1 || N > 15) return fail(AX_ERR_UNSUPPORTED, "order N=%d outside [1,15]", N);
+    if (geom_kind < 0 || geom_kind > 2) return fail(AX_ERR_ARG, "geometry kind %d", geom_kind);
+    if (prec != AX_FP64 && prec != AX_FP32) return fail(AX_ERR_ARG, "precision %d (FP64 or FP32)", prec);
+    if ((epb_alt != 0 && epb_alt != 1) || grid_mult < 1 || grid_mult > 64)
+        return fail(AX_ERR_ARG, "epb_alt must be 0/1 and grid_mult in [1,64]");
+    tune_init();
+    g_tune[N + 1][geom_kind][prec] = TuneEntry{epb_alt, grid_mult};
+    return AX_OK;
+}
+
+extern "C" int ax_tune_get(int N, int geom_kind, int prec, int* epb_alt, int* grid_mult, int* elems_per_group)
+{
+    clear_error();
+    if (N < 1 || N > 15) return fail(AX_ERR_UNSUPPORTED, "order N=%d outside [1,15]", N);
+    if (geom_kind < 0 || geom_kind > 2) return fail(AX_ERR_ARG, "geometry kind %d", geom_kind);
+    if (prec != AX_FP64 && prec != AX_FP32) return fail(AX_ERR_ARG, "precision %d (FP64 or FP32)", prec);
+    const TuneEntry t = tune_get(N + 1, geom_kind, prec);
+    if (epb_alt) *epb_alt = t.epb_alt;
+    if (grid_mult) *grid_mult = t.grid_mult;
+    if (elems_per_group) *elems_per_group = epb_of(N + 1, t.epb_alt != 0);
+    return AX_OK;
+}
 
 extern "C" const char* ax_last_error(void) { return g_err; }
 

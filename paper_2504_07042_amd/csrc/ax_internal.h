@@ -103,4 +103,11 @@ inline bool centro_antisymmetric(int N1, const double* D)
 
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+// Launch tuning of the AxLocal kernels per (N1, geometry kind 0/1/2, precision FP64/FP32).
+struct TuneEntry {
+    int epb_alt;    // 0: default elements per work-group, 1: the alternative shape
+    int grid_mult;  // persistent grid = grid_mult x resident capacity
+};
+TuneEntry tune_get(int N1, int geo_kind, int prec);
+
 }  // namespace ax

@@ -16,18 +16,35 @@ enum { GEO_TRI = 0, GEO_PARA = 1, GEO_STORED = 2 };
 #ifndef AX_PERSIST_MULT
 #define AX_PERSIST_MULT 2
 #endif
+// XOR-swizzled LDS layout for N1 = 8 (no padding; conflict-free for the home, r-pencil and
+// s-pencil access patterns) instead of the padded row stride.
+#ifndef AX_LDS_SWIZZLE
+#define AX_LDS_SWIZZLE 0
+#endif
 
 template <int N1>
 struct Shape {
     static constexpr int NT = N1 * N1;                        // lanes per element
     static constexpr int SJ = (N1 % 2 == 0) ? N1 + 1 : N1;    // LDS row stride (odd)
     static constexpr int SK = N1 * SJ;                        // LDS slice stride
-    static constexpr int FS = N1 * SK;                        // LDS words per field
+    static constexpr bool SWZ = AX_LDS_SWIZZLE && N1 == 8;
+    static constexpr int FS = SWZ ? 512 : N1 * SK;            // LDS words per field
+    // LDS word of node (i, j, k) within one field
+    __device__ static __forceinline__ int pos(int i, int j, int k)
+    {
+        if constexpr (SWZ)
+            return 64 * k + 8 * (j ^ (k & 1)) + (i ^ ((j >> 1) << 1));
+        else
+            return k * SK + j * SJ + i;
+    }
     static constexpr int NP = N1 * N1 * N1;                   // nodes per element
     // elements per work-group: fill (nearly) whole waves while keeping LDS modest
     static constexpr int EPB = N1 == 2 ? 16 : N1 == 3 ? 7 : N1 == 4 ? 4 : N1 == 5 ? 5
                              : N1 == 6 ? 7 : N1 == 7 ? 5 : N1 == 9 ? 3 : N1 == 10 ? 3
                              : N1 == 11 ? 2 : 1;
+    // the alternative elements-per-group the tuner may pick (same as EPB where there is none)
+    static constexpr int EPB_ALT = N1 == 2 ? 32 : N1 == 3 ? 14 : N1 == 4 ? 8 : N1 == 5 ? 10
+                                 : N1 == 6 ? 14 : N1 == 7 ? 10 : N1 == 8 ? 2 : N1 <= 11 ? 1 : EPB;
     static constexpr int BLOCK = ((EPB * NT + 63) / 64) * 64;
     static constexpr int SLOTS = (BLOCK + NT - 1) / NT;
     // waves per SIMD the register allocation must allow (latency hiding for the X/Y streams)

@@ -1,0 +1,17 @@
+// AxLocal kernels instantiated for double arithmetic.
+#include "ax_local_impl.h"
+
+namespace ax {
+
+int axl_dispatch_f64(int geo_kind, int N, int64_t E, int nrhs, const double* geo, const double* Gs,
+                      const double* X, double* Y, const double* D, const double* xi, const double* w,
+                      hipStream_t st, const int32_t* l2g, int64_t ldg)
+{
+    switch (geo_kind) {
+    case GEO_TRI: return dispatch<GEO_TRI, double>(N, E, nrhs, geo, Gs, X, Y, D, xi, w, st, l2g, ldg);
+    case GEO_PARA: return dispatch<GEO_PARA, double>(N, E, nrhs, geo, Gs, X, Y, D, xi, w, st, l2g, ldg);
+    default: return dispatch<GEO_STORED, double>(N, E, nrhs, geo, Gs, X, Y, D, xi, w, st, l2g, ldg);
+    }
+}
+
+}  // namespace ax

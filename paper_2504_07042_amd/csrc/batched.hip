@@ -73,7 +73,7 @@ template <int N1, typename T>
 __device__ void batched_item(const BMesh& m, int64_t eb, int nrhs, const Basis<T>& bs, char* lds)
 {
     using S = BShape<N1>;
-    constexpr int NT = S::NT, EPB = S::EPB, SJ = S::SJ, SK = S::SK, FS = S::FS, NP = S::NP;
+    constexpr int NT = S::NT, EPB = S::EPB, FS = S::FS, NP = S::NP;
     T* smem = reinterpret_cast<T*>(lds);
     double* svert = reinterpret_cast<double*>(lds + (size_t)EPB * 2 * FS * sizeof(T));
     const int tid = threadIdx.x;
@@ -106,7 +106,7 @@ __device__ void batched_item(const BMesh& m, int64_t eb, int nrhs, const Basis<T
         for (int k = 0; k < N1; ++k) xr[k] = active ? X[base + i + j * N1 + k * NT] : T(0);
         if (inslot) {
 #pragma unroll
-            for (int k = 0; k < N1; ++k) A[k * SK + j * SJ + i] = xr[k];
+            for (int k = 0; k < N1; ++k) A[Shape<N1>::pos(i, j, k)] = xr[k];
         }
         contract<N1, false, true>(bs, xr, x2);
         __syncthreads();
@@ -114,25 +114,25 @@ __device__ void batched_item(const BMesh& m, int64_t eb, int nrhs, const Basis<T
         if (inslot) {
             T p[N1], o[N1];
 #pragma unroll
-            for (int n = 0; n < N1; ++n) p[n] = A[pb * SK + pa * SJ + n];
+            for (int n = 0; n < N1; ++n) p[n] = A[Shape<N1>::pos(n, pa, pb)];
             contract<N1, false, true>(bs, p, o);
 #pragma unroll
-            for (int a = 0; a < N1; ++a) B[pb * SK + pa * SJ + a] = o[a];
+            for (int a = 0; a < N1; ++a) B[Shape<N1>::pos(a, pa, pb)] = o[a];
 #pragma unroll
-            for (int n = 0; n < N1; ++n) p[n] = A[pb * SK + n * SJ + pa];
+            for (int n = 0; n < N1; ++n) p[n] = A[Shape<N1>::pos(pa, n, pb)];
             contract<N1, false, true>(bs, p, o1);
         }
         __syncthreads();
         if (inslot) {
 #pragma unroll
-            for (int a = 0; a < N1; ++a) A[pb * SK + a * SJ + pa] = o1[a];
+            for (int a = 0; a < N1; ++a) A[Shape<N1>::pos(pa, a, pb)] = o1[a];
         }
         __syncthreads();
         T tt[N1];
         if (inslot) {
 #pragma unroll
             for (int k = 0; k < N1; ++k) {
-                const int l = k * SK + j * SJ + i;
+                const int l = Shape<N1>::pos(i, j, k);
                 T x0 = B[l], x1 = A[l], xx2 = x2[k];
                 T g[6], lam;
                 tri_adj<T>(tc, T(bs.xi[k]), T(bs.w[k]), g, lam);
@@ -153,23 +153,23 @@ __device__ void batched_item(const BMesh& m, int64_t eb, int nrhs, const Basis<T
         if (inslot) {
             T p[N1], o[N1];
 #pragma unroll
-            for (int n = 0; n < N1; ++n) p[n] = B[pb * SK + pa * SJ + n];
+            for (int n = 0; n < N1; ++n) p[n] = B[Shape<N1>::pos(n, pa, pb)];
             contract<N1, true, true>(bs, p, o);
 #pragma unroll
-            for (int a = 0; a < N1; ++a) B[pb * SK + pa * SJ + a] = o[a];
+            for (int a = 0; a < N1; ++a) B[Shape<N1>::pos(a, pa, pb)] = o[a];
 #pragma unroll
-            for (int n = 0; n < N1; ++n) p[n] = A[pb * SK + n * SJ + pa];
+            for (int n = 0; n < N1; ++n) p[n] = A[Shape<N1>::pos(pa, n, pb)];
             contract<N1, true, true>(bs, p, o1);
         }
         __syncthreads();
         if (inslot) {
 #pragma unroll
-            for (int a = 0; a < N1; ++a) B[pb * SK + a * SJ + pa] += o1[a];
+            for (int a = 0; a < N1; ++a) B[Shape<N1>::pos(pa, a, pb)] += o1[a];
         }
         __syncthreads();
         if (active) {
 #pragma unroll
-            for (int k = 0; k < N1; ++k) Y[base + i + j * N1 + k * NT] = B[k * SK + j * SJ + i] + y2[k];
+            for (int k = 0; k < N1; ++k) Y[base + i + j * N1 + k * NT] = B[Shape<N1>::pos(i, j, k)] + y2[k];
         }
         __syncthreads();
     }

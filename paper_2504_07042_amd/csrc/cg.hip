@@ -19,6 +19,7 @@ namespace ax {
 int gs_apply(int64_t n_local, int64_t n_global, const int32_t* l2g, const int64_t* gptr,
              const int32_t* gidx, const uint8_t* mask, int mode, int nrhs, int dtype, const void* in,
              void* out, hipStream_t st);
+int ax_local_gather(const ax_problem& p, int nrhs, int prec, const void* xg, int64_t ldg, void* Y, hipStream_t st);
 
 constexpr int kRedBlocks = 512;  // partial sums per dot product and column
 constexpr int kRedThreads = 256;
@@ -109,20 +110,65 @@ cg_scalar_kernel(const double* __restrict__ partials, CgScal* __restrict__ sc, i
     }
 }
 
-// x += alpha p; r -= alpha Ap
+// Ap[g] = mask ? 0 : sum of the local copies (ascending local id) and, fused, the partial sums of
+// p . Ap over the same fixed grid as dot_partial_kernel.
+template <typename T>
+__global__ void __launch_bounds__(kRedThreads)
+qt_dot_kernel(int64_t n_local, int64_t n_global, const int64_t* __restrict__ gptr,
+              const int32_t* __restrict__ gidx, const uint8_t* __restrict__ mask, const T* __restrict__ in,
+              const T* __restrict__ pdir, T* __restrict__ out, double* __restrict__ partials)
+{
+    const int c = blockIdx.y;
+    const T* x = in + (int64_t)c * n_local;
+    const T* pd = pdir + (int64_t)c * n_global;
+    T* o = out + (int64_t)c * n_global;
+    double acc = 0.0;
+    for (int64_t g = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; g < n_global;
+         g += (int64_t)gridDim.x * kRedThreads) {
+        T sum = T(0);
+        for (int64_t q = gptr[g]; q < gptr[g + 1]; ++q) sum += x[gidx[q]];
+        if (mask && mask[g]) sum = T(0);
+        o[g] = sum;
+        acc = fma((double)pd[g], (double)sum, acc);
+    }
+    __shared__ double red[kRedThreads];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = kRedThreads / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[c * kRedBlocks + blockIdx.x] = red[0];
+}
+
+// x += alpha p; r -= alpha Ap; partial sums of r . r (fixed grid)
 template <typename TX, typename T>
-__global__ void __launch_bounds__(256)
-cg_update_kernel(TX* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
-                 const T* __restrict__ Ap, const CgScal* __restrict__ sc, int64_t n)
+__global__ void __launch_bounds__(kRedThreads)
+update_dot_kernel(TX* __restrict__ x, T* __restrict__ r, const T* __restrict__ p, const T* __restrict__ Ap,
+                  const CgScal* __restrict__ sc, int64_t n, double* __restrict__ partials)
 {
     const int c = blockIdx.y;
     const double al = sc[c].alpha;
-    if (al == 0.0) return;
     const int64_t o = (int64_t)c * n;
-    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (int64_t)gridDim.x * 256) {
-        x[o + q] = (TX)((double)x[o + q] + al * (double)p[o + q]);
-        r[o + q] = (T)((double)r[o + q] - al * (double)Ap[o + q]);
+    double acc = 0.0;
+    for (int64_t q = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * kRedThreads) {
+        T rv = r[o + q];
+        if (al != 0.0) {
+            x[o + q] = (TX)((double)x[o + q] + al * (double)p[o + q]);
+            rv = (T)((double)rv - al * (double)Ap[o + q]);
+            r[o + q] = rv;
+        }
+        acc = fma((double)rv, (double)rv, acc);
     }
+    __shared__ double red[kRedThreads];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = kRedThreads / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[c * kRedBlocks + blockIdx.x] = red[0];
 }
 
 // p = r + beta p
@@ -266,19 +312,32 @@ struct Operator {
     const void* ws32 = nullptr;
 };
 
+// Local result yl = AxLocal(Q x).  With AX_CG_GATHER the gather Q x of one mesh is fused into
+// the AxLocal load (FP64/FP32, GLL D); measured on MI355X the separate, fully occupied gather
+// kernel followed by the streaming AxLocal load is faster, so the fused form is off by default.
+#ifndef AX_CG_GATHER
+#define AX_CG_GATHER 0
+#endif
+template <typename T>
+static int apply_local(const Operator& op, int nrhs, int prec, const T* x, T* xl, T* yl, hipStream_t st)
+{
+    const int dt = sizeof(T) == 8 ? AX_FP64 : AX_FP32;
+    if (AX_CG_GATHER && op.p && prec != AX_FP16_ACC32 && centro_antisymmetric(op.p->N + 1, op.p->D))
+        return ax_local_gather(*op.p, nrhs, prec, x, op.n_global, yl, st);
+    AX_TRY(gs_apply(op.n_local, op.n_global, op.l2g, op.gptr, op.gidx, nullptr, GS_Q, nrhs, dt, x, xl, st));
+    if (op.p) {
+        const ax_problem& pb = *op.p;
+        return ax_local(pb.E, pb.N, pb.geom, pb.geo, pb.D, pb.xi, pb.w, nrhs, prec, xl, yl, st);
+    }
+    if (sizeof(T) == 8) return ax_local_batched(op.plan64, op.ws64, st);
+    return ax_local_batched(op.plan32, op.ws32, st);
+}
+
 template <typename T>
 static int apply_op(const Operator& op, int nrhs, int prec, const T* x, T* y, T* xl, T* yl, hipStream_t st)
 {
     const int dt = sizeof(T) == 8 ? AX_FP64 : AX_FP32;
-    AX_TRY(gs_apply(op.n_local, op.n_global, op.l2g, op.gptr, op.gidx, nullptr, GS_Q, nrhs, dt, x, xl, st));
-    if (op.p) {
-        const ax_problem& pb = *op.p;
-        AX_TRY(ax_local(pb.E, pb.N, pb.geom, pb.geo, pb.D, pb.xi, pb.w, nrhs, prec, xl, yl, st));
-    } else if (sizeof(T) == 8) {
-        AX_TRY(ax_local_batched(op.plan64, op.ws64, st));
-    } else {
-        AX_TRY(ax_local_batched(op.plan32, op.ws32, st));
-    }
+    AX_TRY(apply_local<T>(op, nrhs, prec, x, xl, yl, st));
     AX_TRY(gs_apply(op.n_local, op.n_global, op.l2g, op.gptr, op.gidx, op.mask, GS_QT, nrhs, dt, yl, y, st));
     return AX_OK;
 }
@@ -314,11 +373,12 @@ static int cg_block(const Operator& op, int nrhs, int prec, TX* x, T* r, T* p, T
     const int64_t ng = op.n_global;
     const dim3 g(vgrid(ng), nrhs);
     for (int q = 0; q < count; ++q) {
-        AX_TRY(apply_op<T>(op, nrhs, prec, p, Ap, pl, wl, st));
-        AX_TRY(dot(p, Ap, ng, nrhs, partials, st));
+        AX_TRY(apply_local<T>(op, nrhs, prec, p, pl, wl, st));
+        hipLaunchKernelGGL(qt_dot_kernel<T>, dim3(kRedBlocks, nrhs), dim3(kRedThreads), 0, st, op.n_local, ng,
+                           op.gptr, op.gidx, op.mask, wl, p, Ap, partials);
         AX_TRY(scal(partials, sc, 1, nrhs, st));
-        hipLaunchKernelGGL((cg_update_kernel<TX, T>), g, dim3(256), 0, st, x, r, p, Ap, sc, ng);
-        AX_TRY(dot(r, r, ng, nrhs, partials, st));
+        hipLaunchKernelGGL((update_dot_kernel<TX, T>), dim3(kRedBlocks, nrhs), dim3(kRedThreads), 0, st, x, r, p,
+                           Ap, sc, ng, partials);
         AX_TRY(scal(partials, sc, 2, nrhs, st));
         hipLaunchKernelGGL(cg_dir_kernel<T>, g, dim3(256), 0, st, p, r, sc, ng);
     }

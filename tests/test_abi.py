@@ -99,3 +99,19 @@ def test_gs_validation_and_csr(ax):
     for g in range(ng):
         loc = gidx[gptr[g]:gptr[g + 1]]
         assert np.array_equal(loc, np.nonzero(l2g == g)[0])
+
+
+def test_tuning_roundtrip(ax):
+    from paper_2504_07042_amd import autotune
+    before = autotune.tune_get(7, ax.AX_TRILINEAR, ax.AX_FP64)
+    autotune.tune_set(7, ax.AX_TRILINEAR, ax.AX_FP64, 1, 4)
+    t = autotune.tune_get(7, ax.AX_TRILINEAR, ax.AX_FP64)
+    assert t["epb_alt"] == 1 and t["grid_mult"] == 4 and t["elems_per_group"] == 2
+    autotune.tune_set(7, ax.AX_TRILINEAR, ax.AX_FP64, before["epb_alt"], before["grid_mult"])
+    assert autotune.tune_get(7, ax.AX_TRILINEAR, ax.AX_FP64) == before
+    L = ax.lib()
+    assert L.ax_tune_set(7, 0, 0, 2, 1) == ax.AX_ERR_ARG
+    assert L.ax_tune_set(7, 0, 0, 0, 0) == ax.AX_ERR_ARG
+    assert L.ax_tune_set(16, 0, 0, 0, 1) == ax.AX_ERR_UNSUPPORTED
+    assert L.ax_tune_set(7, 3, 0, 0, 1) == ax.AX_ERR_ARG
+    assert L.ax_tune_set(7, 0, ax.AX_FP16_ACC32, 0, 1) == ax.AX_ERR_ARG
