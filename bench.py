@@ -136,6 +136,108 @@ def cg_solves(ax, meshgen, dev, N=7, grid=(32, 32, 32), rtol=1e-10, check_with_o
     return res
 
 
+def roofline_gdofs(N, geom, fpsize=8, peak_tf=PEAK_FP64_TFS, peak_gbs=PEAK_HBM_GBS):
+    """Time-based roofline (Sec. 3.4) in local DOFs per second: max(T_cmp, T_mem) per element."""
+    f_ax, f_geo = flops_per_element(N, geom)
+    t_cmp = (f_ax + f_geo) / (peak_tf * 1e12)
+    t_mem = bytes_per_element(N, geom, fpsize=fpsize) / (peak_gbs * 1e9)
+    return (N + 1) ** 3 / max(t_cmp, t_mem) / 1e9, ("alu" if t_cmp >= t_mem else "hbm")
+
+
+def order_sweep(ax, meshgen, dev, orders=(3, 5, 7, 9, 11, 15), steps=20, warmup=3):
+    """Trilinear order sweep at E (N+1)^3 ~ 2^24 local nodes, +-15 % jitter, seed N: on-the-fly vs
+    stored factors, FP64 and FP32, with each kernel's time-based roofline."""
+    import torch
+    rows = []
+    for N in orders:
+        grid = meshgen.grid_for_nodes(N)
+        m = meshgen.jittered_hex(*grid, alpha=0.15, seed=N)
+        b = ax.Basis(N)
+        V = torch.from_numpy(m.verts).to(dev)
+        X64 = [torch.from_numpy(meshgen.random_nodal(m.E, N, seed=N)).to(dev) for _ in range(2)]
+        row = {"N": N, "E": m.E, "grid": list(grid), "local_dofs": m.E * (N + 1) ** 3}
+        for pname, prec, T in (("fp64", ax.AX_FP64, torch.float64), ("fp32", ax.AX_FP32, torch.float32)):
+            X = [x.to(T) for x in X64]
+            Y = [torch.empty_like(x) for x in X]
+            fpsize = 8 if T == torch.float64 else 4
+            peak = PEAK_FP64_TFS if T == torch.float64 else PEAK_FP32_TFS
+            _, per = time_steps(lambda q: ax.ax_local(X[q], V, b, ax.AX_TRILINEAR, prec, out=Y[q]), steps, warmup, 2)
+            g_fly = row["local_dofs"] / per.mean() / 1e9
+            G, _ = ax.geom_factors(V, b, prec)
+            _, per_g = time_steps(lambda q: ax.ax_local_precomputedG(X[q], G, b, prec, out=Y[q]), steps, warmup, 2)
+            del G
+            g_st = row["local_dofs"] / per_g.mean() / 1e9
+            r_fly, bound_fly = roofline_gdofs(N, "tri", fpsize, peak)
+            r_st, bound_st = roofline_gdofs(N, "stored", fpsize, peak)
+            row[pname] = {"on_the_fly_GDOFs": round(g_fly, 1), "R_eff_GDOFs": round(r_fly, 1), "bound": bound_fly,
+                          "pct_of_R_eff": round(g_fly / r_fly, 3), "stored_GDOFs": round(g_st, 1),
+                          "R_orig_GDOFs": round(r_st, 1), "pct_of_R_orig": round(g_st / r_st, 3),
+                          "speedup_vs_stored": round(g_fly / g_st, 2)}
+        rows.append(row)
+        del X64, V
+        torch.cuda.empty_cache()
+    return rows
+
+
+def batched_run(ax, meshgen, dev, nrhs=8, steps=5, warmup=2, check_with_oracle=True):
+    """64 independent trilinear meshes (E ~ U[512, 32768] rounded to a near-cubic grid, N drawn
+    from {3, 5, 7, 9}, seed 1, +-10 % jitter) with 8 columns each: one persistent launch (replayed
+    from a HIP graph) against one ax_local launch per mesh, FP64 and FP32."""
+    import torch
+    specs = meshgen.batch_specs(64, 512, 32768, (3, 5, 7, 9), seed=1)
+    meshes, verts_h = [], []
+    for sp in specs:
+        m = meshgen.jittered_hex(sp.nx, sp.ny, sp.nz, alpha=0.10, seed=sp.seed)
+        verts_h.append(m.verts)
+        meshes.append((torch.from_numpy(m.verts).to(dev), ax.Basis(sp.N)))
+    dofs = sum(v.shape[0] * (sp.N + 1) ** 3 for v, sp in zip(verts_h, specs)) * nrhs
+    res = {"workload": f"64 meshes, N in {{3,5,7,9}}, E in [{min(v.shape[0] for v in verts_h)}, "
+                       f"{max(v.shape[0] for v in verts_h)}], {nrhs} columns, {dofs} local DOFs", "local_dofs": dofs}
+    for pname, prec, T in (("fp64", ax.AX_FP64, torch.float64), ("fp32", ax.AX_FP32, torch.float32)):
+        X = [meshgen.random_nodal_device(v.shape[0], sp.N, nrhs, seed=q, device=dev, dtype=T)
+             for q, (v, sp) in enumerate(zip(verts_h, specs))]
+        Y = [torch.empty_like(x) for x in X]
+        bat = ax.BatchedAxLocal(meshes, X, Y, prec)
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(s):
+            bat.launch(stream=s)
+            with torch.cuda.graph(g, stream=s):
+                bat.launch(stream=s)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        wall_b, per_b = time_steps(lambda q: g.replay(), steps, warmup, 1)
+        Yb = [y.clone() for y in Y] if pname == "fp64" and check_with_oracle else None
+
+        def per_mesh(q):
+            for (v, b), x, y in zip(meshes, X, Y):
+                ax.ax_local(x, v, b, ax.AX_TRILINEAR, prec, out=y)
+
+        wall_l, per_l = time_steps(per_mesh, steps, warmup, 1)
+        res[pname] = {"batched_graph_GDOFs": round(dofs / per_b.mean() / 1e9, 1),
+                      "per_mesh_launches_GDOFs": round(dofs / per_l.mean() / 1e9, 1),
+                      "batched_ms": round(per_b.mean() * 1e3, 3), "per_mesh_ms": round(per_l.mean() * 1e3, 3)}
+        if Yb is not None:
+            import oracle
+            worst = 0.0
+            rng = np.random.default_rng(0)
+            for q in rng.choice(len(specs), 4, replace=False):
+                N = specs[q].N
+                sel = np.sort(rng.choice(verts_h[q].shape[0], 16, replace=False))
+                xi, w, D = oracle.gll(N)
+                G, _, _ = oracle.geom_factors(verts_h[q][sel], N, xi, w)
+                xs = X[q][:, sel].cpu().numpy()
+                yr = oracle.ax_local(D, G, xs)
+                env = oracle.ax_envelope(D, G, xs)
+                d = np.abs(Yb[q][:, sel].cpu().numpy() - yr) / np.maximum(env, 1e-300)
+                worst = max(worst, float(d.max()))
+            res[pname]["oracle_sampled_max_err_over_env"] = worst
+        del X, Y, bat, g
+        torch.cuda.empty_cache()
+    return res
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,6 +250,10 @@ def main(argv=None):
     ap.add_argument("--calib", action="store_true",
                     help="also run a plain 128 MiB device copy (counter calibration)")
     ap.add_argument("--no-cg", action="store_true", help="skip the CG / mixed-precision solves")
+    ap.add_argument("--batched", action="store_true",
+                    help="also run the batched workload: 64 meshes, E~U[512,32768], N in {3,5,7,9}, 8 columns")
+    ap.add_argument("--sweep", action="store_true",
+                    help="also run the order sweep N in {3,5,7,9,11,15} at ~2^24 local nodes")
     args = ap.parse_args(argv)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -267,6 +373,13 @@ def main(argv=None):
 
     if not args.no_cg:
         out["cg"] = cg_solves(ax, meshgen, dev, check_with_oracle=not args.no_cpu)
+
+    if args.batched:
+        out["batched"] = batched_run(ax, meshgen, dev, steps=max(5, args.steps // 10), warmup=2,
+                                     check_with_oracle=not args.no_cpu)
+
+    if args.sweep:
+        out["order_sweep"] = order_sweep(ax, meshgen, dev, steps=max(10, args.steps // 2), warmup=3)
 
     if args.calib:
         a = torch.empty(16 * 2**20, dtype=torch.float64, device=dev).uniform_()

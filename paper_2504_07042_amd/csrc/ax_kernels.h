@@ -13,6 +13,9 @@ enum { GEO_TRI = 0, GEO_PARA = 1, GEO_STORED = 2 };
 #ifndef AX_MINW_SMALL
 #define AX_MINW_SMALL 4
 #endif
+#ifndef AX_MINW_OTHER
+#define AX_MINW_OTHER 2
+#endif
 #ifndef AX_PERSIST_MULT
 #define AX_PERSIST_MULT 2
 #endif
@@ -48,7 +51,7 @@ struct Shape {
     static constexpr int BLOCK = ((EPB * NT + 63) / 64) * 64;
     static constexpr int SLOTS = (BLOCK + NT - 1) / NT;
     // waves per SIMD the register allocation must allow (latency hiding for the X/Y streams)
-    static constexpr int MINW = N1 <= 8 ? AX_MINW_SMALL : 2;
+    static constexpr int MINW = N1 == 8 ? AX_MINW_SMALL : AX_MINW_OTHER;
 };
 
 // out[a] = sum_n D[a][n] in[n]   (TRANS: out[a] = sum_n D[n][a] in[n])

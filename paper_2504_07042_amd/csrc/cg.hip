@@ -21,7 +21,7 @@ int gs_apply(int64_t n_local, int64_t n_global, const int32_t* l2g, const int64_
              void* out, hipStream_t st);
 int ax_local_gather(const ax_problem& p, int nrhs, int prec, const void* xg, int64_t ldg, void* Y, hipStream_t st);
 
-constexpr int kRedBlocks = 512;  // partial sums per dot product and column
+constexpr int kRedBlocks = 4096;  // partial sums per dot product and column (fixed grid)
 constexpr int kRedThreads = 256;
 constexpr int kPoll = 8;         // iterations between host convergence checks
 

@@ -230,3 +230,14 @@ def concat_numbering(parts):
         raise ValueError("union node count exceeds int32")
     return (np.concatenate(l2gs).astype(np.int32), goff[-1], np.concatenate(masks),
             np.array(loff), np.array(goff))
+
+
+def random_nodal_device(E: int, N: int, nrhs: int = 1, seed: int = 0, device="cuda", dtype=None):
+    """X ~ U[-1, 1] per local node generated on the device by torch's seeded generator (for
+    workloads too large to draw on the host); shape ``[nrhs][E][N1**3]``."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    dtype = dtype or torch.float64
+    x = torch.rand((nrhs, E, (N + 1) ** 3), generator=g, device=device, dtype=dtype)
+    return x.mul_(2.0).sub_(1.0)
