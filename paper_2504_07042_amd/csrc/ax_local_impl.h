@@ -24,6 +24,12 @@
 #include "ax_kernels.h"
 #include "geom.h"
 
+// Issue point of the next item's loads: 0 = before the first contraction (longest overlap),
+// 1 = after the pointwise stage (shorter overlap, fewer live registers at the pointwise peak).
+#ifndef AX_PREFETCH_LATE
+#define AX_PREFETCH_LATE 0
+#endif
+
 namespace ax {
 
 // Work-group shape for EPBX elements of order N1 - 1.
@@ -140,17 +146,20 @@ ax_local_kernel(int64_t E, int nrhs, const double* __restrict__ geo, const T* __
         const int64_t eb_n = last_col ? eb + gridDim.x : eb;
         const int c_n = last_col ? 0 : c + 1;
         T xn[N1];
-        load_x(eb_n, c_n, xn);
-        if constexpr (GEO == GEO_TRI) {
-            if (last_col) {
+        auto prefetch = [&]() {
+            load_x(eb_n, c_n, xn);
+            if constexpr (GEO == GEO_TRI) {
+                if (last_col) {
 #pragma unroll
-                for (int q = 0; q < VPT; ++q) {
-                    const int idx = tid + q * BLOCK;
-                    const int64_t off = eb_n * EPB * 24 + idx;
-                    vr[q] = (idx < EPB * 24 && eb_n < nblk && off < E * 24) ? geo[off] : 0.0;
+                    for (int q = 0; q < VPT; ++q) {
+                        const int idx = tid + q * BLOCK;
+                        const int64_t off = eb_n * EPB * 24 + idx;
+                        vr[q] = (idx < EPB * 24 && eb_n < nblk && off < E * 24) ? geo[off] : 0.0;
+                    }
                 }
             }
-        }
+        };
+        if constexpr (AX_PREFETCH_LATE == 0) prefetch();
         T x2[N1];
         contract<N1, false, EO>(bs, xr, x2);  // x2 = D_t x
         __syncthreads();
@@ -207,6 +216,7 @@ ax_local_kernel(int64_t E, int nrhs, const double* __restrict__ geo, const T* __
         }
         T y2[N1];
         contract<N1, true, EO>(bs, tt, y2);  // D_t^T t
+        if constexpr (AX_PREFETCH_LATE != 0) prefetch();
         __syncthreads();
         // P4: D_r^T r in place on the r-pencils; D_s^T s into registers
         {

@@ -112,9 +112,9 @@ cg_scalar_kernel(const double* __restrict__ partials, CgScal* __restrict__ sc, i
 
 // Ap[g] = mask ? 0 : sum of the local copies (ascending local id) and, fused, the partial sums of
 // p . Ap over the same fixed grid as dot_partial_kernel.
-template <typename T>
+template <typename T, typename IP>
 __global__ void __launch_bounds__(kRedThreads)
-qt_dot_kernel(int64_t n_local, int64_t n_global, const int64_t* __restrict__ gptr,
+qt_dot_kernel(int64_t n_local, int64_t n_global, const IP* __restrict__ gptr,
               const int32_t* __restrict__ gidx, const uint8_t* __restrict__ mask, const T* __restrict__ in,
               const T* __restrict__ pdir, T* __restrict__ out, double* __restrict__ partials)
 {
@@ -126,7 +126,8 @@ qt_dot_kernel(int64_t n_local, int64_t n_global, const int64_t* __restrict__ gpt
     for (int64_t g = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; g < n_global;
          g += (int64_t)gridDim.x * kRedThreads) {
         T sum = T(0);
-        for (int64_t q = gptr[g]; q < gptr[g + 1]; ++q) sum += x[gidx[q]];
+        const int64_t q0 = gptr[g], q1 = gptr[g + 1];
+        for (int64_t q = q0; q < q1; ++q) sum += x[gidx[q]];
         if (mask && mask[g]) sum = T(0);
         o[g] = sum;
         acc = fma((double)pd[g], (double)sum, acc);
@@ -227,6 +228,12 @@ copy_kernel(T* __restrict__ dst, const T* __restrict__ src, int64_t n)
         dst[q] = src[q];
 }
 
+__global__ void __launch_bounds__(256) narrow_ptr_kernel(int32_t* __restrict__ dst, const int64_t* __restrict__ src, int64_t n)
+{
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (int64_t)gridDim.x * 256)
+        dst[q] = (int32_t)src[q];
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) zero_kernel(T* __restrict__ dst, int64_t n)
 {
@@ -270,6 +277,7 @@ struct CgWork {
     float *b32, *r32, *p32, *Ap32, *d32; // inner global vectors
     float *pl32, *wl32;            // inner local vectors
     double* partials;              // [nrhs][kRedBlocks]
+    int32_t* gptr32;               // [n_global + 1]
     CgScal *sc, *sc_in;            // outer / inner scalar state [nrhs]
 };
 
@@ -292,6 +300,7 @@ static void carve(Carver& cv, int64_t nl, int64_t ng, int nrhs, bool mixed, CgWo
         w.b32 = w.r32 = w.p32 = w.Ap32 = w.d32 = w.pl32 = w.wl32 = nullptr;
     }
     w.partials = cv.take<double>((size_t)kRedBlocks * nrhs);
+    w.gptr32 = cv.take<int32_t>(ng + 1);
     w.sc = cv.take<CgScal>(nrhs);
     w.sc_in = cv.take<CgScal>(nrhs);
 }
@@ -303,6 +312,7 @@ struct Operator {
     int64_t n_local = 0, n_global = 0;
     const int32_t* l2g = nullptr;
     const int64_t* gptr = nullptr;
+    const int32_t* gptr32 = nullptr;  // the same offsets narrowed to 32 bits (n_local < 2^31)
     const int32_t* gidx = nullptr;
     const uint8_t* mask = nullptr;
     const ax_problem* p = nullptr;  // single mesh
@@ -374,8 +384,8 @@ static int cg_block(const Operator& op, int nrhs, int prec, TX* x, T* r, T* p, T
     const dim3 g(vgrid(ng), nrhs);
     for (int q = 0; q < count; ++q) {
         AX_TRY(apply_local<T>(op, nrhs, prec, p, pl, wl, st));
-        hipLaunchKernelGGL(qt_dot_kernel<T>, dim3(kRedBlocks, nrhs), dim3(kRedThreads), 0, st, op.n_local, ng,
-                           op.gptr, op.gidx, op.mask, wl, p, Ap, partials);
+        hipLaunchKernelGGL((qt_dot_kernel<T, int32_t>), dim3(kRedBlocks, nrhs), dim3(kRedThreads), 0, st,
+                           op.n_local, ng, op.gptr32, op.gidx, op.mask, wl, p, Ap, partials);
         AX_TRY(scal(partials, sc, 1, nrhs, st));
         hipLaunchKernelGGL((update_dot_kernel<TX, T>), dim3(kRedBlocks, nrhs), dim3(kRedThreads), 0, st, x, r, p,
                            Ap, sc, ng, partials);
@@ -532,8 +542,12 @@ static int solve(const Operator& op, int64_t nl, int nrhs, const double* b, doub
             hipLaunchKernelGGL(scale_to_f32_kernel, g, dim3(256), 0, st, w.b32, w.r, w.sc, ng);
             hipLaunchKernelGGL(zero_kernel<float>, dim3(vgrid(ng * nrhs)), dim3(256), 0, st, w.d32, ng * nrhs);
             int it = 0;
+            // the inner solve needs to reduce the residual by at most rtol / |r| (with a safety
+            // factor of 2): the last refinement step is then only as long as it has to be
+            const double need = 0.5 * o->rtol / (worst > 0.0 ? worst : 1.0);
+            const double itol = need > o->inner_rtol ? need : o->inner_rtol;
             const int s = cg_core<float, float>(op, nrhs, o->inner_prec, w.b32, w.d32, w.r32, w.p32, w.Ap32,
-                                                w.pl32, w.wl32, w.partials, w.sc_in, o->inner_rtol, o->max_it,
+                                                w.pl32, w.wl32, w.partials, w.sc_in, itol, o->max_it,
                                                 true, graphs ? &gc32 : nullptr, it, st);
             // an inner solve that stops on its iteration limit or breaks down still yields a
             // useful correction; only launch errors abort
@@ -622,6 +636,9 @@ extern "C" int cg_solve(const ax_problem* p, int nrhs, const double* b, double* 
     op.gidx = p->gidx;
     op.mask = p->mask;
     op.p = p;
+    hipLaunchKernelGGL(narrow_ptr_kernel, dim3(vgrid(p->n_global + 1)), dim3(256), 0, st, w.gptr32, p->gptr,
+                       p->n_global + 1);
+    op.gptr32 = w.gptr32;
     const int status = solve(op, nl, nrhs, b, x, o, rep, w, st);
     if (status != AX_OK && status != AX_ERR_NOT_CONVERGED && status != AX_ERR_BREAKDOWN) {
         (void)hipStreamSynchronize(st);
@@ -731,6 +748,8 @@ extern "C" int cg_solve_batched(int n_mesh, const ax_problem* meshes, int64_t n_
     op.ws64 = ws64;
     op.plan32 = &plan32;
     op.ws32 = ws32;
+    hipLaunchKernelGGL(narrow_ptr_kernel, dim3(vgrid(n_global + 1)), dim3(256), 0, st, w.gptr32, gptr, n_global + 1);
+    op.gptr32 = w.gptr32;
     const int status = solve(op, nl, nrhs, b, x, o, rep, w, st);
     if (status != AX_OK && status != AX_ERR_NOT_CONVERGED && status != AX_ERR_BREAKDOWN) {
         (void)hipStreamSynchronize(st);
