@@ -101,6 +101,17 @@ inline bool centro_antisymmetric(int N1, const double* D)
     return dev <= 1e-13 * mx;
 }
 
+// True if the nodes and weights are mirror-symmetric (xi[N-k] = -xi[k], w[N-k] = w[k], and a
+// zero middle node for odd N1) exactly, as the GLL nodes built here are; the even-odd kernels
+// then keep only half of them.  A null xi (not needed by the caller) only checks w.
+inline bool symmetric_nodes(int N1, const double* xi, const double* w)
+{
+    if (!w) return false;
+    for (int k = 0; k < N1; ++k)
+        if ((xi && xi[N1 - 1 - k] != -xi[k]) || w[N1 - 1 - k] != w[k]) return false;
+    return true;
+}
+
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 // Launch tuning of the AxLocal kernels per (N1, geometry kind 0/1/2, precision FP64/FP32).

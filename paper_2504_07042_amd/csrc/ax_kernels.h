@@ -24,14 +24,24 @@ enum { GEO_TRI = 0, GEO_PARA = 1, GEO_STORED = 2 };
 #ifndef AX_LDS_SWIZZLE
 #define AX_LDS_SWIZZLE 0
 #endif
+// LDS layout for N1 = 8: 0 = word i + 9 j + 72 k (row stride padded to 9); 1 = word
+// i + 8 j + 65 k with the r-pencils assigned to lanes k-fastest.  With 64-bit accesses served
+// 16 lanes per clock over 32 four-byte banks, layout 0 is conflict-free for the r- and s-pencils
+// and 2-way conflicted for the home columns; layout 1 is conflict-free for the home columns and
+// the r-pencils and 2-way conflicted for the s-pencils (no additive layout is conflict-free for
+// all three patterns).
+#ifndef AX_LDS_LAYOUT
+#define AX_LDS_LAYOUT 1
+#endif
 
 template <int N1>
 struct Shape {
     static constexpr int NT = N1 * N1;                        // lanes per element
-    static constexpr int SJ = (N1 % 2 == 0) ? N1 + 1 : N1;    // LDS row stride (odd)
-    static constexpr int SK = N1 * SJ;                        // LDS slice stride
     static constexpr bool SWZ = AX_LDS_SWIZZLE && N1 == 8;
-    static constexpr int FS = SWZ ? 512 : N1 * SK;            // LDS words per field
+    static constexpr bool L1 = !SWZ && AX_LDS_LAYOUT == 1 && N1 == 8;
+    static constexpr int SJ = L1 ? 8 : (N1 % 2 == 0) ? N1 + 1 : N1;   // LDS row stride
+    static constexpr int SK = L1 ? 65 : N1 * SJ;                      // LDS slice stride
+    static constexpr int FS = SWZ ? 512 : L1 ? 520 : N1 * SK;         // LDS words per field
     // LDS word of node (i, j, k) within one field
     __device__ static __forceinline__ int pos(int i, int j, int k)
     {
@@ -40,6 +50,9 @@ struct Shape {
         else
             return k * SK + j * SJ + i;
     }
+    // pencil lanes: the r-pencil (j, k) and the s-pencil (i, k) a lane owns
+    __device__ static __forceinline__ int rpa(int lane) { return L1 ? lane / N1 : lane % N1; }
+    __device__ static __forceinline__ int rpb(int lane) { return L1 ? lane % N1 : lane / N1; }
     static constexpr int NP = N1 * N1 * N1;                   // nodes per element
     // elements per work-group: fill (nearly) whole waves while keeping LDS modest
     static constexpr int EPB = N1 == 2 ? 16 : N1 == 3 ? 7 : N1 == 4 ? 4 : N1 == 5 ? 5

@@ -20,14 +20,23 @@
 //     not overlap with it, so the FP64 contractions stay on the vector unit.
 #pragma once
 
+#include <type_traits>
+
 #include "ax_internal.h"
 #include "ax_kernels.h"
 #include "geom.h"
 
-// Issue point of the next item's loads: 0 = before the first contraction (longest overlap),
-// 1 = after the pointwise stage (shorter overlap, fewer live registers at the pointwise peak).
-#ifndef AX_PREFETCH_LATE
-#define AX_PREFETCH_LATE 0
+// 1: the even-odd kernels (mirror-symmetric nodes) read xi_k and w_k of the node loop from the
+// first half of the kernel-argument tables, which stays resident in scalar registers next to
+// the contraction coefficients; 0: every node reads them from an LDS table.
+#ifndef AX_XW_SCALAR
+#define AX_XW_SCALAR 1
+#endif
+// 1: the s-direction transpose contraction goes back to LDS in place and the output stage sums
+// the two fields (one barrier and one read-modify-write pass fewer); 0: it is added into the
+// r-field through a separate pass.
+#ifndef AX_MERGE_RS
+#define AX_MERGE_RS 1
 #endif
 
 namespace ax {
@@ -40,6 +49,30 @@ struct Tile {
     static constexpr int BLOCK = ((EPB * NT + 63) / 64) * 64;
     static constexpr int SLOTS = (BLOCK + NT - 1) / NT;
 };
+
+// (xi_k, w_k) of node k for the pointwise stage
+template <int N1, bool EO, typename T, typename B>
+__device__ __forceinline__ void node_xw(const B& bs, const double* sxw, int k, T& t, T& wk)
+{
+    if constexpr (EO && AX_XW_SCALAR) {
+        const int m = k < N1 - 1 - k ? k : N1 - 1 - k;
+        const double x = bs.xi[m];
+        t = T(k == m ? x : -x);
+        wk = T(bs.w[m]);
+    } else {
+        t = T(sxw[2 * k]);
+        wk = T(sxw[2 * k + 1]);
+    }
+}
+
+// Element at byte offset `off` (32-bit, non-negative) from a work-group-uniform base: the form
+// the global loads and stores take with a scalar base register and a 32-bit lane offset.
+template <typename P>
+__device__ __forceinline__ P* at_bytes(P* base, uint32_t off)
+{
+    using C = typename std::conditional<std::is_const<P>::value, const char, char>::type;
+    return reinterpret_cast<P*>(reinterpret_cast<C*>(base) + off);
+}
 
 // GATHER: X is a global vector [nrhs][ldg] read through the local-to-global map l2g (the Q of
 // Sec. 2.1 fused into the load), so the solver never materialises Q x.
@@ -57,8 +90,8 @@ ax_local_kernel(int64_t E, int nrhs, const double* __restrict__ geo, const T* __
     constexpr int VPT = (EPB * NV + BLOCK - 1) / BLOCK;          // vertex words per thread
     __shared__ T smem[TL::SLOTS * 2 * FS];
     __shared__ double svert[(GEO == GEO_TRI) ? EPB * 24 : 1];
-    // (xi_k, w_k) pairs: read per node from LDS rather than held in scalar registers, which
-    // leaves the scalar file to the contraction coefficients
+    // (xi_k, w_k) pairs: the per-lane (xi_i, w_i), (xi_j, w_j) of the home columns, and xi_k, w_k
+    // of the node loop for the kernels that do not keep them in scalar registers
     __shared__ double sxw[2 * N1];
 
     const int tid = threadIdx.x;
@@ -67,111 +100,104 @@ ax_local_kernel(int64_t E, int nrhs, const double* __restrict__ geo, const T* __
     T* __restrict__ A = smem + slot * 2 * FS;
     T* __restrict__ B = A + FS;
     const int i = lane % N1, j = lane / N1;    // home lane: node column (i, j, :)
-    const int pa = lane % N1, pb = lane / N1;  // pencil lane: (j,k) for r, (i,k) for s
+    const int pa = lane % N1, pb = lane / N1;  // s-pencil lane (i, k)
+    const int ra = S::rpa(lane), rb = S::rpb(lane);  // r-pencil lane (j, k)
     const int64_t nblk = (E + EPB - 1) / EPB;
     if (tid < 2 * N1) sxw[tid] = (tid & 1) ? bs.w[tid >> 1] : bs.xi[tid >> 1];
 
     // Items are (element group, column) pairs walked in order; each work-group strides over the
     // element groups.  The next item's X (and vertices) are fetched into registers while the
-    // current one is computed, so HBM latency overlaps with the contraction work.
-    int64_t eb = blockIdx.x;
-    int c = 0;
-    auto x_base = [&](int64_t ebq, int cq, bool& act) -> int64_t {
-        const int64_t eq = ebq * EPB + slot;
-        act = (ebq < nblk) && (slot < EPB) && (eq < E);
-        return ((int64_t)cq * E + (act ? eq : 0)) * NP;
-    };
-    // node column (i, j, :) of item (ebq, cq); inactive lanes read element 0 and discard it,
-    // which keeps the loads free of per-load branches
+    // current one is computed and staged into LDS at the end of the current item, so HBM latency
+    // overlaps with a whole item of contraction work.  Addresses are a group-uniform base plus a
+    // 32-bit lane offset; a group past the end is clamped to group 0 and slots past the last
+    // element read the group's first element (results of such slots are never stored).
+    auto clamp_group = [&](int64_t ebq) -> int64_t { return ebq < nblk ? ebq : 0; };
+    auto slot_active = [&](int64_t g) -> bool { return (slot < EPB) && (g * EPB + slot < E); };
+    // byte offset of node (i, j, 0) of this lane's element from the group's first node
+    auto home_off = [&](bool act) -> uint32_t { return (uint32_t)(((act ? slot * NP : 0) + i + j * N1) * sizeof(T)); };
     auto load_x = [&](int64_t ebq, int cq, T* dst) {
-        const int64_t eq = ebq * EPB + slot;
-        const bool act = (ebq < nblk) && (slot < EPB) && (eq < E);
-        const int64_t le = (act ? eq : 0) * NP + i + j * N1;
+        const int64_t g = clamp_group(ebq);
+        const uint32_t lo = home_off(slot_active(g));
         if constexpr (GATHER) {
+            const int32_t* mb = l2g + g * EPB * NP;
             int32_t gi[N1];
 #pragma unroll
-            for (int k = 0; k < N1; ++k) gi[k] = l2g[le + k * NT];
+            for (int k = 0; k < N1; ++k) gi[k] = *at_bytes(mb, lo / sizeof(T) * 4 + k * NT * 4);
             const T* xc = X + (int64_t)cq * ldg;
 #pragma unroll
             for (int k = 0; k < N1; ++k) dst[k] = xc[gi[k]];
         } else {
-            const T* src = X + (int64_t)cq * E * NP + le;
+            const T* src = X + ((int64_t)cq * E + g * EPB) * NP;
 #pragma unroll
-            for (int k = 0; k < N1; ++k) dst[k] = src[k * NT];
-        }
-        if (!act) {
-#pragma unroll
-            for (int k = 0; k < N1; ++k) dst[k] = T(0);
+            for (int k = 0; k < N1; ++k) dst[k] = *at_bytes(src, lo + k * NT * (uint32_t)sizeof(T));
         }
     };
+    auto load_v = [&](int64_t ebq, double* dst) {
+        if constexpr (GEO == GEO_TRI) {
+            const int64_t g = clamp_group(ebq);
+            const double* src = geo + g * EPB * 24;
+            const int64_t lim = (E - g * EPB) * 24;   // vertex words left from the group start
+#pragma unroll
+            for (int q = 0; q < VPT; ++q) {
+                const int idx = tid + q * BLOCK;
+                dst[q] = *at_bytes(src, (uint32_t)((idx < EPB * 24 && idx < lim ? idx : 0) * 8));
+            }
+        }
+    };
+    auto stage = [&](const T* x, const double* v, bool new_elem) {
+#pragma unroll
+        for (int k = 0; k < N1; ++k) A[S::pos(i, j, k)] = x[k];
+        if constexpr (GEO == GEO_TRI) {
+            if (new_elem) {
+#pragma unroll
+                for (int q = 0; q < VPT; ++q) {
+                    const int idx = tid + q * BLOCK;
+                    if (idx < EPB * 24) svert[idx] = v[q];
+                }
+            }
+        }
+    };
+
+    int64_t eb = blockIdx.x;
+    int c = 0;
     T xr[N1];
     double vr[VPT > 0 ? VPT : 1];
-    load_x(eb, c, xr);
-    if constexpr (GEO == GEO_TRI) {
-#pragma unroll
-        for (int q = 0; q < VPT; ++q) {
-            const int idx = tid + q * BLOCK;
-            const int64_t off = eb * EPB * 24 + idx;
-            vr[q] = (idx < EPB * 24 && eb < nblk && off < E * 24) ? geo[off] : 0.0;
-        }
-    }
+    load_x(eb, 0, xr);
+    load_v(eb, vr);
+    stage(xr, vr, true);
 
     TriCoef tc;
     double h[6];
     while (eb < nblk) {
-        bool active;
-        const int64_t base = x_base(eb, c, active);
+        const bool active = slot_active(eb);
         const int64_t e = eb * EPB + slot;
+        const bool last_col = (c + 1 == nrhs);
+        const int64_t eb_n = last_col ? eb + gridDim.x : eb;
+        const int c_n = last_col ? 0 : c + 1;
         if constexpr (GEO == GEO_PARA) {
             if (c == 0) {
                 const double* he = geo + (active ? e : 0) * 6;
-                const double wij = bs.w[i] * bs.w[j];
+                const double wij = sxw[2 * i + 1] * sxw[2 * j + 1];
 #pragma unroll
                 for (int q = 0; q < 6; ++q) h[q] = he[q] * wij;
             }
         }
-        // P0: stage X (and the vertices), prefetch the next item, t-contraction in registers
-#pragma unroll
-        for (int k = 0; k < N1; ++k) A[S::pos(i, j, k)] = xr[k];
-        if constexpr (GEO == GEO_TRI) {
-            if (c == 0) {
-#pragma unroll
-                for (int q = 0; q < VPT; ++q) {
-                    const int idx = tid + q * BLOCK;
-                    if (idx < EPB * 24) svert[idx] = vr[q];
-                }
-            }
-        }
-        const bool last_col = (c + 1 == nrhs);
-        const int64_t eb_n = last_col ? eb + gridDim.x : eb;
-        const int c_n = last_col ? 0 : c + 1;
-        T xn[N1];
-        auto prefetch = [&]() {
-            load_x(eb_n, c_n, xn);
-            if constexpr (GEO == GEO_TRI) {
-                if (last_col) {
-#pragma unroll
-                    for (int q = 0; q < VPT; ++q) {
-                        const int idx = tid + q * BLOCK;
-                        const int64_t off = eb_n * EPB * 24 + idx;
-                        vr[q] = (idx < EPB * 24 && eb_n < nblk && off < E * 24) ? geo[off] : 0.0;
-                    }
-                }
-            }
-        };
-        if constexpr (AX_PREFETCH_LATE == 0) prefetch();
+        // P0: t-contraction in registers, then the next item's loads
         T x2[N1];
         contract<N1, false, EO>(bs, xr, x2);  // x2 = D_t x
+        T xn[N1];
+        load_x(eb_n, c_n, xn);
+        if (last_col) load_v(eb_n, vr);
         __syncthreads();
         // P1: r-pencils (j,k) -> x0 in B; s-pencils (i,k) -> x1 held in registers
         T o1[N1];
         {
             T p[N1], o[N1];
 #pragma unroll
-            for (int n = 0; n < N1; ++n) p[n] = A[S::pos(n, pa, pb)];
+            for (int n = 0; n < N1; ++n) p[n] = A[S::pos(n, ra, rb)];
             contract<N1, false, EO>(bs, p, o);
 #pragma unroll
-            for (int a = 0; a < N1; ++a) B[S::pos(a, pa, pb)] = o[a];
+            for (int a = 0; a < N1; ++a) B[S::pos(a, ra, rb)] = o[a];
 #pragma unroll
             for (int n = 0; n < N1; ++n) p[n] = A[S::pos(pa, n, pb)];
             contract<N1, false, EO>(bs, p, o1);
@@ -183,8 +209,8 @@ ax_local_kernel(int64_t E, int nrhs, const double* __restrict__ geo, const T* __
         if constexpr (GEO == GEO_TRI) {
             if (c == 0) {
                 const double* sv = svert + (slot < EPB ? slot : 0) * 24;
-                tri_prelude([&](int v, int q) { return sv[v * 3 + q]; }, bs.xi[i], bs.xi[j], bs.w[i],
-                            bs.w[j], tc);
+                tri_prelude([&](int v, int q) { return sv[v * 3 + q]; }, sxw[2 * i], sxw[2 * j], sxw[2 * i + 1],
+                            sxw[2 * j + 1], tc);
             }
         }
         __syncthreads();
@@ -197,12 +223,15 @@ ax_local_kernel(int64_t E, int nrhs, const double* __restrict__ geo, const T* __
             T g[6];
             if constexpr (GEO == GEO_TRI) {
                 T lam;
-                tri_adj<T>(tc, T(sxw[2 * k]), T(sxw[2 * k + 1]), g, lam);
+                T tk, wk;
+                node_xw<N1, EO>(bs, sxw, k, tk, wk);
+                tri_adj<T>(tc, tk, wk, g, lam);
                 x0 *= lam;
                 x1 *= lam;
                 xx2 *= lam;
             } else if constexpr (GEO == GEO_PARA) {
-                const T wk = T(sxw[2 * k + 1]);
+                T tk, wk;
+                node_xw<N1, EO>(bs, sxw, k, tk, wk);
 #pragma unroll
                 for (int q = 0; q < 6; ++q) g[q] = T(h[q]) * wk;
             } else {
@@ -216,21 +245,37 @@ ax_local_kernel(int64_t E, int nrhs, const double* __restrict__ geo, const T* __
         }
         T y2[N1];
         contract<N1, true, EO>(bs, tt, y2);  // D_t^T t
-        if constexpr (AX_PREFETCH_LATE != 0) prefetch();
         __syncthreads();
         // P4: D_r^T r in place on the r-pencils; D_s^T s into registers
         {
             T p[N1], o[N1];
 #pragma unroll
-            for (int n = 0; n < N1; ++n) p[n] = B[S::pos(n, pa, pb)];
+            for (int n = 0; n < N1; ++n) p[n] = B[S::pos(n, ra, rb)];
             contract<N1, true, EO>(bs, p, o);
 #pragma unroll
-            for (int a = 0; a < N1; ++a) B[S::pos(a, pa, pb)] = o[a];
+            for (int a = 0; a < N1; ++a) B[S::pos(a, ra, rb)] = o[a];
 #pragma unroll
             for (int n = 0; n < N1; ++n) p[n] = A[S::pos(pa, n, pb)];
             contract<N1, true, EO>(bs, p, o1);
+#if AX_MERGE_RS
+            // each s-pencil is read and written by its own lane only
+#pragma unroll
+            for (int a = 0; a < N1; ++a) A[S::pos(pa, a, pb)] = o1[a];
+#endif
         }
         __syncthreads();
+        T* yb = Y + ((int64_t)c * E + eb * EPB) * NP;
+        const uint32_t lo = home_off(true);
+#if AX_MERGE_RS
+        // P5: Y = (D_r^T r + D_s^T s) + D_t^T t
+        if (active) {
+#pragma unroll
+            for (int k = 0; k < N1; ++k) {
+                const int l = S::pos(i, j, k);
+                *at_bytes(yb, lo + k * NT * (uint32_t)sizeof(T)) = (B[l] + A[l]) + y2[k];
+            }
+        }
+#else
         // P5: add D_s^T s on the s-pencils
 #pragma unroll
         for (int a = 0; a < N1; ++a) B[S::pos(pa, a, pb)] += o1[a];
@@ -238,8 +283,13 @@ ax_local_kernel(int64_t E, int nrhs, const double* __restrict__ geo, const T* __
         // P6: Y = (D_r^T r + D_s^T s) + D_t^T t
         if (active) {
 #pragma unroll
-            for (int k = 0; k < N1; ++k) Y[base + i + j * N1 + k * NT] = B[S::pos(i, j, k)] + y2[k];
+            for (int k = 0; k < N1; ++k)
+                *at_bytes(yb, lo + k * NT * (uint32_t)sizeof(T)) = B[S::pos(i, j, k)] + y2[k];
         }
+#endif
+        // stage the next item: this lane's own home positions (read above by this lane only)
+        // and the vertex table (last read before the barriers of P3 and P4)
+        stage(xn, vr, last_col);
 #pragma unroll
         for (int k = 0; k < N1; ++k) xr[k] = xn[k];
         eb = eb_n;
@@ -283,7 +333,8 @@ static int launch_n1(int64_t E, int nrhs, const double* geo, const T* Gs, const 
     using S = Shape<N1>;
     Basis<T> bs;
     fill_basis(bs, N1, D, xi, w);
-    const bool eo = centro_antisymmetric(N1, D);
+    // the even-odd kernels also take the nodes as mirror-symmetric (the factors need none)
+    const bool eo = centro_antisymmetric(N1, D) && (GEO == GEO_STORED || symmetric_nodes(N1, xi, w));
     const TuneEntry tu = tune_get(N1, GEO, sizeof(T) == 8 ? AX_FP64 : AX_FP32);
     if (l2g) {
         if (!eo) return fail(AX_ERR_UNSUPPORTED, "gathering AxLocal needs a GLL differentiation matrix");

@@ -98,13 +98,18 @@ __device__ __forceinline__ void tri_prelude(VF V, double r, double s, double wi,
     k.cw = 0.125 * wi * wj;
 }
 
-// 1/x: the hardware reciprocal estimate refined by two Newton-Raphson steps
-// r <- r + r (1 - x r), each of which squares the relative error (well below one ulp after two).
+// Newton-Raphson steps applied to the hardware reciprocal estimate in FP64.
+#ifndef AX_RCP_NR
+#define AX_RCP_NR 2
+#endif
+
+// 1/x: the hardware reciprocal estimate refined by Newton-Raphson steps
+// r <- r + r (1 - x r), each of which squares the relative error.
 __device__ __forceinline__ double recip(double x)
 {
     double r = __builtin_amdgcn_rcp(x);
-    r = fma(r, fma(-x, r, 1.0), r);
-    r = fma(r, fma(-x, r, 1.0), r);
+#pragma unroll
+    for (int q = 0; q < AX_RCP_NR; ++q) r = fma(r, fma(-x, r, 1.0), r);
     return r;
 }
 
