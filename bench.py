@@ -91,8 +91,8 @@ def cpu_baseline(mesh, N, X, budget_s=10.0):
 def cg_solves(ax, meshgen, dev, N=7, grid=(32, 32, 32), rtol=1e-10, check_with_oracle=True):
     """-Lap u = f on the unit cube (homogeneous Dirichlet), N = 7, 32^3 trilinear hexes with
     +-10 % jitter (seed 4), f from u = sin(pi x) sin(pi y) sin(pi z).  Time to a true relative
-    residual of 1e-10: plain FP64 CG against mixed-precision refinement with an FP32 and an FP16
-    (matrix-core) inner AxLocal."""
+    residual of 1e-10: plain FP64 CG against mixed precision with an FP32 inner AxLocal (reliable
+    updates, and restarted refinement) and an FP16 (matrix-core) inner AxLocal (restarted)."""
     import torch
     m = meshgen.jittered_hex(*grid, alpha=0.10, seed=4)
     l2g, ng, mask = meshgen.global_numbering(*grid, N)
@@ -109,15 +109,16 @@ def cg_solves(ax, meshgen, dev, N=7, grid=(32, 32, 32), rtol=1e-10, check_with_o
     res = {"workload": f"Poisson N={N} E={grid[0]}x{grid[1]}x{grid[2]} jitter 10% seed 4, global DOFs {ng}",
            "rtol": rtol}
     runs = [("fp64", dict(inner_prec=ax.AX_FP64)),
-            ("mixed_fp32", dict(inner_prec=ax.AX_FP32, inner_rtol=1e-5)),
-            ("mixed_fp16", dict(inner_prec=ax.AX_FP16_ACC32, inner_rtol=1e-2))]
+            ("mixed_fp32_reliable", dict(inner_prec=ax.AX_FP32, inner_rtol=0.1, refine=ax.AX_REFINE_RELIABLE)),
+            ("mixed_fp32_restart", dict(inner_prec=ax.AX_FP32, inner_rtol=1e-5)),
+            ("mixed_fp16_restart", dict(inner_prec=ax.AX_FP16_ACC32, inner_rtol=1e-2))]
     sols = {}
     for name, kw in runs:
         x, rep = ax.cg_solve(prob, rhs, rtol=rtol, max_it=40000, max_outer=60, **kw)
         res[name] = {k: (round(v, 4) if isinstance(v, float) and k == "seconds" else v) for k, v in rep.items()}
         sols[name] = x
     t64 = res["fp64"]["seconds"]
-    for name in ("mixed_fp32", "mixed_fp16"):
+    for name, _ in runs[1:]:
         res[name]["speedup_vs_fp64"] = round(t64 / res[name]["seconds"], 3) if res[name]["seconds"] > 0 else None
     ug = torch.zeros(ng, dtype=torch.float64, device=dev)
     u = torch.sin(np.pi * XYZ[:, 0]) * torch.sin(np.pi * XYZ[:, 1]) * torch.sin(np.pi * XYZ[:, 2])
@@ -238,11 +239,44 @@ def batched_run(ax, meshgen, dev, nrhs=8, steps=5, warmup=2, check_with_oracle=T
     return res
 
 
+def batched_cg(ax, meshgen, dev, rtol=1e-10, nrhs=1):
+    """CG on the block-diagonal union of the 64 batched meshes (same specs as batched_run), every
+    AxLocal application of a step in one persistent launch: plain FP64 against mixed precision
+    (FP32 inner AxLocal, reliable updates and restarted refinement), time to a true relative
+    residual of 1e-10.  b ~ U[-1, 1] per global node, zero on each box boundary."""
+    import torch
+    specs = meshgen.batch_specs(64, 512, 32768, (3, 5, 7, 9), seed=1)
+    meshes, parts = [], []
+    for sp in specs:
+        m = meshgen.jittered_hex(sp.nx, sp.ny, sp.nz, alpha=0.10, seed=sp.seed)
+        meshes.append((torch.from_numpy(m.verts).to(dev), ax.Basis(sp.N)))
+        parts.append(meshgen.global_numbering(sp.nx, sp.ny, sp.nz, sp.N))
+    l2g, ng, mask, _, _ = meshgen.concat_numbering(parts)
+    del parts
+    gs = ax.GatherScatter(l2g, ng, mask)
+    b = meshgen.random_global_device(ng, mask, nrhs, seed=5, device=dev)
+    res = {"workload": f"union of the 64 batched meshes, {l2g.size} local / {ng} global DOFs, {nrhs} column(s), "
+                       f"b ~ U[-1,1]", "rtol": rtol}
+    del l2g
+    runs = [("fp64", dict(inner_prec=ax.AX_FP64)),
+            ("mixed_fp32_reliable", dict(inner_prec=ax.AX_FP32, inner_rtol=0.1, refine=ax.AX_REFINE_RELIABLE)),
+            ("mixed_fp32_restart", dict(inner_prec=ax.AX_FP32, inner_rtol=1e-5))]
+    for name, kw in runs:
+        x, rep = ax.cg_solve_batched(meshes, gs, b, rtol=rtol, max_it=20000, max_outer=80, **kw)
+        res[name] = {k: (round(v, 4) if isinstance(v, float) and k == "seconds" else v) for k, v in rep.items()}
+        print(f"batched cg {name}: {res[name]}", file=sys.stderr, flush=True)
+        del x
+    t64 = res["fp64"]["seconds"]
+    for name, _ in runs[1:]:
+        res[name]["speedup_vs_fp64"] = round(t64 / res[name]["seconds"], 3) if res[name]["seconds"] > 0 else None
+    return res
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=2000)
     ap.add_argument("--N", type=int, default=7)
     ap.add_argument("--grid", type=int, nargs=3, default=None)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -377,6 +411,7 @@ def main(argv=None):
     if args.batched:
         out["batched"] = batched_run(ax, meshgen, dev, steps=max(5, args.steps // 10), warmup=2,
                                      check_with_oracle=not args.no_cpu)
+        out["batched_cg"] = batched_cg(ax, meshgen, dev)
 
     if args.sweep:
         out["order_sweep"] = order_sweep(ax, meshgen, dev, steps=max(10, args.steps // 2), warmup=3)

@@ -185,7 +185,18 @@ typedef struct {
     void* workspace;       /* [dev] at least cg_workspace_bytes() bytes                   */
     size_t workspace_bytes;
     int use_graph;         /* 1: capture the CG iteration block in a HIP graph and replay it */
+    int refine;            /* AX_REFINE_RESTART or AX_REFINE_RELIABLE (refinement only)    */
 } ax_cg_opts;
+
+/* Refinement schemes of the mixed-precision solves (ax_cg_opts.refine):
+ * AX_REFINE_RESTART  - each correction A d = r / ||r|| is an inner CG started from scratch and
+ *                      solved to inner_rtol; max_outer bounds the number of corrections.
+ * AX_REFINE_RELIABLE - one reduced-precision CG recurrence runs throughout; each time its
+ *                      iterated residual has dropped by the factor inner_rtol (< 1) its iterate
+ *                      is added to x in FP64 and its residual is replaced by the FP64 true
+ *                      residual b - A x, keeping the search direction (reliable updates);
+ *                      max_outer bounds the number of such updates. */
+enum { AX_REFINE_RESTART = 0, AX_REFINE_RELIABLE = 1 };
 
 typedef struct {
     int status;            /* ax_status of the solve                                      */
@@ -204,9 +215,9 @@ int cg_workspace_bytes(const ax_problem* p, int nrhs, const ax_cg_opts* o, size_
  * Sec. 5.6).  b, x [dev] double [nrhs][n_global]; x holds the initial guess on entry (warm
  * start / resume) and the solution on exit.  Entries of b under the mask must be 0.
  * inner_prec == AX_FP64 runs plain CG in FP64.  Otherwise mixed-precision iterative refinement:
- * the outer residual r = b - A x, its norm and the update of x are FP64; each correction
- * A d = r / ||r|| is solved by an inner CG whose AxLocal runs in inner_prec with float vectors
- * and FP64-accumulated dot products.  All scalars stay on the device; the host polls the
+ * the outer residual r = b - A x, its norm and the update of x are FP64; the corrections come
+ * from CG iterations whose AxLocal runs in inner_prec with float vectors and FP64-accumulated
+ * dot products, restarted per correction or continued through reliable updates (o->refine).  All scalars stay on the device; the host polls the
  * convergence flags every 8 iterations, and with use_graph those 8 iterations are captured once
  * in a HIP graph and replayed.  The work runs on a private stream of the calling thread after
  * `stream` has been synchronised, and both are synchronised before returning (rep is filled).

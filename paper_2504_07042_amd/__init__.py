@@ -21,6 +21,7 @@ AX_OK, AX_ERR_ARG, AX_ERR_UNSUPPORTED, AX_ERR_HIP, AX_ERR_NOMEM, AX_ERR_NOT_CONV
     0, -1, -2, -3, -4, -5, -6)
 AX_TRILINEAR, AX_PARALLELEPIPED, AX_STORED_G = 0, 1, 2
 AX_FP64, AX_FP32, AX_FP16_ACC32 = 0, 1, 2
+AX_REFINE_RESTART, AX_REFINE_RELIABLE = 0, 1
 GS_QT, GS_Q, GS_QQT = 0, 1, 2
 
 _STATUS = {0: "AX_OK", -1: "AX_ERR_ARG", -2: "AX_ERR_UNSUPPORTED", -3: "AX_ERR_HIP",
@@ -48,7 +49,7 @@ class AxProblem(ctypes.Structure):
 class AxCgOpts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("max_it", _int), ("inner_prec", _int),
                 ("inner_rtol", ctypes.c_double), ("max_outer", _int), ("workspace", _vp),
-                ("workspace_bytes", ctypes.c_size_t), ("use_graph", _int)]
+                ("workspace_bytes", ctypes.c_size_t), ("use_graph", _int), ("refine", _int)]
 
 
 class AxBatchPlan(ctypes.Structure):
@@ -287,16 +288,18 @@ class Problem:
 
 
 def cg_solve(prob: Problem, b, x=None, rtol=1e-10, max_it=20000, inner_prec=AX_FP64, inner_rtol=1e-6,
-             max_outer=50, use_graph=True, stream=None):
-    """Solve A x = b by CG (inner_prec = AX_FP64) or mixed-precision iterative refinement.
-    b [nrhs][n_global] float64 device.  Returns (x, report dict); raises AxError only on
-    argument or launch errors (non-convergence and breakdown are reported in the dict)."""
+             max_outer=50, use_graph=True, refine=None, stream=None):
+    """Solve A x = b by CG (inner_prec = AX_FP64) or mixed-precision iterative refinement
+    (refine = AX_REFINE_RESTART, the default, or AX_REFINE_RELIABLE).  b [nrhs][n_global]
+    float64 device.  Returns (x, report dict); raises AxError only on argument or launch errors
+    (non-convergence and breakdown are reported in the dict)."""
     import torch
     nrhs = b.shape[0] if b.dim() == 2 else 1
     if x is None:
         x = torch.zeros_like(b)
     p = prob.c_struct()
-    opts = AxCgOpts(rtol, max_it, inner_prec, inner_rtol, max_outer, None, 0, 1 if use_graph else 0)
+    opts = AxCgOpts(rtol, max_it, inner_prec, inner_rtol, max_outer, None, 0, 1 if use_graph else 0,
+                    AX_REFINE_RESTART if refine is None else refine)
     nbytes = ctypes.c_size_t()
     _check(lib().cg_workspace_bytes(ctypes.byref(p), nrhs, ctypes.byref(opts), ctypes.byref(nbytes)))
     ws = torch.empty(nbytes.value, dtype=torch.uint8, device=b.device)
@@ -342,7 +345,7 @@ class BatchedAxLocal:
 
 
 def cg_solve_batched(meshes, gs: GatherScatter, b, x=None, rtol=1e-10, max_it=20000, inner_prec=AX_FP64,
-                     inner_rtol=1e-6, max_outer=50, use_graph=True, stream=None):
+                     inner_rtol=1e-6, max_outer=50, use_graph=True, refine=None, stream=None):
     """CG / mixed refinement over the union of many trilinear meshes (block-diagonal system).
     meshes: list of (verts device tensor, Basis) in the order of the concatenated local vectors;
     gs: gather-scatter of the concatenated numbering; b [nrhs][n_global] float64 device."""
@@ -355,7 +358,8 @@ def cg_solve_batched(meshes, gs: GatherScatter, b, x=None, rtol=1e-10, max_it=20
     nrhs = b.shape[0] if b.dim() == 2 else 1
     if x is None:
         x = torch.zeros_like(b)
-    opts = AxCgOpts(rtol, max_it, inner_prec, inner_rtol, max_outer, None, 0, 1 if use_graph else 0)
+    opts = AxCgOpts(rtol, max_it, inner_prec, inner_rtol, max_outer, None, 0, 1 if use_graph else 0,
+                    AX_REFINE_RESTART if refine is None else refine)
     nbytes = ctypes.c_size_t()
     _check(lib().cg_batched_workspace_bytes(n, probs, gs.n_global, nrhs, ctypes.byref(opts), ctypes.byref(nbytes)))
     ws = torch.empty(nbytes.value, dtype=torch.uint8, device=b.device)

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "ax_internal.h"
+#include "gs_impl.h"
 
 namespace ax {
 
@@ -24,6 +25,7 @@ int ax_local_gather(const ax_problem& p, int nrhs, int prec, const void* xg, int
 constexpr int kRedBlocks = 4096;  // partial sums per dot product and column (fixed grid)
 constexpr int kRedThreads = 256;
 constexpr int kPoll = 8;         // iterations between host convergence checks
+constexpr int kReliableCheck = 256;  // longest run of reduced-precision iterations between FP64 checks
 
 // Per-column scalar state of one CG (device).
 struct CgScal {
@@ -75,6 +77,8 @@ __device__ double block_sum_partials(const double* partials)
 
 // mode 0: rr = sum (initial), converged if rr <= tol2.   mode 1: alpha = rr / sum (= p.Ap).
 // mode 2: rr_new = sum; beta = rr_new / rr; rr = rr_new; converged test.
+// mode 3: rr = sum after a reliable update (alpha, beta and the iteration count are kept).
+// mode 4: sum = d . d of the iterate about to be folded; flags a non-finite one (breakdown 2).
 __global__ void __launch_bounds__(kRedThreads)
 cg_scalar_kernel(const double* __restrict__ partials, CgScal* __restrict__ sc, int mode)
 {
@@ -97,6 +101,14 @@ cg_scalar_kernel(const double* __restrict__ partials, CgScal* __restrict__ sc, i
         } else {
             q.alpha = q.rr / s;
         }
+    } else if (mode == 4) {
+        // s = d . d of the reduced-precision iterate: a non-finite one must not reach x
+        if (!isfinite(s)) q.breakdown = 2;
+    } else if (mode == 3) {
+        // the iterated residual was replaced by the true one: new r . r, keep the iteration count
+        q.rr = s;
+        q.converged = (s <= q.tol2) ? 1 : 0;
+        q.breakdown = isfinite(s) ? 0 : 1;
     } else {
         if (q.converged || q.breakdown) {
             q.beta = 0.0;
@@ -111,7 +123,8 @@ cg_scalar_kernel(const double* __restrict__ partials, CgScal* __restrict__ sc, i
 }
 
 // Ap[g] = mask ? 0 : sum of the local copies (ascending local id) and, fused, the partial sums of
-// p . Ap over the same fixed grid as dot_partial_kernel.
+// p . Ap over the same fixed grid as dot_partial_kernel.  Each thread takes kUnroll nodes per
+// tile so that their gathers are in flight together.
 template <typename T, typename IP>
 __global__ void __launch_bounds__(kRedThreads)
 qt_dot_kernel(int64_t n_local, int64_t n_global, const IP* __restrict__ gptr,
@@ -123,14 +136,26 @@ qt_dot_kernel(int64_t n_local, int64_t n_global, const IP* __restrict__ gptr,
     const T* pd = pdir + (int64_t)c * n_global;
     T* o = out + (int64_t)c * n_global;
     double acc = 0.0;
-    for (int64_t g = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; g < n_global;
-         g += (int64_t)gridDim.x * kRedThreads) {
-        T sum = T(0);
-        const int64_t q0 = gptr[g], q1 = gptr[g + 1];
-        for (int64_t q = q0; q < q1; ++q) sum += x[gidx[q]];
-        if (mask && mask[g]) sum = T(0);
-        o[g] = sum;
-        acc = fma((double)pd[g], (double)sum, acc);
+    for (int64_t g0 = (int64_t)blockIdx.x * kRedThreads * kUnroll + threadIdx.x; g0 < n_global;
+         g0 += (int64_t)gridDim.x * kRedThreads * kUnroll) {
+        T s[kUnroll];
+        int64_t gg[kUnroll];
+        bool ok[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            gg[u] = g0 + u * kRedThreads;
+            ok[u] = gg[u] < n_global;
+        }
+        gather_sums<kUnroll>(gptr, gidx, x, gg, ok, s);
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int64_t g = g0 + u * kRedThreads;
+            if (g < n_global) {
+                const T v = (mask && mask[g]) ? T(0) : s[u];
+                o[g] = v;
+                acc = fma((double)pd[g], (double)v, acc);
+            }
+        }
     }
     __shared__ double red[kRedThreads];
     red[threadIdx.x] = acc;
@@ -218,6 +243,29 @@ ir_update_kernel(double* __restrict__ x, const float* __restrict__ d, const CgSc
     const int64_t o = (int64_t)c * n;
     for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (int64_t)gridDim.x * 256)
         x[o + q] += nr * (double)d[o + q];
+}
+
+// dst(float) = src(double)
+__global__ void __launch_bounds__(256)
+to_f32_kernel(float* __restrict__ dst, const double* __restrict__ src, int64_t n)
+{
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (int64_t)gridDim.x * 256)
+        dst[q] = (float)src[q];
+}
+
+// x += sgn d (FP64 accumulation of the reduced-precision iterate) unless the column's iterate
+// was flagged non-finite; d = 0 if `clear`
+__global__ void __launch_bounds__(256)
+fold_kernel(double* __restrict__ x, float* __restrict__ d, const CgScal* __restrict__ sc, int64_t n,
+            double sgn, int clear)
+{
+    const int c = blockIdx.y;
+    const bool keep = sc[c].breakdown != 2;
+    const int64_t o = (int64_t)c * n;
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (int64_t)gridDim.x * 256) {
+        if (keep) x[o + q] += sgn * (double)d[o + q];
+        if (clear) d[o + q] = 0.0f;
+    }
 }
 
 template <typename T>
@@ -406,6 +454,31 @@ struct GraphCache {
     }
 };
 
+// `count` iterations: replays the captured kPoll-iteration graph when count == kPoll (capturing
+// it on first use), otherwise enqueues the kernels directly.
+template <typename TX, typename T>
+static int run_block(const Operator& op, int nrhs, int prec, TX* x, T* r, T* p, T* Ap, T* pl, T* wl,
+                     double* partials, CgScal* sc, int count, GraphCache* gc, hipStream_t st)
+{
+    if (gc && count == kPoll) {
+        if (!gc->exec) {
+            AX_TRY(hip_check(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed), "begin capture"));
+            const int s = cg_block<TX, T>(op, nrhs, prec, x, r, p, Ap, pl, wl, partials, sc, kPoll, st);
+            hipGraph_t graph = nullptr;
+            const hipError_t ec = hipStreamEndCapture(st, &graph);
+            if (s != AX_OK) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return s;
+            }
+            AX_TRY(hip_check(ec, "end capture"));
+            gc->graph = graph;
+            AX_TRY(hip_check(hipGraphInstantiate(&gc->exec, graph, nullptr, nullptr, 0), "graph instantiate"));
+        }
+        return hip_check(hipGraphLaunch(gc->exec, st), "graph launch");
+    }
+    return cg_block<TX, T>(op, nrhs, prec, x, r, p, Ap, pl, wl, partials, sc, count, st);
+}
+
 // Plain CG in precision T on A_T x = b (x holds the initial guess unless x_zero).  `iters` gets
 // the largest iteration count over the columns.  Returns AX_OK (all converged),
 // AX_ERR_NOT_CONVERGED or AX_ERR_BREAKDOWN.
@@ -447,24 +520,7 @@ static int cg_core(const Operator& op, int nrhs, int prec, const T* b, TX* x, T*
         if (all) return AX_OK;
         if (it >= max_it) return fail(AX_ERR_NOT_CONVERGED, "CG reached %d iterations", max_it);
         const int count = (max_it - it) < kPoll ? (max_it - it) : kPoll;
-        if (gc && count == kPoll) {
-            if (!gc->exec) {
-                AX_TRY(hip_check(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed), "begin capture"));
-                const int s = cg_block<TX, T>(op, nrhs, prec, x, r, p, Ap, pl, wl, partials, sc, kPoll, st);
-                hipGraph_t graph = nullptr;
-                const hipError_t ec = hipStreamEndCapture(st, &graph);
-                if (s != AX_OK) {
-                    if (graph) (void)hipGraphDestroy(graph);
-                    return s;
-                }
-                AX_TRY(hip_check(ec, "end capture"));
-                gc->graph = graph;
-                AX_TRY(hip_check(hipGraphInstantiate(&gc->exec, graph, nullptr, nullptr, 0), "graph instantiate"));
-            }
-            AX_TRY(hip_check(hipGraphLaunch(gc->exec, st), "graph launch"));
-        } else {
-            AX_TRY((cg_block<TX, T>(op, nrhs, prec, x, r, p, Ap, pl, wl, partials, sc, count, st)));
-        }
+        AX_TRY((run_block<TX, T>(op, nrhs, prec, x, r, p, Ap, pl, wl, partials, sc, count, gc, st)));
         it += count;
     }
 }
@@ -482,6 +538,10 @@ static int validate(const ax_problem* p, int nrhs, const ax_cg_opts* o)
     if (o->max_it < 1) return fail(AX_ERR_ARG, "max_it < 1");
     if (o->inner_prec != AX_FP64 && (!(o->inner_rtol > 0.0) || o->max_outer < 1))
         return fail(AX_ERR_ARG, "refinement needs inner_rtol > 0 and max_outer >= 1");
+    if (o->refine != AX_REFINE_RESTART && o->refine != AX_REFINE_RELIABLE)
+        return fail(AX_ERR_ARG, "refine must be AX_REFINE_RESTART or AX_REFINE_RELIABLE");
+    if (o->inner_prec != AX_FP64 && o->refine == AX_REFINE_RELIABLE && !(o->inner_rtol < 1.0))
+        return fail(AX_ERR_ARG, "reliable updates need inner_rtol < 1");
     if (p->E > 0 && (!p->geo || !p->D || !p->w || !p->l2g || !p->gptr || !p->gidx))
         return fail(AX_ERR_ARG, "NULL problem array");
     if (p->geom == AX_TRILINEAR && !p->xi) return fail(AX_ERR_ARG, "xi is NULL");
@@ -509,10 +569,13 @@ static int solve(const Operator& op, int64_t nl, int nrhs, const double* b, doub
         AX_TRY(scal(w.partials, w.sc, 0, nrhs, st));
         AX_TRY(poll(w.sc, nrhs, h, st));
         worst = 0.0;
+        bool bad = false;
         for (int c = 0; c < nrhs; ++c) {
             const double rel = h[c].tol2 > 0 ? std::sqrt(h[c].rr / h[c].tol2) : std::sqrt(h[c].rr);
-            worst = worst > rel ? worst : rel;
+            if (!std::isfinite(rel)) bad = true;
+            else worst = worst > rel ? worst : rel;
         }
+        if (bad) worst = std::nan("");
         return AX_OK;
     };
 
@@ -532,7 +595,87 @@ static int solve(const Operator& op, int64_t nl, int nrhs, const double* b, doub
         rep->outer_it = 1;
         rep->inner_it_total = total;
         rep->rel_res_true = worst;
-        if (status == AX_OK && worst > o->rtol) status = AX_ERR_NOT_CONVERGED;
+        if (status == AX_OK && !(worst <= o->rtol)) status = AX_ERR_NOT_CONVERGED;
+    } else if (o->refine == AX_REFINE_RELIABLE) {
+        // One reduced-precision CG recurrence (float vectors, inner_prec AxLocal, FP64-accumulated
+        // dot products) whose iterate d is folded into the FP64 solution, and whose residual is
+        // replaced by the FP64 true residual b - A x, every time its own residual has dropped by
+        // inner_rtol since the last replacement (reliable updates); the search direction is kept,
+        // so the Krylov space is not thrown away as in restarted refinement.
+        const int64_t n = ng * nrhs;
+        const dim3 gv(vgrid(n));
+        int total = 0, updates = 0;
+        double worst = 0.0;
+        std::vector<CgScal> hi;
+        AX_TRY(true_residual(worst));
+        if (worst > o->rtol) {
+            hipLaunchKernelGGL(to_f32_kernel, gv, dim3(256), 0, st, w.r32, w.r, n);
+            hipLaunchKernelGGL(copy_kernel<float>, gv, dim3(256), 0, st, w.p32, w.r32, n);
+            hipLaunchKernelGGL(zero_kernel<float>, gv, dim3(256), 0, st, w.d32, n);
+            AX_TRY(dot(b, b, ng, nrhs, w.partials, st));
+            hipLaunchKernelGGL(set_tol_kernel, dim3(nrhs), dim3(kRedThreads), 0, st, w.sc_in, w.partials, o->rtol);
+            AX_TRY(dot(w.r32, w.r32, ng, nrhs, w.partials, st));
+            AX_TRY(scal(w.partials, w.sc_in, 0, nrhs, st));
+            AX_TRY(poll(w.sc_in, nrhs, hi, st));
+            std::vector<double> rref(nrhs);
+            for (int c = 0; c < nrhs; ++c) rref[c] = hi[c].rr;
+            const double d2 = o->inner_rtol * o->inner_rtol;
+            int since = 0;
+            for (;;) {
+                const int count = (o->max_it - total) < kPoll ? (o->max_it - total) : kPoll;
+                AX_TRY((run_block<float, float>(op, nrhs, o->inner_prec, w.d32, w.r32, w.p32, w.Ap32, w.pl32,
+                                                w.wl32, w.partials, w.sc_in, count, graphs ? &gc32 : nullptr, st)));
+                total += count;
+                since += count;
+                AX_TRY(poll(w.sc_in, nrhs, hi, st));
+                bool all = true, brk = false, drop = false;
+                for (int c = 0; c < nrhs; ++c) {
+                    all = all && hi[c].converged;
+                    brk = brk || hi[c].breakdown;
+                    drop = drop || (!hi[c].converged && hi[c].rr <= d2 * rref[c]);
+                }
+                // besides the residual drop, the true residual is checked at least every
+                // kReliableCheck iterations: a recurrence that drifts away from the FP64 operator
+                // (e.g. with a half-precision AxLocal) is caught and discarded
+                if (!(all || brk || drop || since >= kReliableCheck || total >= o->max_it)) continue;
+                since = 0;
+                if (brk) {
+                    AX_TRY(dot(w.d32, w.d32, ng, nrhs, w.partials, st));
+                    AX_TRY(scal(w.partials, w.sc_in, 4, nrhs, st));
+                }
+                const double prev = worst;
+                hipLaunchKernelGGL(fold_kernel, g, dim3(256), 0, st, x, w.d32, w.sc_in, ng, 1.0, 0);
+                AX_TRY(true_residual(worst));
+                ++updates;
+                bool restart_dir = brk;
+                if (!(worst < prev)) {
+                    // the recurrence has drifted from the FP64 operator (its own residual fell,
+                    // the true one did not): take the update back and restart the direction
+                    hipLaunchKernelGGL(fold_kernel, g, dim3(256), 0, st, x, w.d32, w.sc_in, ng, -1.0, 0);
+                    AX_TRY(true_residual(worst));
+                    restart_dir = true;
+                }
+                hipLaunchKernelGGL(zero_kernel<float>, gv, dim3(256), 0, st, w.d32, n);
+                if (!std::isfinite(worst)) {
+                    status = fail(AX_ERR_BREAKDOWN, "non-finite true residual");
+                    break;
+                }
+                if (worst <= o->rtol || total >= o->max_it || updates >= o->max_outer) break;
+                hipLaunchKernelGGL(to_f32_kernel, gv, dim3(256), 0, st, w.r32, w.r, n);
+                if (restart_dir) hipLaunchKernelGGL(copy_kernel<float>, gv, dim3(256), 0, st, w.p32, w.r32, n);
+                AX_TRY(dot(w.r32, w.r32, ng, nrhs, w.partials, st));
+                AX_TRY(scal(w.partials, w.sc_in, 3, nrhs, st));
+                AX_TRY(poll(w.sc_in, nrhs, hi, st));
+                for (int c = 0; c < nrhs; ++c) rref[c] = hi[c].rr;
+            }
+            int its = 0;
+            for (int c = 0; c < nrhs; ++c) its = its > hi[c].iters ? its : hi[c].iters;
+            total = its;
+        }
+        rep->outer_it = updates;
+        rep->inner_it_total = total;
+        rep->rel_res_true = worst;
+        if (status == AX_OK) status = worst <= o->rtol ? AX_OK : AX_ERR_NOT_CONVERGED;
     } else {
         int total = 0, outer = 0;
         double worst = 0.0;

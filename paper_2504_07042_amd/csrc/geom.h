@@ -100,7 +100,7 @@ __device__ __forceinline__ void tri_prelude(VF V, double r, double s, double wi,
 
 // Newton-Raphson steps applied to the hardware reciprocal estimate in FP64.
 #ifndef AX_RCP_NR
-#define AX_RCP_NR 2
+#define AX_RCP_NR 1
 #endif
 
 // 1/x: the hardware reciprocal estimate refined by Newton-Raphson steps

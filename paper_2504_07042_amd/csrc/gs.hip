@@ -5,61 +5,83 @@
 #include <vector>
 
 #include "ax_internal.h"
+#include "gs_impl.h"
 
 namespace ax {
 
-template <typename T>
+// Column c = blockIdx.y; each thread takes kUnroll nodes per tile (stride 256) so that their
+// loads are in flight together.
+
+template <typename T, typename IP>
 __global__ void __launch_bounds__(256)
-gs_qt_kernel(int64_t n_local, int64_t n_global, int nrhs, const int64_t* __restrict__ gptr,
+gs_qt_kernel(int64_t n_local, int64_t n_global, const IP* __restrict__ gptr,
              const int32_t* __restrict__ gidx, const uint8_t* __restrict__ mask,
              const T* __restrict__ in, T* __restrict__ out)
 {
-    const int64_t total = n_global * nrhs;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
-         q += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t c = q / n_global, g = q - c * n_global;
-        const T* x = in + c * n_local;
-        T s = T(0);
-        for (int64_t p = gptr[g]; p < gptr[g + 1]; ++p) s += x[gidx[p]];
-        out[q] = (mask && mask[g]) ? T(0) : s;
+    const int c = blockIdx.y;
+    const T* x = in + (int64_t)c * n_local;
+    T* o = out + (int64_t)c * n_global;
+    for (int64_t g0 = (int64_t)blockIdx.x * 256 * kUnroll + threadIdx.x; g0 < n_global;
+         g0 += (int64_t)gridDim.x * 256 * kUnroll) {
+        T s[kUnroll];
+        int64_t g[kUnroll];
+        bool ok[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            g[u] = g0 + u * 256;
+            ok[u] = g[u] < n_global;
+        }
+        gather_sums<kUnroll>(gptr, gidx, x, g, ok, s);
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+            if (ok[u]) o[g[u]] = (mask && mask[g[u]]) ? T(0) : s[u];
     }
 }
 
 template <typename T>
 __global__ void __launch_bounds__(256)
-gs_q_kernel(int64_t n_local, int64_t n_global, int nrhs, const int32_t* __restrict__ l2g,
+gs_q_kernel(int64_t n_local, int64_t n_global, const int32_t* __restrict__ l2g,
             const T* __restrict__ in, T* __restrict__ out)
 {
-    const int64_t total = n_local * nrhs;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
-         q += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t c = q / n_local, l = q - c * n_local;
-        out[q] = in[c * n_global + l2g[l]];
+    const int c = blockIdx.y;
+    const T* x = in + (int64_t)c * n_global;
+    T* o = out + (int64_t)c * n_local;
+    for (int64_t l0 = (int64_t)blockIdx.x * 256 * kUnroll + threadIdx.x; l0 < n_local;
+         l0 += (int64_t)gridDim.x * 256 * kUnroll) {
+        int32_t id[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) id[u] = l0 + u * 256 < n_local ? l2g[l0 + u * 256] : 0;
+        T v[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) v[u] = x[id[u]];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+            if (l0 + u * 256 < n_local) o[l0 + u * 256] = v[u];
     }
 }
 
 template <typename T>
 __global__ void __launch_bounds__(256)
-gs_qqt_kernel(int64_t n_local, int nrhs, const int32_t* __restrict__ l2g,
-              const int64_t* __restrict__ gptr, const int32_t* __restrict__ gidx,
-              const uint8_t* __restrict__ mask, const T* __restrict__ in, T* __restrict__ out)
+gs_qqt_kernel(int64_t n_local, const int32_t* __restrict__ l2g, const int64_t* __restrict__ gptr,
+              const int32_t* __restrict__ gidx, const uint8_t* __restrict__ mask, const T* __restrict__ in,
+              T* __restrict__ out)
 {
-    const int64_t total = n_local * nrhs;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
-         q += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t c = q / n_local, l = q - c * n_local;
-        const int32_t g = l2g[l];
-        const T* x = in + c * n_local;
-        T s = T(0);
-        for (int64_t p = gptr[g]; p < gptr[g + 1]; ++p) s += x[gidx[p]];
-        out[q] = (mask && mask[g]) ? T(0) : s;
+    const int c = blockIdx.y;
+    const T* x = in + (int64_t)c * n_local;
+    T* o = out + (int64_t)c * n_local;
+    for (int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x; l < n_local; l += (int64_t)gridDim.x * 256) {
+        const int64_t g = l2g[l];
+        const bool ok = true;
+        T s;
+        gather_sums<1>(gptr, gidx, x, &g, &ok, &s);
+        o[l] = (mask && mask[g]) ? T(0) : s;
     }
 }
 
-static unsigned gs_grid(int64_t n)
+static unsigned gs_grid(int64_t n, int per_thread)
 {
-    const int64_t b = (n + 255) / 256;
-    return (unsigned)(b < 65536 ? (b > 0 ? b : 1) : 65536);
+    const int64_t b = (n + 256LL * per_thread - 1) / (256LL * per_thread);
+    return (unsigned)(b < 65535 ? (b > 0 ? b : 1) : 65535);
 }
 
 template <typename T>
@@ -69,16 +91,16 @@ static int gs_launch(int64_t n_local, int64_t n_global, const int32_t* l2g, cons
 {
     switch (mode) {
     case GS_QT:
-        hipLaunchKernelGGL(gs_qt_kernel<T>, dim3(gs_grid(n_global * nrhs)), dim3(256), 0, st, n_local,
-                           n_global, nrhs, gptr, gidx, mask, (const T*)in, (T*)out);
+        hipLaunchKernelGGL((gs_qt_kernel<T, int64_t>), dim3(gs_grid(n_global, kUnroll), nrhs), dim3(256), 0, st,
+                           n_local, n_global, gptr, gidx, mask, (const T*)in, (T*)out);
         break;
     case GS_Q:
-        hipLaunchKernelGGL(gs_q_kernel<T>, dim3(gs_grid(n_local * nrhs)), dim3(256), 0, st, n_local,
-                           n_global, nrhs, l2g, (const T*)in, (T*)out);
+        hipLaunchKernelGGL(gs_q_kernel<T>, dim3(gs_grid(n_local, kUnroll), nrhs), dim3(256), 0, st, n_local,
+                           n_global, l2g, (const T*)in, (T*)out);
         break;
     default:
-        hipLaunchKernelGGL(gs_qqt_kernel<T>, dim3(gs_grid(n_local * nrhs)), dim3(256), 0, st, n_local,
-                           nrhs, l2g, gptr, gidx, mask, (const T*)in, (T*)out);
+        hipLaunchKernelGGL(gs_qqt_kernel<T>, dim3(gs_grid(n_local, 1), nrhs), dim3(256), 0, st, n_local, l2g, gptr,
+                           gidx, mask, (const T*)in, (T*)out);
         break;
     }
     return hip_check(hipGetLastError(), "gs_assemble launch");
@@ -122,7 +144,7 @@ extern "C" int gs_assemble(int64_t n_local, int64_t n_global, const int32_t* l2g
 {
     clear_error();
     if (n_local < 0 || n_global < 0) return fail(AX_ERR_ARG, "negative size");
-    if (nrhs < 1) return fail(AX_ERR_ARG, "nrhs < 1");
+    if (nrhs < 1 || nrhs > 65535) return fail(AX_ERR_ARG, "nrhs outside [1, 65535]");
     if (mode != GS_QT && mode != GS_Q && mode != GS_QQT) return fail(AX_ERR_UNSUPPORTED, "unknown mode %d", mode);
     if (dtype != AX_FP64 && dtype != AX_FP32) return fail(AX_ERR_UNSUPPORTED, "dtype must be FP64 or FP32");
     if (n_local == 0 && n_global == 0) return AX_OK;

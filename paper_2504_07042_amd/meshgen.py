@@ -134,12 +134,18 @@ def box_element(hx: float, hy: float, hz: float, origin=(0.0, 0.0, 0.0)) -> np.n
     return v
 
 
-def global_numbering(nx: int, ny: int, nz: int, N: int):
-    """Structured global numbering of GLL nodes.
+def global_numbering(nx: int, ny: int, nz: int, N: int, order: str = "lexicographic"):
+    """Global numbering of the GLL nodes of an nx x ny x nz box of hexahedra.
 
+    ``order="lexicographic"`` (default) numbers the nodes of the global
+    (nx N + 1)(ny N + 1)(nz N + 1) grid x-fastest; ``order="element"`` renumbers them by first
+    appearance in the local (element-major) order, so that the new nodes of each element are
+    consecutive.
     Returns ``(l2g, n_global, mask)``: ``l2g`` int32 ``[E*N1**3]``; ``mask`` uint8
     ``[n_global]``, 1 on nodes of the boundary of the box (homogeneous Dirichlet).
     """
+    if order not in ("element", "lexicographic"):
+        raise ValueError(f"unknown numbering order {order!r}")
     N1 = N + 1
     Gx, Gy, Gz = nx * N + 1, ny * N + 1, nz * N + 1
     n_global = Gx * Gy * Gz
@@ -159,7 +165,20 @@ def global_numbering(nx: int, ny: int, nz: int, N: int):
     gJ = (np.arange(n_global) // Gx) % Gy
     gK = np.arange(n_global) // (Gx * Gy)
     mask = ((gI == 0) | (gI == Gx - 1) | (gJ == 0) | (gJ == Gy - 1) | (gK == 0) | (gK == Gz - 1))
-    return l2g, n_global, mask.astype(np.uint8)
+    mask = mask.astype(np.uint8)
+    if order == "element":
+        l2g, mask = first_touch(l2g, n_global, mask)
+    return l2g, n_global, mask
+
+
+def first_touch(l2g: np.ndarray, n_global: int, mask: np.ndarray):
+    """Renumber global nodes by their first appearance in ``l2g``; returns (l2g', mask')."""
+    _, first = np.unique(l2g, return_index=True)
+    new_id = np.empty(n_global, dtype=np.int64)
+    new_id[np.argsort(first, kind="stable")] = np.arange(n_global)
+    mask_new = np.empty_like(mask)
+    mask_new[new_id] = mask
+    return np.ascontiguousarray(new_id[l2g].astype(np.int32)), mask_new
 
 
 def chain_numbering(n: int, N: int):
@@ -241,3 +260,14 @@ def random_nodal_device(E: int, N: int, nrhs: int = 1, seed: int = 0, device="cu
     dtype = dtype or torch.float64
     x = torch.rand((nrhs, E, (N + 1) ** 3), generator=g, device=device, dtype=dtype)
     return x.mul_(2.0).sub_(1.0)
+
+
+def random_global_device(n_global: int, mask: np.ndarray, nrhs: int = 1, seed: int = 0, device="cuda"):
+    """b ~ U[-1, 1] per global node (float64, on the device, torch's seeded generator), zero on
+    the Dirichlet mask; shape ``[nrhs][n_global]``."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    b = torch.rand((nrhs, n_global), generator=g, device=device, dtype=torch.float64).mul_(2.0).sub_(1.0)
+    b[:, torch.from_numpy(np.asarray(mask, dtype=bool)).to(device)] = 0.0
+    return b

@@ -78,6 +78,25 @@ def test_mixed_refinement_reaches_fp64_residual(ax, inner):
     assert _oracle_rel_res(N, ref, rhs, xg.cpu().numpy()[0]) <= 1e-10
 
 
+@pytest.mark.parametrize("inner", ["fp32", "fp16"])
+def test_reliable_updates_reach_fp64_residual(ax, inner):
+    """Mixed precision with reliable updates: one reduced-precision recurrence, FP64 residual
+    replacements; the FP64 true residual reaches the target in about as many iterations as plain
+    FP64 CG (FP32) and the oracle confirms the residual of the solution."""
+    import torch
+    N = 4 if inner == "fp32" else 7
+    m, prob, ref, rhs = _problem(ax, N, (3, 3, 3) if inner == "fp32" else (2, 2, 2))
+    ip = {"fp32": ax.AX_FP32, "fp16": ax.AX_FP16_ACC32}[inner]
+    bd = torch.from_numpy(rhs[None]).cuda()
+    _, r64 = ax.cg_solve(prob, bd, rtol=1e-10)
+    xg, rep = ax.cg_solve(prob, bd, rtol=1e-10, inner_prec=ip, inner_rtol=0.1, refine=ax.AX_REFINE_RELIABLE)
+    assert rep["status"] == "AX_OK", rep
+    assert rep["outer_it"] >= 2
+    assert _oracle_rel_res(N, ref, rhs, xg.cpu().numpy()[0]) <= 1e-10
+    if inner == "fp32":
+        assert rep["iterations"] <= 1.25 * r64["iterations"] + 8, (rep, r64)
+
+
 def test_multi_rhs_and_warm_start(ax):
     import torch
     N = 3

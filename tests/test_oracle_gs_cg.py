@@ -34,6 +34,23 @@ def test_multiplicity_classes(N):
     assert mask.sum() == ng - (Gx - 2) * (Gy - 2) * (Gz - 2)
 
 
+@pytest.mark.parametrize("N", [1, 2, 3])
+def test_element_numbering_is_a_renumbering(N):
+    """The first-touch (element-major) numbering is a permutation of the lexicographic grid
+    numbering that carries the Dirichlet mask along, and numbers nodes in order of first
+    appearance."""
+    la, ng, ma = meshgen.global_numbering(3, 2, 2, N)
+    lb, ngb, mb = meshgen.global_numbering(3, 2, 2, N, order="element")
+    assert ng == ngb
+    perm = np.full(ng, -1, dtype=np.int64)
+    perm[la] = lb
+    assert np.array_equal(perm[la], lb)
+    assert np.array_equal(np.sort(perm), np.arange(ng))
+    assert np.array_equal(mb[perm], ma)
+    _, first = np.unique(lb, return_index=True)
+    assert np.all(np.diff(first) > 0)
+
+
 @pytest.mark.parametrize("N", [2, 3])
 def test_q_and_qt_vs_sparse(N):
     l2g, ng, _ = meshgen.global_numbering(2, 3, 2, N)
