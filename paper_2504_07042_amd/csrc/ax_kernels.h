@@ -67,15 +67,53 @@ struct Shape {
     static constexpr int MINW = N1 == 8 ? AX_MINW_SMALL : AX_MINW_OTHER;
 };
 
+// Coefficient sources of the contractions.  CoefResident reads the basis tables as they are
+// (kernel arguments: the compiler keeps every coefficient it needs in scalar registers).
+// CoefReload reads them through a pointer into the kernel-argument segment that is made opaque
+// before each output row, so only one row of coefficients is live in scalar registers at a time
+// (scalar loads from the scalar cache): for orders whose tables do not fit the scalar register
+// file, where keeping them resident would spill them into vector-register lanes.
+template <typename T>
+struct CoefResident {
+    const Basis<T>& b;
+    __device__ __forceinline__ CoefResident row() const { return *this; }
+    __device__ __forceinline__ T D(int q) const { return b.D[q]; }
+    __device__ __forceinline__ T P(int q) const { return b.P[q]; }
+    __device__ __forceinline__ T M(int q) const { return b.M[q]; }
+    __device__ __forceinline__ T Cm(int q) const { return b.Cm[q]; }
+    __device__ __forceinline__ T Rm(int q) const { return b.Rm[q]; }
+};
+
+template <typename KA>
+using KargPtr = const __attribute__((address_space(4))) KA*;
+
+// KA: the kernel's single by-value argument struct, holding a Basis<T> member `bs`.
+template <typename T, typename KA>
+struct CoefReload {
+    KargPtr<KA> k;
+    __device__ __forceinline__ CoefReload row() const
+    {
+        KargPtr<KA> q = k;
+        asm volatile("" : "+s"(q));
+        return CoefReload{q};
+    }
+    __device__ __forceinline__ T D(int q) const { return k->bs.D[q]; }
+    __device__ __forceinline__ T P(int q) const { return k->bs.P[q]; }
+    __device__ __forceinline__ T M(int q) const { return k->bs.M[q]; }
+    __device__ __forceinline__ T Cm(int q) const { return k->bs.Cm[q]; }
+    __device__ __forceinline__ T Rm(int q) const { return k->bs.Rm[q]; }
+};
+
 // out[a] = sum_n D[a][n] in[n]   (TRANS: out[a] = sum_n D[n][a] in[n])
-template <int N1, bool TRANS, typename T>
-__device__ __forceinline__ void contract_full(const Basis<T>& bs, const T* in, T* out)
+template <int N1, bool TRANS, typename T, typename C>
+__device__ __forceinline__ void contract_full(const C& src, const T* in, T* out)
 {
 #pragma unroll
     for (int a = 0; a < N1; ++a) {
+        const C c = src.row();
         T acc = T(0);
 #pragma unroll
-        for (int n = 0; n < N1; ++n) acc = fma(TRANS ? bs.D[n * N1 + a] : bs.D[a * N1 + n], in[n], acc);
+        for (int n = 0; n < N1; ++n) acc = fma(c.D(TRANS ? n * N1 + a : a * N1 + n), in[n], acc);
         out[a] = acc;
     }
 }
@@ -84,9 +122,9 @@ __device__ __forceinline__ void contract_full(const Basis<T>& bs, const T* in, T
 // blocks P and M, see Basis): with ue[n] = in[n] + in[N-n], uo[n] = in[n] - in[N-n],
 //   e[a] = sum_n P[a][n] ue[n],  o[a] = sum_n M[a][n] uo[n],  out[a] = e + o,  out[N-a] = o - e.
 // D^T is centro-antisymmetric too, with blocks M^T and P^T.  2 H^2 FMAs instead of N1^2, and
-// half as many distinct coefficients (they stay in scalar registers).
-template <int N1, bool TRANS, typename T>
-__device__ __forceinline__ void contract_eo(const Basis<T>& bs, const T* in, T* out)
+// half as many distinct coefficients.
+template <int N1, bool TRANS, typename T, typename C>
+__device__ __forceinline__ void contract_eo(const C& src, const T* in, T* out)
 {
     constexpr int H = N1 / 2, N = N1 - 1;
     T ue[H], uo[H];
@@ -97,31 +135,39 @@ __device__ __forceinline__ void contract_eo(const Basis<T>& bs, const T* in, T* 
     }
 #pragma unroll
     for (int a = 0; a < H; ++a) {
+        const C c = src.row();
         T e = T(0), o = T(0);
 #pragma unroll
         for (int n = 0; n < H; ++n) {
-            e = fma(TRANS ? bs.M[n * H + a] : bs.P[a * H + n], ue[n], e);
-            o = fma(TRANS ? bs.P[n * H + a] : bs.M[a * H + n], uo[n], o);
+            e = fma(TRANS ? c.M(n * H + a) : c.P(a * H + n), ue[n], e);
+            o = fma(TRANS ? c.P(n * H + a) : c.M(a * H + n), uo[n], o);
         }
-        if constexpr (N1 % 2 == 1) e = fma(TRANS ? bs.Rm[a] : bs.Cm[a], in[H], e);
+        if constexpr (N1 % 2 == 1) e = fma(TRANS ? c.Rm(a) : c.Cm(a), in[H], e);
         out[a] = e + o;
         out[N - a] = o - e;
     }
     if constexpr (N1 % 2 == 1) {
+        const C c = src.row();
         T m = T(0);
 #pragma unroll
-        for (int n = 0; n < H; ++n) m = fma(TRANS ? bs.Cm[n] : bs.Rm[n], uo[n], m);
+        for (int n = 0; n < H; ++n) m = fma(TRANS ? c.Cm(n) : c.Rm(n), uo[n], m);
         out[H] = m;
     }
+}
+
+template <int N1, bool TRANS, bool EO, typename T, typename C>
+__device__ __forceinline__ void contract(const C& src, const T* in, T* out)
+{
+    if constexpr (EO)
+        contract_eo<N1, TRANS>(src, in, out);
+    else
+        contract_full<N1, TRANS>(src, in, out);
 }
 
 template <int N1, bool TRANS, bool EO, typename T>
 __device__ __forceinline__ void contract(const Basis<T>& bs, const T* in, T* out)
 {
-    if constexpr (EO)
-        contract_eo<N1, TRANS>(bs, in, out);
-    else
-        contract_full<N1, TRANS>(bs, in, out);
+    contract<N1, TRANS, EO>(CoefResident<T>{bs}, in, out);
 }
 
 }  // namespace ax

@@ -50,11 +50,31 @@ struct Tile {
     static constexpr int SLOTS = (BLOCK + NT - 1) / NT;
 };
 
+// Kernel argument block (one by-value struct, so that the contraction tables can also be read
+// through the kernel-argument segment pointer; see CoefReload).
+template <typename T>
+struct AxArgs {
+    int64_t E;
+    int nrhs;
+    const double* geo;
+    const T* Gs;
+    const T* X;
+    T* Y;
+    const int32_t* l2g;
+    int64_t ldg;
+    Basis<T> bs;
+};
+
+// Orders whose contraction tables are read per output row instead of held in scalar registers.
+// (measured on gfx950: the FP64 trilinear kernel at N1 = 10 is faster with resident tables)
+template <int N1, int GEO, typename T>
+constexpr bool reload_coefs() { return sizeof(T) == 8 ? N1 >= (GEO == GEO_TRI ? 11 : 10) : N1 >= 13; }
+
 // (xi_k, w_k) of node k for the pointwise stage
-template <int N1, bool EO, typename T, typename B>
+template <int N1, int GEO, bool EO, typename T, typename B>
 __device__ __forceinline__ void node_xw(const B& bs, const double* sxw, int k, T& t, T& wk)
 {
-    if constexpr (EO && AX_XW_SCALAR) {
+    if constexpr (EO && AX_XW_SCALAR && !reload_coefs<N1, GEO, T>()) {
         const int m = k < N1 - 1 - k ? k : N1 - 1 - k;
         const double x = bs.xi[m];
         t = T(k == m ? x : -x);
@@ -74,13 +94,14 @@ __device__ __forceinline__ P* at_bytes(P* base, uint32_t off)
     return reinterpret_cast<P*>(reinterpret_cast<C*>(base) + off);
 }
 
-// GATHER: X is a global vector [nrhs][ldg] read through the local-to-global map l2g (the Q of
-// Sec. 2.1 fused into the load), so the solver never materialises Q x.
-template <int N1, int GEO, bool EO, bool GATHER, int EPBX, typename T>
-__global__ void __launch_bounds__((Tile<N1, EPBX>::BLOCK), Shape<N1>::MINW)
-ax_local_kernel(int64_t E, int nrhs, const double* __restrict__ geo, const T* __restrict__ Gs,
-                const T* __restrict__ X, T* __restrict__ Y, const Basis<T> bs,
-                const int32_t* __restrict__ l2g, int64_t ldg)
+// Kernel body.  GATHER: X is a global vector [nrhs][ldg] read through the local-to-global map
+// l2g (the Q of Sec. 2.1 fused into the load), so the solver never materialises Q x.  `cs` is the
+// source of the contraction coefficients (CoefResident or CoefReload).
+template <int N1, int GEO, bool EO, bool GATHER, int EPBX, typename T, typename C>
+__device__ __forceinline__ void
+ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __restrict__ Gs,
+              const T* __restrict__ X, T* __restrict__ Y, const Basis<T>& bs,
+              const int32_t* __restrict__ l2g, int64_t ldg, const C& cs)
 {
     using S = Shape<N1>;
     using TL = Tile<N1, EPBX>;
@@ -184,7 +205,7 @@ ax_local_kernel(int64_t E, int nrhs, const double* __restrict__ geo, const T* __
         }
         // P0: t-contraction in registers, then the next item's loads
         T x2[N1];
-        contract<N1, false, EO>(bs, xr, x2);  // x2 = D_t x
+        contract<N1, false, EO>(cs, xr, x2);  // x2 = D_t x
         T xn[N1];
         load_x(eb_n, c_n, xn);
         if (last_col) load_v(eb_n, vr);
@@ -195,12 +216,12 @@ ax_local_kernel(int64_t E, int nrhs, const double* __restrict__ geo, const T* __
             T p[N1], o[N1];
 #pragma unroll
             for (int n = 0; n < N1; ++n) p[n] = A[S::pos(n, ra, rb)];
-            contract<N1, false, EO>(bs, p, o);
+            contract<N1, false, EO>(cs, p, o);
 #pragma unroll
             for (int a = 0; a < N1; ++a) B[S::pos(a, ra, rb)] = o[a];
 #pragma unroll
             for (int n = 0; n < N1; ++n) p[n] = A[S::pos(pa, n, pb)];
-            contract<N1, false, EO>(bs, p, o1);
+            contract<N1, false, EO>(cs, p, o1);
         }
         __syncthreads();
         // P2: x1 -> A; per-element geometry invariants of the home column from the staged vertices
@@ -224,14 +245,14 @@ ax_local_kernel(int64_t E, int nrhs, const double* __restrict__ geo, const T* __
             if constexpr (GEO == GEO_TRI) {
                 T lam;
                 T tk, wk;
-                node_xw<N1, EO>(bs, sxw, k, tk, wk);
+                node_xw<N1, GEO, EO>(bs, sxw, k, tk, wk);
                 tri_adj<T>(tc, tk, wk, g, lam);
                 x0 *= lam;
                 x1 *= lam;
                 xx2 *= lam;
             } else if constexpr (GEO == GEO_PARA) {
                 T tk, wk;
-                node_xw<N1, EO>(bs, sxw, k, tk, wk);
+                node_xw<N1, GEO, EO>(bs, sxw, k, tk, wk);
 #pragma unroll
                 for (int q = 0; q < 6; ++q) g[q] = T(h[q]) * wk;
             } else {
@@ -244,19 +265,19 @@ ax_local_kernel(int64_t E, int nrhs, const double* __restrict__ geo, const T* __
             tt[k] = fma(g[2], x0, fma(g[4], x1, g[5] * xx2));
         }
         T y2[N1];
-        contract<N1, true, EO>(bs, tt, y2);  // D_t^T t
+        contract<N1, true, EO>(cs, tt, y2);  // D_t^T t
         __syncthreads();
         // P4: D_r^T r in place on the r-pencils; D_s^T s into registers
         {
             T p[N1], o[N1];
 #pragma unroll
             for (int n = 0; n < N1; ++n) p[n] = B[S::pos(n, ra, rb)];
-            contract<N1, true, EO>(bs, p, o);
+            contract<N1, true, EO>(cs, p, o);
 #pragma unroll
             for (int a = 0; a < N1; ++a) B[S::pos(a, ra, rb)] = o[a];
 #pragma unroll
             for (int n = 0; n < N1; ++n) p[n] = A[S::pos(pa, n, pb)];
-            contract<N1, true, EO>(bs, p, o1);
+            contract<N1, true, EO>(cs, p, o1);
 #if AX_MERGE_RS
             // each s-pencil is read and written by its own lane only
 #pragma unroll
@@ -297,6 +318,25 @@ ax_local_kernel(int64_t E, int nrhs, const double* __restrict__ geo, const T* __
     }
 }
 
+// Entry points: the tables of orders that fit the scalar register file stay resident; the
+// others are reloaded per output row through the kernel-argument segment (one struct argument).
+template <int N1, int GEO, bool EO, bool GATHER, int EPBX, typename T>
+__global__ void __launch_bounds__((Tile<N1, EPBX>::BLOCK), Shape<N1>::MINW)
+ax_local_kernel(int64_t E, int nrhs, const double* __restrict__ geo, const T* __restrict__ Gs,
+                const T* __restrict__ X, T* __restrict__ Y, const Basis<T> bs,
+                const int32_t* __restrict__ l2g, int64_t ldg)
+{
+    ax_local_body<N1, GEO, EO, GATHER, EPBX, T>(E, nrhs, geo, Gs, X, Y, bs, l2g, ldg, CoefResident<T>{bs});
+}
+
+template <int N1, int GEO, bool EO, bool GATHER, int EPBX, typename T>
+__global__ void __launch_bounds__((Tile<N1, EPBX>::BLOCK), Shape<N1>::MINW)
+ax_local_kernel_rl(const AxArgs<T> ka)
+{
+    const CoefReload<T, AxArgs<T>> cs{(KargPtr<AxArgs<T>>)__builtin_amdgcn_kernarg_segment_ptr()};
+    ax_local_body<N1, GEO, EO, GATHER, EPBX, T>(ka.E, ka.nrhs, ka.geo, ka.Gs, ka.X, ka.Y, ka.bs, ka.l2g, ka.ldg, cs);
+}
+
 template <int N1, int GEO, bool EO, bool GATHER, int EPBX, typename T>
 static int launch_tile(int64_t E, int nrhs, const double* geo, const T* Gs, const T* X, T* Y, const Basis<T>& bs,
                        int grid_mult, hipStream_t st, const int32_t* l2g, int64_t ldg)
@@ -308,8 +348,12 @@ static int launch_tile(int64_t E, int nrhs, const double* geo, const T* Gs, cons
         int dev = 0, c = 256, q = 0;
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev);
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&q, ax_local_kernel<N1, GEO, EO, GATHER, EPBX, T>,
-                                                         TL::BLOCK, 0) != hipSuccess || q < 1)
+        const void* kf;
+        if constexpr (reload_coefs<N1, GEO, T>())
+            kf = reinterpret_cast<const void*>(ax_local_kernel_rl<N1, GEO, EO, GATHER, EPBX, T>);
+        else
+            kf = reinterpret_cast<const void*>(ax_local_kernel<N1, GEO, EO, GATHER, EPBX, T>);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&q, kf, TL::BLOCK, 0) != hipSuccess || q < 1)
             q = 1;
         cus = c;
         per = q;
@@ -320,8 +364,14 @@ static int launch_tile(int64_t E, int nrhs, const double* geo, const T* Gs, cons
     const int64_t cap = (int64_t)cus * per * (grid_mult > 0 ? grid_mult : 1);
     const int64_t blocks = nblk < cap ? nblk : cap;
     if (blocks > 0x7fffffff) return fail(AX_ERR_UNSUPPORTED, "too many elements for one launch");
-    hipLaunchKernelGGL((ax_local_kernel<N1, GEO, EO, GATHER, EPBX, T>), dim3((unsigned)blocks), dim3(TL::BLOCK),
-                       0, st, E, nrhs, geo, Gs, X, Y, bs, l2g, ldg);
+    if constexpr (reload_coefs<N1, GEO, T>()) {
+        const AxArgs<T> ka{E, nrhs, geo, Gs, X, Y, l2g, ldg, bs};
+        hipLaunchKernelGGL((ax_local_kernel_rl<N1, GEO, EO, GATHER, EPBX, T>), dim3((unsigned)blocks),
+                           dim3(TL::BLOCK), 0, st, ka);
+    } else {
+        hipLaunchKernelGGL((ax_local_kernel<N1, GEO, EO, GATHER, EPBX, T>), dim3((unsigned)blocks), dim3(TL::BLOCK),
+                           0, st, E, nrhs, geo, Gs, X, Y, bs, l2g, ldg);
+    }
     return hip_check(hipGetLastError(), "ax_local launch");
 }
 
