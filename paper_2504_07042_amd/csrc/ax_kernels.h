@@ -82,27 +82,51 @@ struct CoefResident {
     __device__ __forceinline__ T M(int q) const { return b.M[q]; }
     __device__ __forceinline__ T Cm(int q) const { return b.Cm[q]; }
     __device__ __forceinline__ T Rm(int q) const { return b.Rm[q]; }
+    __device__ __forceinline__ double xi(int q) const { return b.xi[q]; }
+    __device__ __forceinline__ double w(int q) const { return b.w[q]; }
 };
 
 template <typename KA>
 using KargPtr = const __attribute__((address_space(4))) KA*;
 
-// KA: the kernel's single by-value argument struct, holding a Basis<T> member `bs`.
-template <typename T, typename KA>
+// The tables behind a constant-address-space pointer (the kernel-argument segment, or a device
+// table that the kernel only reads), which keeps the loads on the scalar unit.
+template <typename T>
 struct CoefReload {
-    KargPtr<KA> k;
+    KargPtr<Basis<T>> k;
     __device__ __forceinline__ CoefReload row() const
     {
-        KargPtr<KA> q = k;
+        KargPtr<Basis<T>> q = k;
         asm volatile("" : "+s"(q));
         return CoefReload{q};
     }
-    __device__ __forceinline__ T D(int q) const { return k->bs.D[q]; }
-    __device__ __forceinline__ T P(int q) const { return k->bs.P[q]; }
-    __device__ __forceinline__ T M(int q) const { return k->bs.M[q]; }
-    __device__ __forceinline__ T Cm(int q) const { return k->bs.Cm[q]; }
-    __device__ __forceinline__ T Rm(int q) const { return k->bs.Rm[q]; }
+    __device__ __forceinline__ T D(int q) const { return k->D[q]; }
+    __device__ __forceinline__ T P(int q) const { return k->P[q]; }
+    __device__ __forceinline__ T M(int q) const { return k->M[q]; }
+    __device__ __forceinline__ T Cm(int q) const { return k->Cm[q]; }
+    __device__ __forceinline__ T Rm(int q) const { return k->Rm[q]; }
+    __device__ __forceinline__ double xi(int q) const { return k->xi[q]; }
+    __device__ __forceinline__ double w(int q) const { return k->w[q]; }
 };
+
+// Basis member `bs` of the kernel's single by-value argument struct KA.
+template <typename T, typename KA>
+__device__ __forceinline__ CoefReload<T> karg_coefs()
+{
+    const KargPtr<KA> ka = (KargPtr<KA>)__builtin_amdgcn_kernarg_segment_ptr();
+    return CoefReload<T>{&ka->bs};
+}
+
+// A device pointer that every lane shares (moved to scalar registers), viewed in the constant
+// address space.
+template <typename T>
+__device__ __forceinline__ KargPtr<T> as_constant(const T* p)
+{
+    const uint64_t v = (uint64_t)(uintptr_t)p;
+    const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (KargPtr<T>)(uintptr_t)(lo | (hi << 32));
+}
 
 // out[a] = sum_n D[a][n] in[n]   (TRANS: out[a] = sum_n D[n][a] in[n])
 template <int N1, bool TRANS, typename T, typename C>

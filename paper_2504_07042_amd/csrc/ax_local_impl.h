@@ -32,6 +32,11 @@
 #ifndef AX_XW_SCALAR
 #define AX_XW_SCALAR 1
 #endif
+// 1: the trilinear per-element prelude runs at the start of each item (fewest live registers);
+// 0: between the forward r/s contractions and the pointwise stage.
+#ifndef AX_EARLY_PRELUDE
+#define AX_EARLY_PRELUDE 1
+#endif
 // 1: the s-direction transpose contraction goes back to LDS in place and the output stage sums
 // the two fields (one barrier and one read-modify-write pass fewer); 0: it is added into the
 // r-field through a separate pass.
@@ -187,6 +192,9 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
     load_v(eb, vr);
     stage(xr, vr, true);
 
+    // where the trilinear prelude runs: at the item start (before the prefetch registers are
+    // live) or between the forward r/s contractions and the pointwise stage
+    constexpr bool EARLY = AX_EARLY_PRELUDE;
     TriCoef tc;
     double h[6];
     while (eb < nblk) {
@@ -203,13 +211,25 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
                 for (int q = 0; q < 6; ++q) h[q] = he[q] * wij;
             }
         }
-        // P0: t-contraction in registers, then the next item's loads
+        // P0: (per-element geometry invariants of the home column from the staged vertices, at
+        // the point of the item where the fewest registers are live,) t-contraction in
+        // registers, then the next item's loads
+        if constexpr (EARLY) {
+            __syncthreads();
+            if constexpr (GEO == GEO_TRI) {
+                if (c == 0) {
+                    const double* sv = svert + (slot < EPB ? slot : 0) * 24;
+                    tri_prelude([&](int v, int q) { return sv[v * 3 + q]; }, sxw[2 * i], sxw[2 * j],
+                                sxw[2 * i + 1], sxw[2 * j + 1], tc);
+                }
+            }
+        }
         T x2[N1];
         contract<N1, false, EO>(cs, xr, x2);  // x2 = D_t x
         T xn[N1];
         load_x(eb_n, c_n, xn);
         if (last_col) load_v(eb_n, vr);
-        __syncthreads();
+        if constexpr (!EARLY) __syncthreads();
         // P1: r-pencils (j,k) -> x0 in B; s-pencils (i,k) -> x1 held in registers
         T o1[N1];
         {
@@ -224,10 +244,10 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
             contract<N1, false, EO>(cs, p, o1);
         }
         __syncthreads();
-        // P2: x1 -> A; per-element geometry invariants of the home column from the staged vertices
+        // P2: x1 -> A; (per-element geometry invariants of the home column from the staged vertices)
 #pragma unroll
         for (int a = 0; a < N1; ++a) A[S::pos(pa, a, pb)] = o1[a];
-        if constexpr (GEO == GEO_TRI) {
+        if constexpr (GEO == GEO_TRI && !EARLY) {
             if (c == 0) {
                 const double* sv = svert + (slot < EPB ? slot : 0) * 24;
                 tri_prelude([&](int v, int q) { return sv[v * 3 + q]; }, sxw[2 * i], sxw[2 * j], sxw[2 * i + 1],
@@ -333,7 +353,7 @@ template <int N1, int GEO, bool EO, bool GATHER, int EPBX, typename T>
 __global__ void __launch_bounds__((Tile<N1, EPBX>::BLOCK), Shape<N1>::MINW)
 ax_local_kernel_rl(const AxArgs<T> ka)
 {
-    const CoefReload<T, AxArgs<T>> cs{(KargPtr<AxArgs<T>>)__builtin_amdgcn_kernarg_segment_ptr()};
+    const CoefReload<T> cs = karg_coefs<T, AxArgs<T>>();
     ax_local_body<N1, GEO, EO, GATHER, EPBX, T>(ka.E, ka.nrhs, ka.geo, ka.Gs, ka.X, ka.Y, ka.bs, ka.l2g, ka.ldg, cs);
 }
 
@@ -375,6 +395,14 @@ static int launch_tile(int64_t E, int nrhs, const double* geo, const T* Gs, cons
     return hip_check(hipGetLastError(), "ax_local launch");
 }
 
+int tri_item_dispatch_f64(int N1, int64_t E, int nrhs, const double* verts, const double* X, double* Y,
+                          const Basis<double>& bs, int grid_mult, hipStream_t st);
+
+// Trilinear FP64 orders served by the per-item kernel (see batched.hip); measured on gfx950
+// it is faster than the prefetching kernel for 9 <= N1 <= 15 and slower at N1 = 8 and 16.
+template <int N1, int GEO, typename T>
+constexpr bool use_item_kernel() { return GEO == GEO_TRI && sizeof(T) == 8 && N1 >= 9 && N1 <= 15; }
+
 template <int N1, int GEO, typename T>
 static int launch_n1(int64_t E, int nrhs, const double* geo, const T* Gs, const T* X, T* Y,
                      const double* D, const double* xi, const double* w, hipStream_t st,
@@ -391,6 +419,10 @@ static int launch_n1(int64_t E, int nrhs, const double* geo, const T* Gs, const 
         if constexpr (GEO != GEO_STORED)
             return launch_tile<N1, GEO, true, true, S::EPB, T>(E, nrhs, geo, Gs, X, Y, bs, tu.grid_mult, st, l2g, ldg);
         return fail(AX_ERR_UNSUPPORTED, "gathering AxLocal needs on-the-fly factors");
+    }
+    if constexpr (use_item_kernel<N1, GEO, T>()) {
+        if (eo && !l2g)
+            return tri_item_dispatch_f64(N1, E, nrhs, geo, (const double*)X, (double*)Y, bs, tu.grid_mult, st);
     }
     if (!eo)
         return launch_tile<N1, GEO, false, false, S::EPB, T>(E, nrhs, geo, Gs, X, Y, bs, tu.grid_mult, st, nullptr, 0);

@@ -69,8 +69,9 @@ struct BHeader {
     int pad;
 };
 
-template <int N1, typename T>
-__device__ void batched_item(const BMesh& m, int64_t eb, int nrhs, const Basis<T>& bs, char* lds)
+// cs: source of the basis tables (CoefResident or CoefReload)
+template <int N1, typename T, typename C>
+__device__ __forceinline__ void batched_item(const BMesh& m, int64_t eb, int nrhs, const C& cs, char* lds)
 {
     using S = BShape<N1>;
     constexpr int NT = S::NT, EPB = S::EPB, FS = S::FS, NP = S::NP;
@@ -97,7 +98,8 @@ __device__ void batched_item(const BMesh& m, int64_t eb, int nrhs, const Basis<T
     TriCoef tc;
     if (inslot) {
         const double* sv = svert + slot * 24;
-        tri_prelude([&](int v, int q) { return sv[v * 3 + q]; }, bs.xi[i], bs.xi[j], bs.w[i], bs.w[j], tc);
+        const C b = cs.row();
+        tri_prelude([&](int v, int q) { return sv[v * 3 + q]; }, b.xi(i), b.xi(j), b.w(i), b.w(j), tc);
     }
     for (int c = 0; c < nrhs; ++c) {
         const int64_t base = (int64_t)c * m.ld + (active ? e : 0) * NP;
@@ -108,19 +110,19 @@ __device__ void batched_item(const BMesh& m, int64_t eb, int nrhs, const Basis<T
 #pragma unroll
             for (int k = 0; k < N1; ++k) A[Shape<N1>::pos(i, j, k)] = xr[k];
         }
-        contract<N1, false, true>(bs, xr, x2);
+        contract<N1, false, true>(cs, xr, x2);
         __syncthreads();
         T o1[N1];
         if (inslot) {
             T p[N1], o[N1];
 #pragma unroll
             for (int n = 0; n < N1; ++n) p[n] = A[Shape<N1>::pos(n, pa, pb)];
-            contract<N1, false, true>(bs, p, o);
+            contract<N1, false, true>(cs, p, o);
 #pragma unroll
             for (int a = 0; a < N1; ++a) B[Shape<N1>::pos(a, pa, pb)] = o[a];
 #pragma unroll
             for (int n = 0; n < N1; ++n) p[n] = A[Shape<N1>::pos(pa, n, pb)];
-            contract<N1, false, true>(bs, p, o1);
+            contract<N1, false, true>(cs, p, o1);
         }
         __syncthreads();
         if (inslot) {
@@ -135,7 +137,8 @@ __device__ void batched_item(const BMesh& m, int64_t eb, int nrhs, const Basis<T
                 const int l = Shape<N1>::pos(i, j, k);
                 T x0 = B[l], x1 = A[l], xx2 = x2[k];
                 T g[6], lam;
-                tri_adj<T>(tc, T(bs.xi[k]), T(bs.w[k]), g, lam);
+                const C b = cs.row();
+                tri_adj<T>(tc, T(b.xi(k)), T(b.w(k)), g, lam);
                 x0 *= lam;
                 x1 *= lam;
                 xx2 *= lam;
@@ -148,18 +151,18 @@ __device__ void batched_item(const BMesh& m, int64_t eb, int nrhs, const Basis<T
             for (int k = 0; k < N1; ++k) tt[k] = T(0);
         }
         T y2[N1];
-        contract<N1, true, true>(bs, tt, y2);
+        contract<N1, true, true>(cs, tt, y2);
         __syncthreads();
         if (inslot) {
             T p[N1], o[N1];
 #pragma unroll
             for (int n = 0; n < N1; ++n) p[n] = B[Shape<N1>::pos(n, pa, pb)];
-            contract<N1, true, true>(bs, p, o);
+            contract<N1, true, true>(cs, p, o);
 #pragma unroll
             for (int a = 0; a < N1; ++a) B[Shape<N1>::pos(a, pa, pb)] = o[a];
 #pragma unroll
             for (int n = 0; n < N1; ++n) p[n] = A[Shape<N1>::pos(pa, n, pb)];
-            contract<N1, true, true>(bs, p, o1);
+            contract<N1, true, true>(cs, p, o1);
         }
         __syncthreads();
         if (inslot) {
@@ -188,18 +191,76 @@ batched_kernel(const char* __restrict__ ws)
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const BItem item = items[it];
         const BMesh m = meshes[item.mesh];
-        const Basis<T>& bs = bases[m.N1 - 2];
+        // (measured on gfx950: resident tables beat per-row reloads here despite the spills)
+        const CoefResident<T> cs{bases[m.N1 - 2]};
         switch (m.N1) {
-        case 2: batched_item<2, T>(m, item.eb, nrhs, bs, lds); break;
-        case 3: batched_item<3, T>(m, item.eb, nrhs, bs, lds); break;
-        case 4: batched_item<4, T>(m, item.eb, nrhs, bs, lds); break;
-        case 5: batched_item<5, T>(m, item.eb, nrhs, bs, lds); break;
-        case 6: batched_item<6, T>(m, item.eb, nrhs, bs, lds); break;
-        case 7: batched_item<7, T>(m, item.eb, nrhs, bs, lds); break;
-        case 8: batched_item<8, T>(m, item.eb, nrhs, bs, lds); break;
-        case 9: batched_item<9, T>(m, item.eb, nrhs, bs, lds); break;
-        default: batched_item<10, T>(m, item.eb, nrhs, bs, lds); break;
+        case 2: batched_item<2, T>(m, item.eb, nrhs, cs, lds); break;
+        case 3: batched_item<3, T>(m, item.eb, nrhs, cs, lds); break;
+        case 4: batched_item<4, T>(m, item.eb, nrhs, cs, lds); break;
+        case 5: batched_item<5, T>(m, item.eb, nrhs, cs, lds); break;
+        case 6: batched_item<6, T>(m, item.eb, nrhs, cs, lds); break;
+        case 7: batched_item<7, T>(m, item.eb, nrhs, cs, lds); break;
+        case 8: batched_item<8, T>(m, item.eb, nrhs, cs, lds); break;
+        case 9: batched_item<9, T>(m, item.eb, nrhs, cs, lds); break;
+        default: batched_item<10, T>(m, item.eb, nrhs, cs, lds); break;
         }
+    }
+}
+
+// The per-item path above as a single-mesh persistent kernel (no work list): work-group g takes
+// element groups g, g + grid, ...  Used by ax_local for the trilinear FP64 orders whose register
+// footprint the prefetching kernel exceeds (N1 = 9..15: 118-162 VGPRs here against 256 plus
+// spills there; measured 1.4-3.2x faster), with the tables reloaded per output row.
+template <typename T>
+struct ItemArgs {
+    BMesh m;
+    int nrhs;
+    Basis<T> bs;
+};
+
+template <int N1, typename T>
+__global__ void __launch_bounds__(kBBlock, 2)
+tri_item_kernel(const ItemArgs<T> a)
+{
+    __shared__ __attribute__((aligned(16))) char lds[BShape<N1>::template lds_bytes<T>()];
+    const int64_t ng = (a.m.E + BShape<N1>::EPB - 1) / BShape<N1>::EPB;
+    const CoefReload<T> cs = karg_coefs<T, ItemArgs<T>>();
+    for (int64_t eb = blockIdx.x; eb < ng; eb += gridDim.x) batched_item<N1, T>(a.m, eb, a.nrhs, cs, lds);
+}
+
+template <int N1, typename T>
+static int tri_item_launch(int64_t E, int nrhs, const double* verts, const T* X, T* Y, const Basis<T>& bs,
+                           int grid_mult, hipStream_t st)
+{
+    static int per = 0, cus = 0;
+    if (per == 0) {
+        int dev = 0, c = 256, q = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&q, tri_item_kernel<N1, T>, kBBlock, 0) != hipSuccess || q < 1)
+            q = 1;
+        cus = c;
+        per = q;
+    }
+    const int64_t ng = (E + BShape<N1>::EPB - 1) / BShape<N1>::EPB;
+    const int64_t cap = (int64_t)cus * per * (grid_mult > 0 ? grid_mult : 1);
+    const int64_t blocks = ng < cap ? ng : cap;
+    if (blocks <= 0) return AX_OK;
+    const ItemArgs<T> a{BMesh{E, E * N1 * N1 * N1, verts, X, Y, N1, 0}, nrhs, bs};
+    hipLaunchKernelGGL((tri_item_kernel<N1, T>), dim3((unsigned)blocks), dim3(kBBlock), 0, st, a);
+    return hip_check(hipGetLastError(), "ax_local (item kernel) launch");
+}
+
+int tri_item_dispatch_f64(int N1, int64_t E, int nrhs, const double* verts, const double* X, double* Y,
+                          const Basis<double>& bs, int grid_mult, hipStream_t st)
+{
+    switch (N1) {
+#define AX_ITEM_CASE(n) \
+    case n: return tri_item_launch<n, double>(E, nrhs, verts, X, Y, bs, grid_mult, st);
+        AX_ITEM_CASE(8) AX_ITEM_CASE(9) AX_ITEM_CASE(10) AX_ITEM_CASE(11) AX_ITEM_CASE(12) AX_ITEM_CASE(13)
+        AX_ITEM_CASE(14) AX_ITEM_CASE(15) AX_ITEM_CASE(16)
+#undef AX_ITEM_CASE
+    default: return fail(AX_ERR_UNSUPPORTED, "item kernel for N1=%d", N1);
     }
 }
 
