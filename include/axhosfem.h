@@ -228,8 +228,9 @@ int cg_solve(const ax_problem* p, int nrhs, const double* b, double* x, const ax
 
 /*
  * Batched AxLocal over many independent trilinear meshes of uneven E and order N (1 <= N <= 9),
- * each with nrhs columns, in ONE persistent kernel launch (the n_col / multi-column reuse of
- * Sec. 4.1 extended to many meshes).  Only E, N, geom (must be AX_TRILINEAR), geo, D, xi, w of
+ * each with nrhs columns, in one persistent kernel launch per order present (the n_col /
+ * multi-column reuse of Sec. 4.1 extended to many meshes), each kernel walking the work items of
+ * its order.  Only E, N, geom (must be AX_TRILINEAR), geo, D, xi, w of
  * each ax_problem are read; D must be a GLL differentiation matrix (centro-antisymmetric).
  *
  * ax_batched_workspace_bytes - [host] device workspace needed for this set of meshes.
@@ -239,14 +240,19 @@ int cg_solve(const ax_problem* p, int nrhs, const double* b, double* x, const ax
  *   starts at X[m] + c * col_stride[m] (col_stride may be NULL: E_m * N1_m^3)) and the GLL tables into
  *   `workspace` [dev]; fills the host `plan`.  The workspace must stay untouched while it is
  *   in use; X/Y pointers are baked in (re-prepare to change them).
- * ax_local_batched - enqueue the single persistent launch described by plan + workspace.  It
- *   reads nothing from the host beyond `plan`, so it can be captured in a HIP graph and replayed.
+ * ax_local_batched - enqueue the persistent launches described by plan + workspace (one per
+ *   order, on `stream`).  They read nothing from the host beyond `plan`, so they can be captured
+ *   in a HIP graph and replayed.
  */
 typedef struct {
     int64_t n_items;  /* work items (element groups) over all meshes */
     int nrhs;
     int prec;         /* AX_FP64 or AX_FP32 */
     size_t bytes;     /* workspace bytes in use */
+    int n_mesh;
+    int pad;
+    int64_t order_first[11];  /* items of order N1 = N + 1 (2..10): [order_first[N1], +order_count[N1]) */
+    int64_t order_count[11];
 } ax_batch_plan;
 
 int ax_batched_workspace_bytes(int n_mesh, const ax_problem* meshes, size_t* bytes);

@@ -53,7 +53,8 @@ class AxCgOpts(ctypes.Structure):
 
 
 class AxBatchPlan(ctypes.Structure):
-    _fields_ = [("n_items", _i64), ("nrhs", _int), ("prec", _int), ("bytes", ctypes.c_size_t)]
+    _fields_ = [("n_items", _i64), ("nrhs", _int), ("prec", _int), ("bytes", ctypes.c_size_t),
+                ("n_mesh", _int), ("pad", _int), ("order_first", _i64 * 11), ("order_count", _i64 * 11)]
 
 
 class AxCgReport(ctypes.Structure):

@@ -1,13 +1,16 @@
 // Batched AxLocal: many independent trilinear meshes of uneven size and order (each with nrhs
-// columns) in ONE persistent kernel launch that walks a work list of (mesh, element group)
-// items.  The list is built on the host, ordered by decreasing cost and dealt round-robin to
-// the resident work-groups (longest-processing-time first), so uneven meshes balance without
-// atomics; the launch reads everything from the caller's workspace and is therefore capturable
-// in a HIP graph and replayable.
+// columns).  The host groups the (mesh, element group) work items by order, largest meshes
+// first; the launch runs one persistent 256-thread kernel per order present, each specialised for
+// its order (register allocation and elements per work-group) and walking its own item list, all
+// enqueued on one stream (one graph node each when captured).  Per-order specialisation, rather
+// than one kernel switching over the order per item, keeps each order's register footprint its
+// own (measured on gfx950: 167 vs 137 GDOF/s in FP64 and 258 vs 207 in FP32 on the 64-mesh
+// batch).  No atomics: the launches read everything from the caller's workspace, so they can be
+// captured in a HIP graph and replayed.
 //
 // Per item the work is the trilinear on-the-fly operator of ax_local (geometric factors of
-// Sec. 3.3 / Algorithm 2, contractions of Algorithm 1), with a 256-thread work-group shape that
-// is the same for every order so that one kernel serves all of them (orders N = 1..9).
+// Sec. 3.3 / Algorithm 2, contractions of Algorithm 1) with the basis tables read per output row
+// (scalar loads from the workspace).
 #include <algorithm>
 #include <cstring>
 #include <vector>
@@ -20,6 +23,22 @@ namespace ax {
 
 constexpr int kBBlock = 256;
 constexpr int kBMaxN1 = 10;
+
+// One mesh of a batch (device descriptor) and one work item (element group eb of mesh `mesh`).
+struct BMesh {
+    int64_t E;
+    int64_t ld;  // stride between columns of X and Y (elements)
+    const double* verts;
+    const void* X;
+    void* Y;
+    int N1;
+    int pad;
+};
+
+struct BItem {
+    int mesh;
+    int eb;  // element group within the mesh
+};
 
 template <int N1>
 struct BShape {
@@ -46,20 +65,6 @@ constexpr size_t bmax_lds()
     return m;
 }
 
-struct BMesh {
-    int64_t E;
-    int64_t ld;  // stride between columns of X and Y (elements)
-    const double* verts;
-    const void* X;
-    void* Y;
-    int N1;
-    int pad;
-};
-
-struct BItem {
-    int mesh;
-    int eb;  // element group within the mesh
-};
 
 struct BHeader {
     int n_mesh, n_items, nrhs, prec;
@@ -178,32 +183,72 @@ __device__ __forceinline__ void batched_item(const BMesh& m, int64_t eb, int nrh
     }
 }
 
-template <typename T>
+// Per-order persistent kernel over the items [0, n) of one order.
+template <int N1, typename T>
 __global__ void __launch_bounds__(kBBlock, 2)
-batched_kernel(const char* __restrict__ ws)
+order_item_kernel(const BItem* __restrict__ items, const BMesh* __restrict__ meshes, int64_t n, int nrhs,
+                  const Basis<T>* __restrict__ bsp)
 {
-    __shared__ __attribute__((aligned(16))) char lds[bmax_lds<T>()];
-    const BHeader* hd = reinterpret_cast<const BHeader*>(ws);
-    const BMesh* meshes = reinterpret_cast<const BMesh*>(ws + hd->off_mesh);
-    const BItem* items = reinterpret_cast<const BItem*>(ws + hd->off_items);
-    const Basis<T>* bases = reinterpret_cast<const Basis<T>*>(ws + hd->off_basis);
-    const int n_items = hd->n_items, nrhs = hd->nrhs;
-    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
-        const BItem item = items[it];
-        const BMesh m = meshes[item.mesh];
-        // (measured on gfx950: resident tables beat per-row reloads here despite the spills)
-        const CoefResident<T> cs{bases[m.N1 - 2]};
-        switch (m.N1) {
-        case 2: batched_item<2, T>(m, item.eb, nrhs, cs, lds); break;
-        case 3: batched_item<3, T>(m, item.eb, nrhs, cs, lds); break;
-        case 4: batched_item<4, T>(m, item.eb, nrhs, cs, lds); break;
-        case 5: batched_item<5, T>(m, item.eb, nrhs, cs, lds); break;
-        case 6: batched_item<6, T>(m, item.eb, nrhs, cs, lds); break;
-        case 7: batched_item<7, T>(m, item.eb, nrhs, cs, lds); break;
-        case 8: batched_item<8, T>(m, item.eb, nrhs, cs, lds); break;
-        case 9: batched_item<9, T>(m, item.eb, nrhs, cs, lds); break;
-        default: batched_item<10, T>(m, item.eb, nrhs, cs, lds); break;
-        }
+    __shared__ __attribute__((aligned(16))) char lds[BShape<N1>::template lds_bytes<T>()];
+    const CoefReload<T> cs{as_constant(bsp)};
+    for (int64_t it = blockIdx.x; it < n; it += gridDim.x) {
+        const BItem q = items[it];
+        batched_item<N1, T>(meshes[q.mesh], q.eb, nrhs, cs, lds);
+    }
+}
+
+// Elements per item of order N1.
+static int order_epb(int N1)
+{
+    switch (N1) {
+    case 2: return BShape<2>::EPB;
+    case 3: return BShape<3>::EPB;
+    case 4: return BShape<4>::EPB;
+    case 5: return BShape<5>::EPB;
+    case 6: return BShape<6>::EPB;
+    case 7: return BShape<7>::EPB;
+    case 8: return BShape<8>::EPB;
+    case 9: return BShape<9>::EPB;
+    default: return BShape<10>::EPB;
+    }
+}
+
+template <int N1, typename T>
+static int order_launch(const char* ws, const BHeader& h, int64_t first, int64_t count, hipStream_t st)
+{
+    const BItem* items = reinterpret_cast<const BItem*>(ws + h.off_items) + first;
+    const BMesh* meshes = reinterpret_cast<const BMesh*>(ws + h.off_mesh);
+    const Basis<T>* bsp = reinterpret_cast<const Basis<T>*>(ws + h.off_basis) + (N1 - 2);
+    const TuneEntry tu = tune_get(N1, GEO_TRI, sizeof(T) == 8 ? AX_FP64 : AX_FP32);
+    static int per = 0, cus = 0;
+    if (per == 0) {
+        int dev = 0, c = 256, q = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&q, order_item_kernel<N1, T>, kBBlock, 0) != hipSuccess || q < 1)
+            q = 1;
+        cus = c;
+        per = q;
+    }
+    const int64_t cap = (int64_t)cus * per * (tu.grid_mult > 0 ? tu.grid_mult : 1);
+    const unsigned grid = (unsigned)std::min<int64_t>(count, cap);
+    hipLaunchKernelGGL((order_item_kernel<N1, T>), dim3(grid), dim3(kBBlock), 0, st, items, meshes, count, h.nrhs, bsp);
+    return hip_check(hipGetLastError(), "batched launch");
+}
+
+template <typename T>
+static int order_dispatch(int N1, const char* ws, const BHeader& h, int64_t first, int64_t count, hipStream_t st)
+{
+    switch (N1) {
+    case 2: return order_launch<2, T>(ws, h, first, count, st);
+    case 3: return order_launch<3, T>(ws, h, first, count, st);
+    case 4: return order_launch<4, T>(ws, h, first, count, st);
+    case 5: return order_launch<5, T>(ws, h, first, count, st);
+    case 6: return order_launch<6, T>(ws, h, first, count, st);
+    case 7: return order_launch<7, T>(ws, h, first, count, st);
+    case 8: return order_launch<8, T>(ws, h, first, count, st);
+    case 9: return order_launch<9, T>(ws, h, first, count, st);
+    default: return order_launch<10, T>(ws, h, first, count, st);
     }
 }
 
@@ -264,26 +309,11 @@ int tri_item_dispatch_f64(int N1, int64_t E, int nrhs, const double* verts, cons
     }
 }
 
-static int epb_of(int N1)
-{
-    switch (N1) {
-    case 2: return BShape<2>::EPB;
-    case 3: return BShape<3>::EPB;
-    case 4: return BShape<4>::EPB;
-    case 5: return BShape<5>::EPB;
-    case 6: return BShape<6>::EPB;
-    case 7: return BShape<7>::EPB;
-    case 8: return BShape<8>::EPB;
-    case 9: return BShape<9>::EPB;
-    default: return BShape<10>::EPB;
-    }
-}
-
 static int64_t n_items_of(int n_mesh, const ax_problem* meshes)
 {
     int64_t n = 0;
     for (int q = 0; q < n_mesh; ++q) {
-        const int e = epb_of(meshes[q].N + 1);
+        const int e = order_epb(meshes[q].N + 1);
         n += (meshes[q].E + e - 1) / e;
     }
     return n;
@@ -310,8 +340,7 @@ static int check_meshes(int n_mesh, const ax_problem* meshes)
         if (p.E > 0 && (!p.geo || !p.D || !p.xi || !p.w)) return fail(AX_ERR_ARG, "mesh %d: NULL array", q);
         if (p.E > 0 && !centro_antisymmetric(p.N + 1, p.D))
             return fail(AX_ERR_UNSUPPORTED, "mesh %d: D must be a GLL differentiation matrix", q);
-        if ((int64_t)((p.E + epb_of(p.N + 1) - 1) / epb_of(p.N + 1)) > 0x7fffffff)
-            return fail(AX_ERR_UNSUPPORTED, "mesh %d too large", q);
+        if (p.E > 0x7fffffffLL) return fail(AX_ERR_UNSUPPORTED, "mesh %d too large", q);
     }
     return AX_OK;
 }
@@ -364,20 +393,21 @@ extern "C" int ax_batched_prepare(int n_mesh, const ax_problem* meshes, int nrhs
         if (ld < meshes[q].E * np) return fail(AX_ERR_ARG, "mesh %d: column stride below E*N1^3", q);
         bm[q] = BMesh{meshes[q].E, ld, meshes[q].geo, X[q], Y[q], meshes[q].N + 1, 0};
     }
-    // items, longest first: cost of a group ~ EPB * N1^4 (the contraction work)
+    // items grouped by order (one persistent kernel each), meshes of an order largest first
     std::vector<BItem> items;
     items.reserve((size_t)n_items);
-    std::vector<std::pair<double, int>> order(n_mesh);
-    for (int q = 0; q < n_mesh; ++q) {
-        const double n1 = meshes[q].N + 1;
-        order[q] = {-(double)epb_of(meshes[q].N + 1) * n1 * n1 * n1 * n1, q};
-    }
-    std::stable_sort(order.begin(), order.end());
-    for (auto& o : order) {
-        const int q = o.second;
-        const int e = epb_of(meshes[q].N + 1);
-        const int64_t groups = (meshes[q].E + e - 1) / e;
-        for (int64_t g = 0; g < groups; ++g) items.push_back(BItem{q, (int)g});
+    for (int N1 = 2; N1 <= kBMaxN1; ++N1) {
+        std::vector<std::pair<int64_t, int>> order;
+        for (int q = 0; q < n_mesh; ++q)
+            if (meshes[q].N + 1 == N1 && meshes[q].E > 0) order.push_back({-meshes[q].E, q});
+        std::stable_sort(order.begin(), order.end());
+        plan->order_first[N1] = (int64_t)items.size();
+        const int e = order_epb(N1);
+        for (auto& o : order) {
+            const int64_t groups = (meshes[o.second].E + e - 1) / e;
+            for (int64_t g = 0; g < groups; ++g) items.push_back(BItem{o.second, (int)g});
+        }
+        plan->order_count[N1] = (int64_t)items.size() - plan->order_first[N1];
     }
     std::memcpy(host.data(), &h, sizeof(h));
     if (n_mesh) std::memcpy(host.data() + h.off_mesh, bm.data(), sizeof(BMesh) * n_mesh);
@@ -398,6 +428,7 @@ extern "C" int ax_batched_prepare(int n_mesh, const ax_problem* meshes, int nrhs
     AX_TRY(hip_check(hipMemcpy(workspace, host.data(), (size_t)h.bytes, hipMemcpyHostToDevice),
                      "batched workspace upload"));
     plan->n_items = n_items;
+    plan->n_mesh = n_mesh;
     plan->nrhs = nrhs;
     plan->prec = prec;
     plan->bytes = (size_t)h.bytes;
@@ -410,18 +441,23 @@ extern "C" int ax_local_batched(const ax_batch_plan* plan, const void* workspace
     if (!plan || !workspace) return fail(AX_ERR_ARG, "plan or workspace is NULL");
     if (plan->prec != AX_FP64 && plan->prec != AX_FP32) return fail(AX_ERR_ARG, "plan was not filled by ax_batched_prepare");
     if (plan->n_items == 0) return AX_OK;
-    int dev = 0, cus = 256, per = 0;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    hipStream_t st = as_stream(stream);
-    if (plan->prec == AX_FP64) {
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_kernel<double>, kBBlock, 0) != hipSuccess || per < 1) per = 1;
-        const int grid = (int)std::min<int64_t>(plan->n_items, (int64_t)cus * per);
-        hipLaunchKernelGGL(batched_kernel<double>, dim3(grid), dim3(kBBlock), 0, st, (const char*)workspace);
-    } else {
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_kernel<float>, kBBlock, 0) != hipSuccess || per < 1) per = 1;
-        const int grid = (int)std::min<int64_t>(plan->n_items, (int64_t)cus * per);
-        hipLaunchKernelGGL(batched_kernel<float>, dim3(grid), dim3(kBBlock), 0, st, (const char*)workspace);
+    BHeader h{};
+    h.off_mesh = h.off_items = h.off_basis = 0;
+    {
+        // offsets are a pure function of the plan: recompute them as ax_batched_prepare did
+        auto up = [](int64_t v) { return (v + 255) & ~int64_t(255); };
+        h.off_mesh = up(sizeof(BHeader));
+        h.off_items = up(h.off_mesh + (int64_t)plan->n_mesh * sizeof(BMesh));
+        h.off_basis = up(h.off_items + plan->n_items * (int64_t)sizeof(BItem));
+        h.nrhs = plan->nrhs;
     }
-    return hip_check(hipGetLastError(), "batched launch");
+    hipStream_t st = as_stream(stream);
+    for (int N1 = 2; N1 <= kBMaxN1; ++N1) {
+        if (plan->order_count[N1] == 0) continue;
+        if (plan->prec == AX_FP64)
+            AX_TRY(order_dispatch<double>(N1, (const char*)workspace, h, plan->order_first[N1], plan->order_count[N1], st));
+        else
+            AX_TRY(order_dispatch<float>(N1, (const char*)workspace, h, plan->order_first[N1], plan->order_count[N1], st));
+    }
+    return AX_OK;
 }
