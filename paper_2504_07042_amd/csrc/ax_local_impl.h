@@ -400,8 +400,11 @@ int tri_item_dispatch_f64(int N1, int64_t E, int nrhs, const double* verts, cons
 
 // Trilinear FP64 orders served by the per-item kernel (see batched.hip); measured on gfx950
 // it is faster than the prefetching kernel for 9 <= N1 <= 15 and slower at N1 = 8 and 16.
+#ifndef AX_ITEM_LO
+#define AX_ITEM_LO 9
+#endif
 template <int N1, int GEO, typename T>
-constexpr bool use_item_kernel() { return GEO == GEO_TRI && sizeof(T) == 8 && N1 >= 9 && N1 <= 15; }
+constexpr bool use_item_kernel() { return GEO == GEO_TRI && sizeof(T) == 8 && N1 >= AX_ITEM_LO && N1 <= 15 && N1 != 8; }
 
 template <int N1, int GEO, typename T>
 static int launch_n1(int64_t E, int nrhs, const double* geo, const T* Gs, const T* X, T* Y,

@@ -302,6 +302,7 @@ int tri_item_dispatch_f64(int N1, int64_t E, int nrhs, const double* verts, cons
     switch (N1) {
 #define AX_ITEM_CASE(n) \
     case n: return tri_item_launch<n, double>(E, nrhs, verts, X, Y, bs, grid_mult, st);
+        AX_ITEM_CASE(2) AX_ITEM_CASE(3) AX_ITEM_CASE(4) AX_ITEM_CASE(5) AX_ITEM_CASE(6) AX_ITEM_CASE(7)
         AX_ITEM_CASE(8) AX_ITEM_CASE(9) AX_ITEM_CASE(10) AX_ITEM_CASE(11) AX_ITEM_CASE(12) AX_ITEM_CASE(13)
         AX_ITEM_CASE(14) AX_ITEM_CASE(15) AX_ITEM_CASE(16)
 #undef AX_ITEM_CASE

@@ -142,7 +142,7 @@ def test_deterministic(ax):
     assert np.array_equal(Y1, Y2)
 
 
-@pytest.mark.parametrize("N,geom", [(7, "tri"), (7, "para"), (3, "tri")])
+@pytest.mark.parametrize("N,geom", [(7, "tri"), (7, "para"), (3, "tri"), (9, "tri"), (11, "para")])
 def test_full_size_sampled(ax, N, geom):
     """At the benchmark's full size (about 2^24 local nodes, same launch as the benchmark),
     compare a random sample of elements with the oracle (AxLocal is element-local)."""
