@@ -122,13 +122,38 @@ cg_scalar_kernel(const double* __restrict__ partials, CgScal* __restrict__ sc, i
     }
 }
 
-// Ap[g] = mask ? 0 : sum of the local copies (ascending local id) and, fused, the partial sums of
-// p . Ap over the same fixed grid as dot_partial_kernel.  Each thread takes kUnroll nodes per
-// tile so that their gathers are in flight together.
-template <typename T, typename IP>
+// The solver's view of Q^T: per global node the first two local copies (ascending local id),
+// built once per solve from the CSR inverse and the Dirichlet mask.  first < 0: the node is
+// masked or has no copy (its sum is 0); second >= 0: the second copy; second == -1: a single
+// copy; second == -2: more than two copies, the rest read through the CSR.  Most nodes of a hex
+// mesh have one or two copies, so their gather is one 8-byte index load and one or two value
+// loads, against three dependent loads (offsets, index, value) through the CSR.
+struct alignas(8) CopyPair {
+    int32_t first, second;
+};
+
+__global__ void __launch_bounds__(256)
+copy_pairs_kernel(CopyPair* __restrict__ cp, const int64_t* __restrict__ gptr, const int32_t* __restrict__ gidx,
+                  const uint8_t* __restrict__ mask, int64_t n_global)
+{
+    for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < n_global; g += (int64_t)gridDim.x * 256) {
+        const int64_t q0 = gptr[g], n = gptr[g + 1] - q0;
+        CopyPair c{-1, -1};
+        if (n > 0 && !(mask && mask[g])) {
+            c.first = gidx[q0];
+            c.second = n == 1 ? -1 : n == 2 ? gidx[q0 + 1] : -2;
+        }
+        cp[g] = c;
+    }
+}
+
+// Ap[g] = mask ? 0 : sum of the local copies (ascending local id, the order of the plain loop)
+// and, fused, the partial sums of p . Ap over the same fixed grid as dot_partial_kernel.  Each
+// thread takes kUnroll nodes per tile so that their loads are in flight together.
+template <typename T>
 __global__ void __launch_bounds__(kRedThreads)
-qt_dot_kernel(int64_t n_local, int64_t n_global, const IP* __restrict__ gptr,
-              const int32_t* __restrict__ gidx, const uint8_t* __restrict__ mask, const T* __restrict__ in,
+qt_dot_kernel(int64_t n_global, const CopyPair* __restrict__ cp, const int64_t* __restrict__ gptr,
+              const int32_t* __restrict__ gidx, int64_t n_local, const T* __restrict__ in,
               const T* __restrict__ pdir, T* __restrict__ out, double* __restrict__ partials)
 {
     const int c = blockIdx.y;
@@ -138,22 +163,31 @@ qt_dot_kernel(int64_t n_local, int64_t n_global, const IP* __restrict__ gptr,
     double acc = 0.0;
     for (int64_t g0 = (int64_t)blockIdx.x * kRedThreads * kUnroll + threadIdx.x; g0 < n_global;
          g0 += (int64_t)gridDim.x * kRedThreads * kUnroll) {
-        T s[kUnroll];
-        int64_t gg[kUnroll];
-        bool ok[kUnroll];
+        CopyPair q[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-            gg[u] = g0 + u * kRedThreads;
-            ok[u] = gg[u] < n_global;
+            const int64_t g = g0 + u * kRedThreads;
+            q[u] = g < n_global ? cp[g] : CopyPair{-1, -1};
         }
-        gather_sums<kUnroll>(gptr, gidx, x, gg, ok, s);
+        T v0[kUnroll], v1[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            v0[u] = q[u].first >= 0 ? x[q[u].first] : T(0);
+            v1[u] = q[u].second >= 0 ? x[q[u].second] : T(0);
+        }
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             const int64_t g = g0 + u * kRedThreads;
             if (g < n_global) {
-                const T v = (mask && mask[g]) ? T(0) : s[u];
-                o[g] = v;
-                acc = fma((double)pd[g], (double)v, acc);
+                T s = T(0) + v0[u];
+                if (q[u].second >= 0) {
+                    s += v1[u];
+                } else if (q[u].second == -2) {
+                    const int64_t e = gptr[g + 1];
+                    for (int64_t k = gptr[g] + 1; k < e; ++k) s += x[gidx[k]];
+                }
+                o[g] = s;
+                acc = fma((double)pd[g], (double)s, acc);
             }
         }
     }
@@ -276,12 +310,6 @@ copy_kernel(T* __restrict__ dst, const T* __restrict__ src, int64_t n)
         dst[q] = src[q];
 }
 
-__global__ void __launch_bounds__(256) narrow_ptr_kernel(int32_t* __restrict__ dst, const int64_t* __restrict__ src, int64_t n)
-{
-    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (int64_t)gridDim.x * 256)
-        dst[q] = (int32_t)src[q];
-}
-
 template <typename T>
 __global__ void __launch_bounds__(256) zero_kernel(T* __restrict__ dst, int64_t n)
 {
@@ -325,7 +353,7 @@ struct CgWork {
     float *b32, *r32, *p32, *Ap32, *d32; // inner global vectors
     float *pl32, *wl32;            // inner local vectors
     double* partials;              // [nrhs][kRedBlocks]
-    int32_t* gptr32;               // [n_global + 1]
+    CopyPair* pairs;               // [n_global]
     CgScal *sc, *sc_in;            // outer / inner scalar state [nrhs]
 };
 
@@ -348,7 +376,7 @@ static void carve(Carver& cv, int64_t nl, int64_t ng, int nrhs, bool mixed, CgWo
         w.b32 = w.r32 = w.p32 = w.Ap32 = w.d32 = w.pl32 = w.wl32 = nullptr;
     }
     w.partials = cv.take<double>((size_t)kRedBlocks * nrhs);
-    w.gptr32 = cv.take<int32_t>(ng + 1);
+    w.pairs = cv.take<CopyPair>(ng);
     w.sc = cv.take<CgScal>(nrhs);
     w.sc_in = cv.take<CgScal>(nrhs);
 }
@@ -360,7 +388,7 @@ struct Operator {
     int64_t n_local = 0, n_global = 0;
     const int32_t* l2g = nullptr;
     const int64_t* gptr = nullptr;
-    const int32_t* gptr32 = nullptr;  // the same offsets narrowed to 32 bits (n_local < 2^31)
+    const CopyPair* pairs = nullptr;  // first two copies per global node, mask applied
     const int32_t* gidx = nullptr;
     const uint8_t* mask = nullptr;
     const ax_problem* p = nullptr;  // single mesh
@@ -432,8 +460,8 @@ static int cg_block(const Operator& op, int nrhs, int prec, TX* x, T* r, T* p, T
     const dim3 g(vgrid(ng), nrhs);
     for (int q = 0; q < count; ++q) {
         AX_TRY(apply_local<T>(op, nrhs, prec, p, pl, wl, st));
-        hipLaunchKernelGGL((qt_dot_kernel<T, int32_t>), dim3(kRedBlocks, nrhs), dim3(kRedThreads), 0, st,
-                           op.n_local, ng, op.gptr32, op.gidx, op.mask, wl, p, Ap, partials);
+        hipLaunchKernelGGL(qt_dot_kernel<T>, dim3(kRedBlocks, nrhs), dim3(kRedThreads), 0, st, ng, op.pairs,
+                           op.gptr, op.gidx, op.n_local, wl, p, Ap, partials);
         AX_TRY(scal(partials, sc, 1, nrhs, st));
         hipLaunchKernelGGL((update_dot_kernel<TX, T>), dim3(kRedBlocks, nrhs), dim3(kRedThreads), 0, st, x, r, p,
                            Ap, sc, ng, partials);
@@ -779,9 +807,9 @@ extern "C" int cg_solve(const ax_problem* p, int nrhs, const double* b, double* 
     op.gidx = p->gidx;
     op.mask = p->mask;
     op.p = p;
-    hipLaunchKernelGGL(narrow_ptr_kernel, dim3(vgrid(p->n_global + 1)), dim3(256), 0, st, w.gptr32, p->gptr,
-                       p->n_global + 1);
-    op.gptr32 = w.gptr32;
+    hipLaunchKernelGGL(copy_pairs_kernel, dim3(vgrid(p->n_global)), dim3(256), 0, st, w.pairs, p->gptr, p->gidx,
+                       p->mask, p->n_global);
+    op.pairs = w.pairs;
     const int status = solve(op, nl, nrhs, b, x, o, rep, w, st);
     if (status != AX_OK && status != AX_ERR_NOT_CONVERGED && status != AX_ERR_BREAKDOWN) {
         (void)hipStreamSynchronize(st);
@@ -891,8 +919,9 @@ extern "C" int cg_solve_batched(int n_mesh, const ax_problem* meshes, int64_t n_
     op.ws64 = ws64;
     op.plan32 = &plan32;
     op.ws32 = ws32;
-    hipLaunchKernelGGL(narrow_ptr_kernel, dim3(vgrid(n_global + 1)), dim3(256), 0, st, w.gptr32, gptr, n_global + 1);
-    op.gptr32 = w.gptr32;
+    hipLaunchKernelGGL(copy_pairs_kernel, dim3(vgrid(n_global)), dim3(256), 0, st, w.pairs, gptr, gidx, mask,
+                       n_global);
+    op.pairs = w.pairs;
     const int status = solve(op, nl, nrhs, b, x, o, rep, w, st);
     if (status != AX_OK && status != AX_ERR_NOT_CONVERGED && status != AX_ERR_BREAKDOWN) {
         (void)hipStreamSynchronize(st);
