@@ -221,7 +221,8 @@ int cg_workspace_bytes(const ax_problem* p, int nrhs, const ax_cg_opts* o, size_
  * convergence flags every 8 iterations, and with use_graph those 8 iterations are captured once
  * in a HIP graph and replayed.  The work runs on a private stream of the calling thread after
  * `stream` has been synchronised, and both are synchronised before returning (rep is filled).
- * Returns AX_OK, AX_ERR_NOT_CONVERGED or AX_ERR_BREAKDOWN (rep->status holds the same).
+ * Returns AX_OK, AX_ERR_NOT_CONVERGED or AX_ERR_BREAKDOWN (rep->status holds the same);
+ * AX_ERR_UNSUPPORTED, before any work, for more than 2^31 - 1 local nodes (local ids are int32).
  */
 int cg_solve(const ax_problem* p, int nrhs, const double* b, double* x, const ax_cg_opts* o,
              ax_cg_report* rep, void* stream);

@@ -573,6 +573,9 @@ static int validate(const ax_problem* p, int nrhs, const ax_cg_opts* o)
     if (p->E > 0 && (!p->geo || !p->D || !p->w || !p->l2g || !p->gptr || !p->gidx))
         return fail(AX_ERR_ARG, "NULL problem array");
     if (p->geom == AX_TRILINEAR && !p->xi) return fail(AX_ERR_ARG, "xi is NULL");
+    const int64_t N1 = p->N + 1;
+    if (p->E > 0x7fffffffLL / (N1 * N1 * N1))
+        return fail(AX_ERR_UNSUPPORTED, "more than 2^31 - 1 local nodes (local ids are int32)");
     return AX_OK;
 }
 
@@ -842,7 +845,12 @@ static int validate_batched(int n_mesh, const ax_problem* meshes, int64_t n_glob
     u.gidx = reinterpret_cast<const int32_t*>(1);
     AX_TRY(validate(&u, nrhs, o));
     size_t bytes = 0;
-    return ax_batched_workspace_bytes(n_mesh, meshes, &bytes);
+    AX_TRY(ax_batched_workspace_bytes(n_mesh, meshes, &bytes));
+    int64_t nl;
+    std::vector<int64_t> lbase;
+    batched_sizes(n_mesh, meshes, nl, lbase);
+    if (nl > 0x7fffffffLL) return fail(AX_ERR_UNSUPPORTED, "more than 2^31 - 1 local nodes (local ids are int32)");
+    return AX_OK;
 }
 
 extern "C" int cg_batched_workspace_bytes(int n_mesh, const ax_problem* meshes, int64_t n_global, int nrhs,

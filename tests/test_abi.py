@@ -115,3 +115,24 @@ def test_tuning_roundtrip(ax):
     assert L.ax_tune_set(16, 0, 0, 0, 1) == ax.AX_ERR_UNSUPPORTED
     assert L.ax_tune_set(7, 3, 0, 0, 1) == ax.AX_ERR_ARG
     assert L.ax_tune_set(7, 0, ax.AX_FP16_ACC32, 0, 1) == ax.AX_ERR_ARG
+
+
+def test_cg_validation(ax):
+    """cg_workspace_bytes validates the problem and options before any GPU work: a local node
+    count beyond int32 local ids, a bad order and bad options are rejected."""
+    L = ax.lib()
+    b = ax.Basis(7)
+    p = ax.AxProblem(E=32768, N=7, geom=ax.AX_TRILINEAR, geo=3, D=ax._np_ptr(b.D), xi=ax._np_ptr(b.xi),
+                     w=ax._np_ptr(b.w), n_global=225 ** 3, l2g=5, gptr=6, gidx=7, mask=None)
+    o = ax.AxCgOpts(rtol=1e-10, max_it=100, inner_prec=ax.AX_FP64, inner_rtol=0.1, max_outer=10,
+                    workspace=None, workspace_bytes=0, use_graph=1, refine=ax.AX_REFINE_RELIABLE)
+    n = ctypes.c_size_t(0)
+    assert L.cg_workspace_bytes(ctypes.byref(p), 1, ctypes.byref(o), ctypes.byref(n)) == ax.AX_OK
+    assert n.value > 8 * 3 * 225 ** 3
+    p.E = (2 ** 31) // 512 + 1          # 2^31 + 512 local nodes
+    assert L.cg_workspace_bytes(ctypes.byref(p), 1, ctypes.byref(o), ctypes.byref(n)) == ax.AX_ERR_UNSUPPORTED
+    p.E, p.N = 64, 16
+    assert L.cg_workspace_bytes(ctypes.byref(p), 1, ctypes.byref(o), ctypes.byref(n)) == ax.AX_ERR_UNSUPPORTED
+    p.N = 3
+    o.rtol = 0.0
+    assert L.cg_workspace_bytes(ctypes.byref(p), 1, ctypes.byref(o), ctypes.byref(n)) == ax.AX_ERR_ARG
