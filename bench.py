@@ -30,18 +30,22 @@ PEAK_FP32_TFS = 157.3
 
 def flops_per_element(N, geom="tri", nrhs=1):
     """Per-element FLOPs: F_ax (Table 2, Poisson) per column plus F_geo (Table 3): trilinear
-    72 N1 + 45 N1^2 + 80 N1^3, parallelepiped 7 N1^3, stored factors 0."""
+    72 N1 + 45 N1^2 + 80 N1^3, trilinear with partial recomputation 72 N1 + 45 N1^2 + 60 N1^3,
+    parallelepiped 7 N1^3, stored factors 0."""
     N1 = N + 1
     f_ax = 12 * N1**4 + 15 * N1**3
-    f_geo = {"tri": 72 * N1 + 45 * N1**2 + 80 * N1**3, "para": 7 * N1**3, "stored": 0}[geom]
+    f_geo = {"tri": 72 * N1 + 45 * N1**2 + 80 * N1**3, "partial": 72 * N1 + 45 * N1**2 + 60 * N1**3,
+             "para": 7 * N1**3, "stored": 0}[geom]
     return nrhs * f_ax, f_geo
 
 
 def bytes_per_element(N, geom="tri", nrhs=1, fpsize=8):
     """Algorithmic HBM bytes per element: X read + Y write (nrhs columns) plus the geometry input
-    (24 vertex words, 6 h words, or 6 N1^3 stored factors); D is cache-resident."""
+    (24 vertex words; plus N1^3 scale words with partial recomputation; 6 h words; or 6 N1^3
+    stored factors); D is cache-resident."""
     N1 = N + 1
-    geo = {"tri": 24 * 8, "para": 6 * 8, "stored": 6 * N1**3 * fpsize}[geom]
+    geo = {"tri": 24 * 8, "partial": 24 * 8 + N1**3 * fpsize, "para": 6 * 8,
+           "stored": 6 * N1**3 * fpsize}[geom]
     return 2 * nrhs * N1**3 * fpsize + geo
 
 
@@ -188,12 +192,18 @@ def order_sweep(ax, meshgen, dev, orders=(3, 5, 7, 9, 11, 15), steps=20, warmup=
             _, per_g = time_steps(lambda q: ax.ax_local_precomputedG(X[q], G, b, prec, out=Y[q]), steps, warmup, 2)
             del G
             g_st = row["local_dofs"] / per_g.mean() / 1e9
+            lam = ax.geom_lambda(V, b, prec)
+            _, per_p = time_steps(lambda q: ax.ax_local_partial(X[q], V, lam, b, prec, out=Y[q]), steps, warmup, 2)
+            del lam
+            g_pa = row["local_dofs"] / per_p.mean() / 1e9
+            r_pa, _ = roofline_gdofs(N, "partial", fpsize, peak)
             r_fly, bound_fly = roofline_gdofs(N, "tri", fpsize, peak)
             r_st, bound_st = roofline_gdofs(N, "stored", fpsize, peak)
             row[pname] = {"on_the_fly_GDOFs": round(g_fly, 1), "R_eff_GDOFs": round(r_fly, 1), "bound": bound_fly,
                           "pct_of_R_eff": round(g_fly / r_fly, 3), "stored_GDOFs": round(g_st, 1),
                           "R_orig_GDOFs": round(r_st, 1), "pct_of_R_orig": round(g_st / r_st, 3),
-                          "speedup_vs_stored": round(g_fly / g_st, 2)}
+                          "speedup_vs_stored": round(g_fly / g_st, 2),
+                          "partial_GDOFs": round(g_pa, 1), "R_partial_GDOFs": round(r_pa, 1)}
         rows.append(row)
         del X64, V
         torch.cuda.empty_cache()
@@ -404,6 +414,24 @@ def main(argv=None):
                                    "R_orig_GDOFs": round(dofs / (byg * E / (PEAK_HBM_GBS * 1e9)) / 1e9, 1)}
         extras["speedup_on_the_fly_vs_stored"] = round(wall_g / wall, 3)
         del G
+        # partial recomputation (Sec. 4.2.1): the per-node scale read from memory
+        lam = ax.geom_lambda(V, b, ax.AX_FP64)
+
+        def step_p(q):
+            ax.ax_local_partial(Xs[q], V, lam, b, ax.AX_FP64, out=Ys[q])
+
+        wall_p, per_p = time_steps(step_p, args.steps, args.warmup, NBUF)
+        fa_p, fg_p = flops_per_element(N, "partial")
+        byp = bytes_per_element(N, "partial")
+        r_p, bound_p = roofline_gdofs(N, "partial")
+        extras["partial_recompute_fp64"] = {
+            "GDOFs": round(dofs * args.steps / wall_p / 1e9, 3),
+            "TFLOPs": round((fa_p + fg_p) * E / per_p.mean() / 1e12, 3),
+            "hbm_GBs": round(byp * E / per_p.mean() / 1e9, 1),
+            "R_eff_GDOFs": round(r_p, 1), "bound": bound_p,
+            "pct_of_R_eff": round(dofs / per_p.mean() / 1e9 / r_p, 4),
+            "vs_full_recompute": round(wall / wall_p, 3)}
+        del lam
         # FP32 on-the-fly on the same mesh
         X32 = [x.float() for x in Xs]
         Y32 = [y.float() for y in Ys]

@@ -106,6 +106,29 @@ int ax_local_precomputedG(int64_t E, int N, const void* G, const double* D, int 
                           const void* X, void* Y, void* stream);
 
 /*
+ * ax_local_partial - the trilinear operator with partial recomputation (Sec. 4.2.1, Table 3,
+ * the Poisson form): the per-node scale lam = 0.125 w_i w_j w_k / det(8J) of Eq. (12) is read
+ * from memory and the kernel recomputes only K = (8J)^T (8J) and adj(K) per node, with no
+ * determinant and no division (F_geo = 72 N1 + 45 N1^2 + 60 N1^3 per element, one more word per
+ * node of traffic).  verts [dev] double [E][8][3] as ax_local; lam [dev] [E][N1^3], double for
+ * AX_FP64, float for AX_FP32 (written by ax_geom_lambda); prec AX_FP64 or AX_FP32 (AX_FP16_ACC32
+ * -> AX_ERR_UNSUPPORTED); xi, w [host] double[N1]; other arguments and errors as ax_local.
+ */
+int ax_local_partial(int64_t E, int N, const double* verts, const void* lam, const double* D,
+                     const double* xi, const double* w, int nrhs, int prec, const void* X, void* Y,
+                     void* stream);
+
+/*
+ * ax_geom_lambda - set-up for ax_local_partial: lam [dev] [E][N1^3] = 0.125 w_i w_j w_k / det(8J)
+ * at every node of the trilinear elements (8J: the Jacobian of Eq. 9 without its factor 1/8, as
+ * in Algorithm 2), double if prec == AX_FP64, float if AX_FP32.  verts [dev] double [E][8][3];
+ * xi, w [host] double[N1].  AX_ERR_ARG for NULL arrays, AX_ERR_UNSUPPORTED for N outside [1,15]
+ * or another prec.  Asynchronous on `stream`.
+ */
+int ax_geom_lambda(int64_t E, int N, const double* verts, const double* xi, const double* w, int prec,
+                   void* lam, void* stream);
+
+/*
  * ax_geom_factors - set-up: write the stored factors of Eq. (7) for trilinear elements,
  * G [dev] [E][6][N1^3] (double if prec == AX_FP64, float if AX_FP32) and, if gwj is not NULL,
  * gwj [dev] double [E][N1^3] = w_i w_j w_k det J (the lumped mass, second factor of Eq. 7).

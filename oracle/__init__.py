@@ -105,6 +105,15 @@ def geom_factors(verts, N: int, xi, w):
     return G, gwj, mind.value
 
 
+def lambda_geo(verts, N: int, xi, w) -> np.ndarray:
+    """Per-node scale of the partial recomputation (Sec. 4.2.1; the lambda of Eq. 12):
+    lam = 0.125 w_i w_j w_k / det(8J) = w_i w_j w_k / (4096 det J) [E][N1^3], with det J taken
+    from the lumped mass gwj = w_i w_j w_k det J of geom_factors (Eq. 7, J from Eq. 9)."""
+    _, gwj, _ = geom_factors(verts, N, xi, w)
+    W = np.einsum("k,j,i->kji", w, w, w).reshape(-1)
+    return W * W / (4096.0 * gwj)
+
+
 def node_coords(verts, N: int, xi) -> np.ndarray:
     """Physical node coordinates [E][3][N1^3] (Eq. 8)."""
     verts = _c64(verts)

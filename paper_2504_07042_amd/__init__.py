@@ -74,6 +74,8 @@ _SIGS = {
     "ax_local": (_int, [_i64, _int, _int, _vp, _vp, _vp, _vp, _int, _int, _vp, _vp, _vp]),
     "ax_local_precomputedG": (_int, [_i64, _int, _vp, _vp, _int, _int, _vp, _vp, _vp]),
     "ax_geom_factors": (_int, [_i64, _int, _vp, _vp, _vp, _int, _vp, _vp, _vp]),
+    "ax_local_partial": (_int, [_i64, _int, _vp, _vp, _vp, _vp, _vp, _int, _int, _vp, _vp, _vp]),
+    "ax_geom_lambda": (_int, [_i64, _int, _vp, _vp, _vp, _int, _vp, _vp]),
     "ax_parallelepiped_factors": (_int, [_i64, _vp, _vp, _vp]),
     "ax_node_coords": (_int, [_i64, _int, _vp, _vp, _vp, _vp]),
     "gs_build_csr": (_int, [_i64, _i64, _vp, _vp, _vp]),
@@ -191,6 +193,29 @@ def ax_local_precomputedG(X, G, basis: Basis, prec=AX_FP64, out=None, stream=Non
     _check(lib().ax_local_precomputedG(E, basis.N, _dptr(G), _np_ptr(basis.D), nrhs, prec,
                                        _dptr(X), _dptr(Y), _stream(stream)))
     return Y
+
+
+def ax_local_partial(X, verts, lam, basis: Basis, prec=AX_FP64, out=None, stream=None):
+    """Y = AxLocal(X) on trilinear elements with partial recomputation: the per-node scale lam
+    [E][N1^3] (from geom_lambda) is read, K and adj(K) are recomputed (Sec. 4.2.1)."""
+    import torch
+    E = verts.shape[0]
+    nrhs = _nrhs(X, E, basis.N)
+    assert X.dtype == _prec_dtype(prec) and lam.dtype == _prec_dtype(prec) and verts.dtype == torch.float64
+    Y = torch.empty_like(X) if out is None else out
+    _check(lib().ax_local_partial(E, basis.N, _dptr(verts), _dptr(lam), _np_ptr(basis.D), _np_ptr(basis.xi),
+                                  _np_ptr(basis.w), nrhs, prec, _dptr(X), _dptr(Y), _stream(stream)))
+    return Y
+
+
+def geom_lambda(verts, basis: Basis, prec=AX_FP64, stream=None):
+    """Per-node scale lam [E][N1^3] = 0.125 w_i w_j w_k / det(8J) for ax_local_partial."""
+    import torch
+    E = verts.shape[0]
+    lam = torch.empty((E, (basis.N + 1) ** 3), dtype=_prec_dtype(prec), device=verts.device)
+    _check(lib().ax_geom_lambda(E, basis.N, _dptr(verts), _np_ptr(basis.xi), _np_ptr(basis.w), prec,
+                                _dptr(lam), _stream(stream)))
+    return lam
 
 
 def geom_factors(verts, basis: Basis, prec=AX_FP64, want_G=True, want_gwj=False, stream=None):

@@ -6,7 +6,11 @@
 
 namespace ax {
 
-enum { GEO_TRI = 0, GEO_PARA = 1, GEO_STORED = 2 };
+// GEO_TRIL: trilinear with the per-node scale lam = 0.125 w / det(8J) read from memory (the
+// partial recomputation of Sec. 4.2.1): no determinant and no division in the kernel.
+enum { GEO_TRI = 0, GEO_PARA = 1, GEO_STORED = 2, GEO_TRIL = 3 };
+
+constexpr bool is_trilinear(int geo) { return geo == GEO_TRI || geo == GEO_TRIL; }
 
 // Tuning knobs (compile-time): waves per SIMD the register allocation targets for N1 <= 8, and
 // how many times the resident capacity the persistent grid is.

@@ -99,3 +99,21 @@ extern "C" int ax_local_precomputedG(int64_t E, int N, const void* G, const doub
         return axl_dispatch_f32(GEO_STORED, N, E, nrhs, nullptr, (const float*)G, (const float*)X, (float*)Y, D, nullptr, nullptr, st, nullptr, 0);
     return ax_local_f16(E, N, GEO_STORED, nullptr, (const float*)G, D, nullptr, nullptr, nrhs, (const float*)X, (float*)Y, st);
 }
+
+extern "C" int ax_local_partial(int64_t E, int N, const double* verts, const void* lam, const double* D,
+                                const double* xi, const double* w, int nrhs, int prec, const void* X, void* Y,
+                                void* stream)
+{
+    clear_error();
+    AX_TRY(check_common(E, N, nrhs, prec, X, Y, D));
+    if (prec == AX_FP16_ACC32) return fail(AX_ERR_UNSUPPORTED, "partial recomputation is FP64 or FP32");
+    if (!xi || !w) return fail(AX_ERR_ARG, "xi or w is NULL");
+    if (E == 0) return AX_OK;
+    if (!verts || !lam) return fail(AX_ERR_ARG, "verts or lam is NULL");
+    hipStream_t st = as_stream(stream);
+    if (prec == AX_FP64)
+        return axl_dispatch_f64(GEO_TRIL, N, E, nrhs, verts, (const double*)lam, (const double*)X, (double*)Y, D,
+                                xi, w, st, nullptr, 0);
+    return axl_dispatch_f32(GEO_TRIL, N, E, nrhs, verts, (const float*)lam, (const float*)X, (float*)Y, D, xi, w,
+                            st, nullptr, 0);
+}

@@ -73,7 +73,7 @@ struct AxArgs {
 // Orders whose contraction tables are read per output row instead of held in scalar registers.
 // (measured on gfx950: the FP64 trilinear kernel at N1 = 10 is faster with resident tables)
 template <int N1, int GEO, typename T>
-constexpr bool reload_coefs() { return sizeof(T) == 8 ? N1 >= (GEO == GEO_TRI ? 11 : 10) : N1 >= 13; }
+constexpr bool reload_coefs() { return sizeof(T) == 8 ? N1 >= (is_trilinear(GEO) ? 11 : 10) : N1 >= 13; }
 
 // (xi_k, w_k) of node k for the pointwise stage
 template <int N1, int GEO, bool EO, typename T, typename B>
@@ -112,10 +112,10 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
     using TL = Tile<N1, EPBX>;
     constexpr int NT = S::NT, FS = S::FS, NP = S::NP, EPB = TL::EPB;
     constexpr int BLOCK = TL::BLOCK;
-    constexpr int NV = (GEO == GEO_TRI) ? 24 : 0;                // vertex words per element
+    constexpr int NV = is_trilinear(GEO) ? 24 : 0;               // vertex words per element
     constexpr int VPT = (EPB * NV + BLOCK - 1) / BLOCK;          // vertex words per thread
     __shared__ T smem[TL::SLOTS * 2 * FS];
-    __shared__ double svert[(GEO == GEO_TRI) ? EPB * 24 : 1];
+    __shared__ double svert[is_trilinear(GEO) ? EPB * 24 : 1];
     // (xi_k, w_k) pairs: the per-lane (xi_i, w_i), (xi_j, w_j) of the home columns, and xi_k, w_k
     // of the node loop for the kernels that do not keep them in scalar registers
     __shared__ double sxw[2 * N1];
@@ -159,7 +159,7 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
         }
     };
     auto load_v = [&](int64_t ebq, double* dst) {
-        if constexpr (GEO == GEO_TRI) {
+        if constexpr (is_trilinear(GEO)) {
             const int64_t g = clamp_group(ebq);
             const double* src = geo + g * EPB * 24;
             const int64_t lim = (E - g * EPB) * 24;   // vertex words left from the group start
@@ -173,7 +173,7 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
     auto stage = [&](const T* x, const double* v, bool new_elem) {
 #pragma unroll
         for (int k = 0; k < N1; ++k) A[S::pos(i, j, k)] = x[k];
-        if constexpr (GEO == GEO_TRI) {
+        if constexpr (is_trilinear(GEO)) {
             if (new_elem) {
 #pragma unroll
                 for (int q = 0; q < VPT; ++q) {
@@ -216,7 +216,7 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
         // registers, then the next item's loads
         if constexpr (EARLY) {
             __syncthreads();
-            if constexpr (GEO == GEO_TRI) {
+            if constexpr (is_trilinear(GEO)) {
                 if (c == 0) {
                     const double* sv = svert + (slot < EPB ? slot : 0) * 24;
                     tri_prelude([&](int v, int q) { return sv[v * 3 + q]; }, sxw[2 * i], sxw[2 * j],
@@ -247,7 +247,7 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
         // P2: x1 -> A; (per-element geometry invariants of the home column from the staged vertices)
 #pragma unroll
         for (int a = 0; a < N1; ++a) A[S::pos(pa, a, pb)] = o1[a];
-        if constexpr (GEO == GEO_TRI && !EARLY) {
+        if constexpr (is_trilinear(GEO) && !EARLY) {
             if (c == 0) {
                 const double* sv = svert + (slot < EPB ? slot : 0) * 24;
                 tri_prelude([&](int v, int q) { return sv[v * 3 + q]; }, sxw[2 * i], sxw[2 * j], sxw[2 * i + 1],
@@ -267,6 +267,14 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
                 T tk, wk;
                 node_xw<N1, GEO, EO>(bs, sxw, k, tk, wk);
                 tri_adj<T>(tc, tk, wk, g, lam);
+                x0 *= lam;
+                x1 *= lam;
+                xx2 *= lam;
+            } else if constexpr (GEO == GEO_TRIL) {
+                T tk, wk;
+                node_xw<N1, GEO, EO>(bs, sxw, k, tk, wk);
+                const T lam = Gs[(active ? e : 0) * NP + i + j * N1 + k * NT];
+                tri_adj_k<T>(tc, tk, g);
                 x0 *= lam;
                 x1 *= lam;
                 xx2 *= lam;
@@ -416,10 +424,10 @@ static int launch_n1(int64_t E, int nrhs, const double* geo, const T* Gs, const 
     fill_basis(bs, N1, D, xi, w);
     // the even-odd kernels also take the nodes as mirror-symmetric (the factors need none)
     const bool eo = centro_antisymmetric(N1, D) && (GEO == GEO_STORED || symmetric_nodes(N1, xi, w));
-    const TuneEntry tu = tune_get(N1, GEO, sizeof(T) == 8 ? AX_FP64 : AX_FP32);
+    const TuneEntry tu = tune_get(N1, GEO == GEO_TRIL ? GEO_TRI : GEO, sizeof(T) == 8 ? AX_FP64 : AX_FP32);
     if (l2g) {
         if (!eo) return fail(AX_ERR_UNSUPPORTED, "gathering AxLocal needs a GLL differentiation matrix");
-        if constexpr (GEO != GEO_STORED)
+        if constexpr (GEO == GEO_TRI || GEO == GEO_PARA)
             return launch_tile<N1, GEO, true, true, S::EPB, T>(E, nrhs, geo, Gs, X, Y, bs, tu.grid_mult, st, l2g, ldg);
         return fail(AX_ERR_UNSUPPORTED, "gathering AxLocal needs on-the-fly factors");
     }

@@ -34,6 +34,26 @@ geom_factors_kernel(int64_t E, int N1, const double* __restrict__ verts, T* __re
     if (gwj) gwj[idx] = nd.w[i] * nd.w[j] * nd.w[k] * tri_det(tc, nd.xi[k]) * (1.0 / 512.0);
 }
 
+// The per-node scale of the partial recomputation (Sec. 4.2.1): lam = 0.125 w_i w_j w_k / det(8J),
+// the factor that turns adj(K) into the geometric factors (Eq. 12).  One thread per node.
+template <typename T>
+__global__ void __launch_bounds__(256)
+geom_lambda_kernel(int64_t E, int N1, const double* __restrict__ verts, T* __restrict__ lam, const Nodes nd)
+{
+    const int NP = N1 * N1 * N1;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= E * NP) return;
+    const int64_t e = idx / NP;
+    const int l = (int)(idx - e * NP);
+    const int i = l % N1, j = (l / N1) % N1, k = l / (N1 * N1);
+    const double* Ve = verts + e * 24;
+    TriCoef tc;
+    tri_prelude([&](int v, int q) { return Ve[v * 3 + q]; }, nd.xi[i], nd.xi[j], nd.w[i], nd.w[j], tc);
+    double g[6], lm;
+    tri_adj<double>(tc, nd.xi[k], nd.w[k], g, lm);
+    lam[idx] = T(lm);
+}
+
 // h = det J J^-1 J^-T = adj(J^T J) / det J with J = 1/2 [v1 - v0, v2 - v0, v4 - v0] (columns).
 __global__ void __launch_bounds__(256)
 parallelepiped_kernel(int64_t E, const double* __restrict__ verts, double* __restrict__ h)
@@ -122,6 +142,31 @@ extern "C" int ax_geom_factors(int64_t E, int N, const double* verts, const doub
         hipLaunchKernelGGL(geom_factors_kernel<float>, dim3(grid_for(n, 256)), dim3(256), 0, st, E, N1,
                            verts, (float*)G, gwj, nd);
     return hip_check(hipGetLastError(), "ax_geom_factors launch");
+}
+
+extern "C" int ax_geom_lambda(int64_t E, int N, const double* verts, const double* xi, const double* w, int prec,
+                              void* lam, void* stream)
+{
+    clear_error();
+    if (E < 0) return fail(AX_ERR_ARG, "E < 0");
+    if (N < 1 || N > 15) return fail(AX_ERR_UNSUPPORTED, "order N=%d outside [1,15]", N);
+    if (prec != AX_FP64 && prec != AX_FP32) return fail(AX_ERR_UNSUPPORTED, "prec must be FP64 or FP32");
+    if (!xi || !w) return fail(AX_ERR_ARG, "xi or w is NULL");
+    if (E == 0) return AX_OK;
+    if (!verts || !lam) return fail(AX_ERR_ARG, "verts or lam is NULL");
+    const int N1 = N + 1;
+    const int64_t n = E * N1 * N1 * N1;
+    if (n / 256 > 0x7fffffff) return fail(AX_ERR_UNSUPPORTED, "too many nodes");
+    Nodes nd;
+    fill_nodes(nd, N1, xi, w);
+    hipStream_t st = as_stream(stream);
+    if (prec == AX_FP64)
+        hipLaunchKernelGGL(geom_lambda_kernel<double>, dim3(grid_for(n, 256)), dim3(256), 0, st, E, N1, verts,
+                           (double*)lam, nd);
+    else
+        hipLaunchKernelGGL(geom_lambda_kernel<float>, dim3(grid_for(n, 256)), dim3(256), 0, st, E, N1, verts,
+                           (float*)lam, nd);
+    return hip_check(hipGetLastError(), "ax_geom_lambda launch");
 }
 
 extern "C" int ax_parallelepiped_factors(int64_t E, const double* verts, double* h, void* stream)

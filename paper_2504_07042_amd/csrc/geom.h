@@ -119,10 +119,10 @@ __device__ __forceinline__ float recip(float x)
     return fmaf(r, fmaf(-x, r, 1.0f), r);
 }
 
-// Unscaled factors at node t = xi_k: g[6] = adj(K) and lam = 0.125 w_i w_j w_k / det(8J), so
-// that the geometric factors of Eq. (7) are lam * g (Eq. 12).
+// Unscaled factors at node t = xi_k without the Jacobian determinant: g[6] = adj(K).  The
+// partial-recomputation variant (Sec. 4.2.1, Table 3) reads lam per node from memory instead.
 template <typename R>
-__device__ __forceinline__ void tri_adj(const TriCoef& k, R t, R wk, R* g, R& lam)
+__device__ __forceinline__ void tri_adj_k(const TriCoef& k, R t, R* g)
 {
     const R K00 = fma(fma(R(k.q2), t, R(k.q1)), t, R(k.q0));
     const R K11 = fma(fma(R(k.p2), t, R(k.p1)), t, R(k.p0));
@@ -130,14 +130,22 @@ __device__ __forceinline__ void tri_adj(const TriCoef& k, R t, R wk, R* g, R& la
     const R K01 = fma(fma(R(k.m2), t, R(k.m1)), t, R(k.m0));
     const R K02 = fma(R(k.n1), t, R(k.n0));
     const R K12 = fma(R(k.o1), t, R(k.o0));
-    const R det = fma(fma(R(k.d2), t, R(k.d1)), t, R(k.d0));
-    lam = R(k.cw) * wk * recip(det);
     g[0] = fma(K11, K22, -K12 * K12);
     g[1] = fma(K02, K12, -K01 * K22);
     g[2] = fma(K01, K12, -K02 * K11);
     g[3] = fma(K00, K22, -K02 * K02);
     g[4] = fma(K01, K02, -K00 * K12);
     g[5] = fma(K00, K11, -K01 * K01);
+}
+
+// Unscaled factors at node t = xi_k: g[6] = adj(K) and lam = 0.125 w_i w_j w_k / det(8J), so
+// that the geometric factors of Eq. (7) are lam * g (Eq. 12).
+template <typename R>
+__device__ __forceinline__ void tri_adj(const TriCoef& k, R t, R wk, R* g, R& lam)
+{
+    const R det = fma(fma(R(k.d2), t, R(k.d1)), t, R(k.d0));
+    lam = R(k.cw) * wk * recip(det);
+    tri_adj_k(k, t, g);
 }
 
 // det(8J) at node t (for the lumped mass w det J = w det(8J) / 512).

@@ -136,3 +136,19 @@ def test_cg_validation(ax):
     p.N = 3
     o.rtol = 0.0
     assert L.cg_workspace_bytes(ctypes.byref(p), 1, ctypes.byref(o), ctypes.byref(n)) == ax.AX_ERR_ARG
+
+
+def test_partial_validation(ax):
+    """ax_local_partial and ax_geom_lambda reject bad arguments before touching the GPU."""
+    b = ax.Basis(3)
+    L = ax.lib()
+    D, xi, w = ax._np_ptr(b.D), ax._np_ptr(b.xi), ax._np_ptr(b.w)
+    assert L.ax_local_partial(2, 3, None, None, D, xi, w, 1, ax.AX_FP64, 8, 16, None) == ax.AX_ERR_ARG
+    assert L.ax_local_partial(2, 3, 8, 8, D, xi, w, 1, ax.AX_FP16_ACC32, 8, 16, None) == ax.AX_ERR_UNSUPPORTED
+    assert L.ax_local_partial(2, 3, 8, 8, D, None, w, 1, ax.AX_FP64, 8, 16, None) == ax.AX_ERR_ARG
+    assert L.ax_local_partial(2, 16, 8, 8, D, xi, w, 1, ax.AX_FP64, 8, 16, None) == ax.AX_ERR_UNSUPPORTED
+    assert L.ax_local_partial(2, 3, 8, 8, D, xi, w, 1, ax.AX_FP64, 8, 8, None) == ax.AX_ERR_ARG
+    assert L.ax_local_partial(0, 3, None, None, D, xi, w, 1, ax.AX_FP64, None, None, None) == ax.AX_OK
+    assert L.ax_geom_lambda(2, 3, None, xi, w, ax.AX_FP64, 8, None) == ax.AX_ERR_ARG
+    assert L.ax_geom_lambda(2, 3, 8, xi, w, ax.AX_FP16_ACC32, 8, None) == ax.AX_ERR_UNSUPPORTED
+    assert L.ax_geom_lambda(-1, 3, 8, xi, w, ax.AX_FP64, 8, None) == ax.AX_ERR_ARG

@@ -109,6 +109,34 @@ def test_factors_match_adjugate_form(N, jmesh):
             assert gwj[e, l] == pytest.approx(W * d, rel=1e-13)
 
 
+@pytest.mark.parametrize("N", [1, 3, 7])
+def test_lambda_box_closed_form(N):
+    """Partial-recomputation scale on an axis-aligned box: det J = hx hy hz / 8, so
+    lam = 0.125 W / det(8J) = W / (512 hx hy hz)."""
+    hx, hy, hz = 0.3, 0.7, 1.9
+    V = meshgen.box_element(hx, hy, hz, origin=(0.1, -2.0, 5.0))
+    xi, w, _ = oracle.gll(N)
+    lam = oracle.lambda_geo(V, N, xi, w)
+    W = np.einsum("k,j,i->kji", w, w, w).reshape(-1)
+    assert np.allclose(lam[0], W / (512 * hx * hy * hz), rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("N", [2, 5])
+def test_lambda_times_adjugate_is_factors(N, jmesh):
+    """Eq. (12) in the scaling of Algorithm 2: lam * adj((8J)^T (8J)) = G, with J from the
+    independent interpolator (a wrong factor 0.125 or 8 in lam fails here)."""
+    xi, w, _ = oracle.gll(N)
+    G, _, _ = oracle.geom_factors(jmesh.verts, N, xi, w)
+    lam = oracle.lambda_geo(jmesh.verts, N, xi, w)
+    N1 = N + 1
+    for e in (0, jmesh.E - 1):
+        for (i, j, k) in [(0, 0, 0), (N, 1, N - 1), (N // 2, N, 1)]:
+            l = i + j * N1 + k * N1 * N1
+            J8 = 8.0 * _fd_jacobian(jmesh.verts[e], xi[i], xi[j], xi[k])
+            ref = lam[e, l] * _sym6(_adj(J8.T @ J8))
+            assert np.allclose(G[e, :, l], ref, rtol=0, atol=2e-14 * np.abs(G[e, :, l]).max())
+
+
 @pytest.mark.parametrize("N", [2, 4])
 def test_invariances(N, jmesh):
     """Rotation and translation leave G unchanged; uniform scaling by s scales G by s."""
