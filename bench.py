@@ -30,22 +30,23 @@ PEAK_FP32_TFS = 157.3
 
 def flops_per_element(N, geom="tri", nrhs=1):
     """Per-element FLOPs: F_ax (Table 2, Poisson) per column plus F_geo (Table 3): trilinear
-    72 N1 + 45 N1^2 + 80 N1^3, trilinear with partial recomputation 72 N1 + 45 N1^2 + 60 N1^3,
-    parallelepiped 7 N1^3, stored factors 0."""
+    72 N1 + 45 N1^2 + 80 N1^3, trilinear with partial recomputation 72 N1 + 45 N1^2 + 60 N1^3
+    (Helmholtz with merged factors: plus the mass term, 2 N1^3), parallelepiped 7 N1^3, stored
+    factors 0."""
     N1 = N + 1
     f_ax = 12 * N1**4 + 15 * N1**3
     f_geo = {"tri": 72 * N1 + 45 * N1**2 + 80 * N1**3, "partial": 72 * N1 + 45 * N1**2 + 60 * N1**3,
-             "para": 7 * N1**3, "stored": 0}[geom]
+             "helm": 72 * N1 + 45 * N1**2 + 62 * N1**3, "para": 7 * N1**3, "stored": 0}[geom]
     return nrhs * f_ax, f_geo
 
 
 def bytes_per_element(N, geom="tri", nrhs=1, fpsize=8):
     """Algorithmic HBM bytes per element: X read + Y write (nrhs columns) plus the geometry input
-    (24 vertex words; plus N1^3 scale words with partial recomputation; 6 h words; or 6 N1^3
-    stored factors); D is cache-resident."""
+    (24 vertex words; plus N1^3 scale words with partial recomputation, 2 N1^3 merged factors
+    for Helmholtz; 6 h words; or 6 N1^3 stored factors); D is cache-resident."""
     N1 = N + 1
-    geo = {"tri": 24 * 8, "partial": 24 * 8 + N1**3 * fpsize, "para": 6 * 8,
-           "stored": 6 * N1**3 * fpsize}[geom]
+    geo = {"tri": 24 * 8, "partial": 24 * 8 + N1**3 * fpsize, "helm": 24 * 8 + 2 * N1**3 * fpsize,
+           "para": 6 * 8, "stored": 6 * N1**3 * fpsize}[geom]
     return 2 * nrhs * N1**3 * fpsize + geo
 
 
@@ -432,6 +433,27 @@ def main(argv=None):
             "pct_of_R_eff": round(dofs / per_p.mean() / 1e9 / r_p, 4),
             "vs_full_recompute": round(wall / wall_p, 3)}
         del lam
+        # Helmholtz operator with merged scalar factors (Eq. 3, Sec. 4.2.1), seeded coefficient fields
+        rng = np.random.default_rng(11)
+        lam0 = torch.from_numpy(rng.uniform(0.5, 2.0, (E, NP))).to(dev)
+        lam1 = torch.from_numpy(rng.uniform(0.0, 3.0, (E, NP))).to(dev)
+        L23 = ax.helmholtz_factors(V, lam0, lam1, b, ax.AX_FP64)
+        del lam0, lam1
+
+        def step_h(q):
+            ax.ax_local_helmholtz(Xs[q], V, L23, b, ax.AX_FP64, out=Ys[q])
+
+        wall_h, per_h = time_steps(step_h, args.steps, args.warmup, NBUF)
+        fa_h, fg_h = flops_per_element(N, "helm")
+        byh = bytes_per_element(N, "helm")
+        r_h, bound_h = roofline_gdofs(N, "helm")
+        extras["helmholtz_merged_fp64"] = {
+            "GDOFs": round(dofs * args.steps / wall_h / 1e9, 3),
+            "TFLOPs": round((fa_h + fg_h) * E / per_h.mean() / 1e12, 3),
+            "hbm_GBs": round(byh * E / per_h.mean() / 1e9, 1),
+            "R_eff_GDOFs": round(r_h, 1), "bound": bound_h,
+            "pct_of_R_eff": round(dofs / per_h.mean() / 1e9 / r_h, 4)}
+        del L23
         # FP32 on-the-fly on the same mesh
         X32 = [x.float() for x in Xs]
         Y32 = [y.float() for y in Ys]

@@ -119,6 +119,31 @@ int ax_local_partial(int64_t E, int N, const double* verts, const void* lam, con
                      void* stream);
 
 /*
+ * ax_local_helmholtz - the trilinear Helmholtz operator of Eq. (3),
+ *   Y_e = D^T (Lambda0 G_e) D X_e + Lambda1 Gwj X_e,
+ * with the merged scalar factors of Sec. 4.2.1 read per node: Lambda2 = lam lambda0 scales
+ * adj(K) (K, adj(K) recomputed from the vertices as in ax_local_partial) and Lambda3 =
+ * gwj lambda1 scales the mass term; no determinant and no division in the kernel.
+ * L23 [dev] [E][2][N1^3] (Lambda2 block, then Lambda3 block, per element), double for AX_FP64,
+ * float for AX_FP32 (written by ax_helmholtz_factors); prec AX_FP64 or AX_FP32 (AX_FP16_ACC32
+ * -> AX_ERR_UNSUPPORTED); other arguments and errors as ax_local_partial.
+ */
+int ax_local_helmholtz(int64_t E, int N, const double* verts, const void* L23, const double* D,
+                       const double* xi, const double* w, int nrhs, int prec, const void* X, void* Y,
+                       void* stream);
+
+/*
+ * ax_helmholtz_factors - set-up for ax_local_helmholtz (Sec. 4.2.1): from the nodal values of
+ * the coefficient fields lambda0, lambda1 [dev] double [E][N1^3] of Eq. (2), writes
+ * L23[e][0][node] = 0.125 w_i w_j w_k / det(8J) * lambda0 and L23[e][1][node] =
+ * w_i w_j w_k det J * lambda1 (the lumped mass Gwj of Eq. 3), double if prec == AX_FP64, float
+ * if AX_FP32.  verts [dev] double [E][8][3]; xi, w [host] double[N1].  AX_ERR_ARG for NULL
+ * arrays, AX_ERR_UNSUPPORTED for N outside [1,15] or another prec.  Asynchronous on `stream`.
+ */
+int ax_helmholtz_factors(int64_t E, int N, const double* verts, const double* xi, const double* w,
+                         const double* lambda0, const double* lambda1, int prec, void* L23, void* stream);
+
+/*
  * ax_geom_lambda - set-up for ax_local_partial: lam [dev] [E][N1^3] = 0.125 w_i w_j w_k / det(8J)
  * at every node of the trilinear elements (8J: the Jacobian of Eq. 9 without its factor 1/8, as
  * in Algorithm 2), double if prec == AX_FP64, float if AX_FP32.  verts [dev] double [E][8][3];

@@ -114,6 +114,15 @@ def lambda_geo(verts, N: int, xi, w) -> np.ndarray:
     return W * W / (4096.0 * gwj)
 
 
+def ax_local_helmholtz(D, G, gwj, lambda0, lambda1, X) -> np.ndarray:
+    """Helmholtz AxLocal (Eq. 3): Y_e = D^T (Lambda0 G_e) D X_e + Lambda1 Gwj X_e, with the nodal
+    coefficient fields lambda0, lambda1 [E][N1^3] scaling the factors G [E][6][N1^3] and the
+    lumped mass gwj [E][N1^3] node by node (the diagonal matrices of Eq. 3)."""
+    lambda0 = np.asarray(lambda0, dtype=np.float64)
+    Y = ax_local(D, G * lambda0[:, None, :], X)
+    return Y + (np.asarray(lambda1, dtype=np.float64) * gwj)[None] * np.asarray(X, dtype=np.float64).reshape(Y.shape)
+
+
 def node_coords(verts, N: int, xi) -> np.ndarray:
     """Physical node coordinates [E][3][N1^3] (Eq. 8)."""
     verts = _c64(verts)

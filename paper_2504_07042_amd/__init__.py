@@ -76,6 +76,8 @@ _SIGS = {
     "ax_geom_factors": (_int, [_i64, _int, _vp, _vp, _vp, _int, _vp, _vp, _vp]),
     "ax_local_partial": (_int, [_i64, _int, _vp, _vp, _vp, _vp, _vp, _int, _int, _vp, _vp, _vp]),
     "ax_geom_lambda": (_int, [_i64, _int, _vp, _vp, _vp, _int, _vp, _vp]),
+    "ax_local_helmholtz": (_int, [_i64, _int, _vp, _vp, _vp, _vp, _vp, _int, _int, _vp, _vp, _vp]),
+    "ax_helmholtz_factors": (_int, [_i64, _int, _vp, _vp, _vp, _vp, _vp, _int, _vp, _vp]),
     "ax_parallelepiped_factors": (_int, [_i64, _vp, _vp, _vp]),
     "ax_node_coords": (_int, [_i64, _int, _vp, _vp, _vp, _vp]),
     "gs_build_csr": (_int, [_i64, _i64, _vp, _vp, _vp]),
@@ -206,6 +208,33 @@ def ax_local_partial(X, verts, lam, basis: Basis, prec=AX_FP64, out=None, stream
     _check(lib().ax_local_partial(E, basis.N, _dptr(verts), _dptr(lam), _np_ptr(basis.D), _np_ptr(basis.xi),
                                   _np_ptr(basis.w), nrhs, prec, _dptr(X), _dptr(Y), _stream(stream)))
     return Y
+
+
+def ax_local_helmholtz(X, verts, L23, basis: Basis, prec=AX_FP64, out=None, stream=None):
+    """Y = Helmholtz AxLocal(X) (Eq. 3) on trilinear elements with the merged scalar factors L23
+    [E][2][N1^3] from helmholtz_factors (Sec. 4.2.1)."""
+    import torch
+    E = verts.shape[0]
+    nrhs = _nrhs(X, E, basis.N)
+    assert X.dtype == _prec_dtype(prec) and L23.dtype == _prec_dtype(prec) and verts.dtype == torch.float64
+    Y = torch.empty_like(X) if out is None else out
+    _check(lib().ax_local_helmholtz(E, basis.N, _dptr(verts), _dptr(L23), _np_ptr(basis.D), _np_ptr(basis.xi),
+                                    _np_ptr(basis.w), nrhs, prec, _dptr(X), _dptr(Y), _stream(stream)))
+    return Y
+
+
+def helmholtz_factors(verts, lambda0, lambda1, basis: Basis, prec=AX_FP64, stream=None):
+    """Merged scalar factors L23 [E][2][N1^3]: lam * lambda0 and gwj * lambda1 per node, from the
+    nodal coefficient fields lambda0, lambda1 (float64 [E][N1^3] device tensors)."""
+    import torch
+    E = verts.shape[0]
+    NP = (basis.N + 1) ** 3
+    assert lambda0.shape == (E, NP) and lambda1.shape == (E, NP)
+    assert lambda0.dtype == torch.float64 and lambda1.dtype == torch.float64
+    L23 = torch.empty((E, 2, NP), dtype=_prec_dtype(prec), device=verts.device)
+    _check(lib().ax_helmholtz_factors(E, basis.N, _dptr(verts), _np_ptr(basis.xi), _np_ptr(basis.w),
+                                      _dptr(lambda0), _dptr(lambda1), prec, _dptr(L23), _stream(stream)))
+    return L23
 
 
 def geom_lambda(verts, basis: Basis, prec=AX_FP64, stream=None):

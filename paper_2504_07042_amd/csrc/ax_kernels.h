@@ -8,9 +8,11 @@ namespace ax {
 
 // GEO_TRIL: trilinear with the per-node scale lam = 0.125 w / det(8J) read from memory (the
 // partial recomputation of Sec. 4.2.1): no determinant and no division in the kernel.
-enum { GEO_TRI = 0, GEO_PARA = 1, GEO_STORED = 2, GEO_TRIL = 3 };
+// GEO_HELM: the trilinear Helmholtz operator with merged scalar factors (Sec. 4.2.1): per node
+// Lambda2 = lam * lambda0 scales adj(K) and Lambda3 = gwj * lambda1 the mass term.
+enum { GEO_TRI = 0, GEO_PARA = 1, GEO_STORED = 2, GEO_TRIL = 3, GEO_HELM = 4 };
 
-constexpr bool is_trilinear(int geo) { return geo == GEO_TRI || geo == GEO_TRIL; }
+constexpr bool is_trilinear(int geo) { return geo == GEO_TRI || geo == GEO_TRIL || geo == GEO_HELM; }
 
 // Tuning knobs (compile-time): waves per SIMD the register allocation targets for N1 <= 8, and
 // how many times the resident capacity the persistent grid is.

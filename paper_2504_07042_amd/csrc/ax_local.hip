@@ -117,3 +117,21 @@ extern "C" int ax_local_partial(int64_t E, int N, const double* verts, const voi
     return axl_dispatch_f32(GEO_TRIL, N, E, nrhs, verts, (const float*)lam, (const float*)X, (float*)Y, D, xi, w,
                             st, nullptr, 0);
 }
+
+extern "C" int ax_local_helmholtz(int64_t E, int N, const double* verts, const void* L23, const double* D,
+                                  const double* xi, const double* w, int nrhs, int prec, const void* X, void* Y,
+                                  void* stream)
+{
+    clear_error();
+    AX_TRY(check_common(E, N, nrhs, prec, X, Y, D));
+    if (prec == AX_FP16_ACC32) return fail(AX_ERR_UNSUPPORTED, "the Helmholtz operator is FP64 or FP32");
+    if (!xi || !w) return fail(AX_ERR_ARG, "xi or w is NULL");
+    if (E == 0) return AX_OK;
+    if (!verts || !L23) return fail(AX_ERR_ARG, "verts or L23 is NULL");
+    hipStream_t st = as_stream(stream);
+    if (prec == AX_FP64)
+        return axl_dispatch_f64(GEO_HELM, N, E, nrhs, verts, (const double*)L23, (const double*)X, (double*)Y, D,
+                                xi, w, st, nullptr, 0);
+    return axl_dispatch_f32(GEO_HELM, N, E, nrhs, verts, (const float*)L23, (const float*)X, (float*)Y, D, xi, w,
+                            st, nullptr, 0);
+}

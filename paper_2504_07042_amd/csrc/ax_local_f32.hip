@@ -11,6 +11,7 @@ int axl_dispatch_f32(int geo_kind, int N, int64_t E, int nrhs, const double* geo
     case GEO_TRI: return dispatch<GEO_TRI, float>(N, E, nrhs, geo, Gs, X, Y, D, xi, w, st, l2g, ldg);
     case GEO_PARA: return dispatch<GEO_PARA, float>(N, E, nrhs, geo, Gs, X, Y, D, xi, w, st, l2g, ldg);
     case GEO_TRIL: return dispatch<GEO_TRIL, float>(N, E, nrhs, geo, Gs, X, Y, D, xi, w, st, l2g, ldg);
+    case GEO_HELM: return dispatch<GEO_HELM, float>(N, E, nrhs, geo, Gs, X, Y, D, xi, w, st, l2g, ldg);
     default: return dispatch<GEO_STORED, float>(N, E, nrhs, geo, Gs, X, Y, D, xi, w, st, l2g, ldg);
     }
 }

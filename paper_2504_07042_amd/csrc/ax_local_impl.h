@@ -226,6 +226,14 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
         }
         T x2[N1];
         contract<N1, false, EO>(cs, xr, x2);  // x2 = D_t x
+        // Helmholtz: this item's mass-term products Lambda3 x at the home column (added to the
+        // t-direction output after the pointwise stage)
+        T mx[GEO == GEO_HELM ? N1 : 1];
+        if constexpr (GEO == GEO_HELM) {
+            const T* l3 = Gs + ((active ? e : 0) * 2 + 1) * NP + i + j * N1;
+#pragma unroll
+            for (int k = 0; k < N1; ++k) mx[k] = l3[k * NT] * xr[k];
+        }
         T xn[N1];
         load_x(eb_n, c_n, xn);
         if (last_col) load_v(eb_n, vr);
@@ -270,10 +278,11 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
                 x0 *= lam;
                 x1 *= lam;
                 xx2 *= lam;
-            } else if constexpr (GEO == GEO_TRIL) {
+            } else if constexpr (GEO == GEO_TRIL || GEO == GEO_HELM) {
                 T tk, wk;
                 node_xw<N1, GEO, EO>(bs, sxw, k, tk, wk);
-                const T lam = Gs[(active ? e : 0) * NP + i + j * N1 + k * NT];
+                constexpr int LS = GEO == GEO_HELM ? 2 : 1;  // fields per element in Gs
+                const T lam = Gs[(active ? e : 0) * LS * NP + i + j * N1 + k * NT];
                 tri_adj_k<T>(tc, tk, g);
                 x0 *= lam;
                 x1 *= lam;
@@ -294,6 +303,10 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
         }
         T y2[N1];
         contract<N1, true, EO>(cs, tt, y2);  // D_t^T t
+        if constexpr (GEO == GEO_HELM) {
+#pragma unroll
+            for (int k = 0; k < N1; ++k) y2[k] += mx[k];
+        }
         __syncthreads();
         // P4: D_r^T r in place on the r-pencils; D_s^T s into registers
         {
@@ -346,10 +359,15 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
     }
 }
 
+// Waves per SIMD the register allocation targets: the Helmholtz kernel at N1 = 8 also carries
+// the mass-term products through the item, which does not fit the four-wave budget.
+template <int N1, int GEO>
+constexpr int min_waves() { return (GEO == GEO_HELM && N1 == 8) ? 3 : Shape<N1>::MINW; }
+
 // Entry points: the tables of orders that fit the scalar register file stay resident; the
 // others are reloaded per output row through the kernel-argument segment (one struct argument).
 template <int N1, int GEO, bool EO, bool GATHER, int EPBX, typename T>
-__global__ void __launch_bounds__((Tile<N1, EPBX>::BLOCK), Shape<N1>::MINW)
+__global__ void __launch_bounds__((Tile<N1, EPBX>::BLOCK), (min_waves<N1, GEO>()))
 ax_local_kernel(int64_t E, int nrhs, const double* __restrict__ geo, const T* __restrict__ Gs,
                 const T* __restrict__ X, T* __restrict__ Y, const Basis<T> bs,
                 const int32_t* __restrict__ l2g, int64_t ldg)
@@ -358,7 +376,7 @@ ax_local_kernel(int64_t E, int nrhs, const double* __restrict__ geo, const T* __
 }
 
 template <int N1, int GEO, bool EO, bool GATHER, int EPBX, typename T>
-__global__ void __launch_bounds__((Tile<N1, EPBX>::BLOCK), Shape<N1>::MINW)
+__global__ void __launch_bounds__((Tile<N1, EPBX>::BLOCK), (min_waves<N1, GEO>()))
 ax_local_kernel_rl(const AxArgs<T> ka)
 {
     const CoefReload<T> cs = karg_coefs<T, AxArgs<T>>();
@@ -424,7 +442,7 @@ static int launch_n1(int64_t E, int nrhs, const double* geo, const T* Gs, const 
     fill_basis(bs, N1, D, xi, w);
     // the even-odd kernels also take the nodes as mirror-symmetric (the factors need none)
     const bool eo = centro_antisymmetric(N1, D) && (GEO == GEO_STORED || symmetric_nodes(N1, xi, w));
-    const TuneEntry tu = tune_get(N1, GEO == GEO_TRIL ? GEO_TRI : GEO, sizeof(T) == 8 ? AX_FP64 : AX_FP32);
+    const TuneEntry tu = tune_get(N1, is_trilinear(GEO) ? GEO_TRI : GEO, sizeof(T) == 8 ? AX_FP64 : AX_FP32);
     if (l2g) {
         if (!eo) return fail(AX_ERR_UNSUPPORTED, "gathering AxLocal needs a GLL differentiation matrix");
         if constexpr (GEO == GEO_TRI || GEO == GEO_PARA)

@@ -54,6 +54,29 @@ geom_lambda_kernel(int64_t E, int N1, const double* __restrict__ verts, T* __res
     lam[idx] = T(lm);
 }
 
+// Merged scalar factors of the Helmholtz operator (Sec. 4.2.1): L23[e][0][node] = lam lambda0,
+// L23[e][1][node] = gwj lambda1 with lam = 0.125 w_i w_j w_k / det(8J) and gwj = w_i w_j w_k det J.
+template <typename T>
+__global__ void __launch_bounds__(256)
+helmholtz_factors_kernel(int64_t E, int N1, const double* __restrict__ verts, const double* __restrict__ lambda0,
+                         const double* __restrict__ lambda1, T* __restrict__ L23, const Nodes nd)
+{
+    const int NP = N1 * N1 * N1;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= E * NP) return;
+    const int64_t e = idx / NP;
+    const int l = (int)(idx - e * NP);
+    const int i = l % N1, j = (l / N1) % N1, k = l / (N1 * N1);
+    const double* Ve = verts + e * 24;
+    TriCoef tc;
+    tri_prelude([&](int v, int q) { return Ve[v * 3 + q]; }, nd.xi[i], nd.xi[j], nd.w[i], nd.w[j], tc);
+    double g[6], lm;
+    tri_adj<double>(tc, nd.xi[k], nd.w[k], g, lm);
+    const double gwj = nd.w[i] * nd.w[j] * nd.w[k] * tri_det(tc, nd.xi[k]) * (1.0 / 512.0);
+    L23[(e * 2) * NP + l] = T(lm * lambda0[idx]);
+    L23[(e * 2 + 1) * NP + l] = T(gwj * lambda1[idx]);
+}
+
 // h = det J J^-1 J^-T = adj(J^T J) / det J with J = 1/2 [v1 - v0, v2 - v0, v4 - v0] (columns).
 __global__ void __launch_bounds__(256)
 parallelepiped_kernel(int64_t E, const double* __restrict__ verts, double* __restrict__ h)
@@ -167,6 +190,31 @@ extern "C" int ax_geom_lambda(int64_t E, int N, const double* verts, const doubl
         hipLaunchKernelGGL(geom_lambda_kernel<float>, dim3(grid_for(n, 256)), dim3(256), 0, st, E, N1, verts,
                            (float*)lam, nd);
     return hip_check(hipGetLastError(), "ax_geom_lambda launch");
+}
+
+extern "C" int ax_helmholtz_factors(int64_t E, int N, const double* verts, const double* xi, const double* w,
+                                    const double* lambda0, const double* lambda1, int prec, void* L23, void* stream)
+{
+    clear_error();
+    if (E < 0) return fail(AX_ERR_ARG, "E < 0");
+    if (N < 1 || N > 15) return fail(AX_ERR_UNSUPPORTED, "order N=%d outside [1,15]", N);
+    if (prec != AX_FP64 && prec != AX_FP32) return fail(AX_ERR_UNSUPPORTED, "prec must be FP64 or FP32");
+    if (!xi || !w) return fail(AX_ERR_ARG, "xi or w is NULL");
+    if (E == 0) return AX_OK;
+    if (!verts || !lambda0 || !lambda1 || !L23) return fail(AX_ERR_ARG, "NULL array");
+    const int N1 = N + 1;
+    const int64_t n = E * N1 * N1 * N1;
+    if (n / 256 > 0x7fffffff) return fail(AX_ERR_UNSUPPORTED, "too many nodes");
+    Nodes nd;
+    fill_nodes(nd, N1, xi, w);
+    hipStream_t st = as_stream(stream);
+    if (prec == AX_FP64)
+        hipLaunchKernelGGL(helmholtz_factors_kernel<double>, dim3(grid_for(n, 256)), dim3(256), 0, st, E, N1, verts,
+                           lambda0, lambda1, (double*)L23, nd);
+    else
+        hipLaunchKernelGGL(helmholtz_factors_kernel<float>, dim3(grid_for(n, 256)), dim3(256), 0, st, E, N1, verts,
+                           lambda0, lambda1, (float*)L23, nd);
+    return hip_check(hipGetLastError(), "ax_helmholtz_factors launch");
 }
 
 extern "C" int ax_parallelepiped_factors(int64_t E, const double* verts, double* h, void* stream)

@@ -152,3 +152,15 @@ def test_partial_validation(ax):
     assert L.ax_geom_lambda(2, 3, None, xi, w, ax.AX_FP64, 8, None) == ax.AX_ERR_ARG
     assert L.ax_geom_lambda(2, 3, 8, xi, w, ax.AX_FP16_ACC32, 8, None) == ax.AX_ERR_UNSUPPORTED
     assert L.ax_geom_lambda(-1, 3, 8, xi, w, ax.AX_FP64, 8, None) == ax.AX_ERR_ARG
+
+
+def test_helmholtz_validation(ax):
+    b = ax.Basis(3)
+    L = ax.lib()
+    D, xi, w = ax._np_ptr(b.D), ax._np_ptr(b.xi), ax._np_ptr(b.w)
+    assert L.ax_local_helmholtz(2, 3, 8, None, D, xi, w, 1, ax.AX_FP64, 8, 16, None) == ax.AX_ERR_ARG
+    assert L.ax_local_helmholtz(2, 3, 8, 8, D, xi, w, 1, ax.AX_FP16_ACC32, 8, 16, None) == ax.AX_ERR_UNSUPPORTED
+    assert L.ax_local_helmholtz(2, 0, 8, 8, D, xi, w, 1, ax.AX_FP64, 8, 16, None) == ax.AX_ERR_UNSUPPORTED
+    assert L.ax_local_helmholtz(0, 3, None, None, D, xi, w, 1, ax.AX_FP64, None, None, None) == ax.AX_OK
+    assert L.ax_helmholtz_factors(2, 3, 8, xi, w, None, 8, ax.AX_FP64, 8, None) == ax.AX_ERR_ARG
+    assert L.ax_helmholtz_factors(2, 3, 8, xi, w, 8, 8, 7, 8, None) == ax.AX_ERR_UNSUPPORTED
