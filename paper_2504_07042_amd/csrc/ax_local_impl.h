@@ -226,14 +226,6 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
         }
         T x2[N1];
         contract<N1, false, EO>(cs, xr, x2);  // x2 = D_t x
-        // Helmholtz: this item's mass-term products Lambda3 x at the home column (added to the
-        // t-direction output after the pointwise stage)
-        T mx[GEO == GEO_HELM ? N1 : 1];
-        if constexpr (GEO == GEO_HELM) {
-            const T* l3 = Gs + ((active ? e : 0) * 2 + 1) * NP + i + j * N1;
-#pragma unroll
-            for (int k = 0; k < N1; ++k) mx[k] = l3[k * NT] * xr[k];
-        }
         T xn[N1];
         load_x(eb_n, c_n, xn);
         if (last_col) load_v(eb_n, vr);
@@ -303,9 +295,14 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
         }
         T y2[N1];
         contract<N1, true, EO>(cs, tt, y2);  // D_t^T t
+        // Helmholtz: Lambda3 and this item's X at the home column for the mass term, loaded here
+        // (X again, now from the cache) so that they are in flight during the next phase
+        T l3v[GEO == GEO_HELM ? N1 : 1], xv[GEO == GEO_HELM ? N1 : 1];
         if constexpr (GEO == GEO_HELM) {
+            const T* l3 = Gs + ((active ? e : 0) * 2 + 1) * NP + i + j * N1;
 #pragma unroll
-            for (int k = 0; k < N1; ++k) y2[k] += mx[k];
+            for (int k = 0; k < N1; ++k) l3v[k] = l3[k * NT];
+            load_x(eb, c, xv);
         }
         __syncthreads();
         // P4: D_r^T r in place on the r-pencils; D_s^T s into registers
@@ -326,6 +323,10 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
 #endif
         }
         __syncthreads();
+        if constexpr (GEO == GEO_HELM) {
+#pragma unroll
+            for (int k = 0; k < N1; ++k) y2[k] = fma(l3v[k], xv[k], y2[k]);
+        }
         T* yb = Y + ((int64_t)c * E + eb * EPB) * NP;
         const uint32_t lo = home_off(true);
 #if AX_MERGE_RS
@@ -359,10 +360,14 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
     }
 }
 
-// Waves per SIMD the register allocation targets: the Helmholtz kernel at N1 = 8 also carries
-// the mass-term products through the item, which does not fit the four-wave budget.
+// Waves per SIMD the register allocation targets: the FP64 Helmholtz kernel at N1 = 8 also
+// carries the mass-term operands through the last phases, which does not fit the four-wave
+// budget without spills.
+#ifndef AX_HELM_MINW
+#define AX_HELM_MINW 3
+#endif
 template <int N1, int GEO>
-constexpr int min_waves() { return (GEO == GEO_HELM && N1 == 8) ? 3 : Shape<N1>::MINW; }
+constexpr int min_waves() { return (GEO == GEO_HELM && N1 == 8) ? AX_HELM_MINW : Shape<N1>::MINW; }
 
 // Entry points: the tables of orders that fit the scalar register file stay resident; the
 // others are reloaded per output row through the kernel-argument segment (one struct argument).
