@@ -211,6 +211,35 @@ def order_sweep(ax, meshgen, dev, orders=(3, 5, 7, 9, 11, 15), steps=20, warmup=
     return rows
 
 
+def element_sweep(ax, meshgen, dev, N=7, steps=20, warmup=20):
+    """Trilinear FP64 AxLocal at N = 7 for E = 2^15 ... 2^20 elements (one X/Y pair, +-15 %
+    jitter, seed N): the plateau of the throughput with the problem size, from inside the 256 MB
+    Infinity Cache (X and Y of E = 2^15 take 256 MiB) to far outside it."""
+    import torch
+    rows = []
+    b = ax.Basis(N)
+    for grid in ((32, 32, 32), (64, 32, 32), (64, 64, 32), (64, 64, 64), (128, 64, 64), (128, 128, 64)):
+        m = meshgen.jittered_hex(*grid, alpha=0.15, seed=N)
+        V = torch.from_numpy(m.verts).to(dev)
+        del m
+        X = meshgen.random_nodal_device(V.shape[0], N, seed=N, device=dev)
+        Y = torch.empty_like(X)
+        # warm up for a fixed time (the clocks need about 0.2 s of continuous launches to ramp)
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < 0.3:
+            for _ in range(10):
+                ax.ax_local(X, V, b, ax.AX_TRILINEAR, ax.AX_FP64, out=Y)
+            torch.cuda.synchronize()
+        _, per = time_steps(lambda q: ax.ax_local(X, V, b, ax.AX_TRILINEAR, ax.AX_FP64, out=Y), steps, warmup, 1)
+        dofs = V.shape[0] * (N + 1) ** 3
+        rows.append({"E": V.shape[0], "grid": list(grid), "local_dofs": dofs,
+                     "x_plus_y_MiB": round(2 * dofs * 8 / 2**20), "GDOFs": round(dofs / per.mean() / 1e9, 1),
+                     "us_per_launch": round(per.mean() * 1e6, 1)})
+        del X, Y, V
+        torch.cuda.empty_cache()
+    return rows
+
+
 def batched_run(ax, meshgen, dev, nrhs=8, steps=5, warmup=2, check_with_oracle=True):
     """64 independent trilinear meshes (E ~ U[512, 32768] rounded to a near-cubic grid, N drawn
     from {3, 5, 7, 9}, seed 1, +-10 % jitter) with 8 columns each: one persistent launch (replayed
@@ -319,6 +348,8 @@ def main(argv=None):
                     help="also run the batched workload: 64 meshes, E~U[512,32768], N in {3,5,7,9}, 8 columns")
     ap.add_argument("--batched-cg", action="store_true",
                     help="also run CG (FP64 vs mixed precision) on the union of the 64 batched meshes (minutes)")
+    ap.add_argument("--esweep", action="store_true",
+                    help="also run the element-count sweep E = 2^15..2^20 at N = 7 (trilinear FP64)")
     ap.add_argument("--sweep", action="store_true",
                     help="also run the order sweep N in {3,5,7,9,11,15} at ~2^24 local nodes")
     args = ap.parse_args(argv)
@@ -488,6 +519,8 @@ def main(argv=None):
 
     if args.sweep:
         out["order_sweep"] = order_sweep(ax, meshgen, dev, steps=max(10, args.steps // 2), warmup=3)
+    if args.esweep:
+        out["element_sweep"] = element_sweep(ax, meshgen, dev)
 
     if args.calib:
         a = torch.empty(16 * 2**20, dtype=torch.float64, device=dev).uniform_()
