@@ -108,9 +108,25 @@ def cpu_baseline(mesh, N, X, budget_s=10.0):
         if el >= budget_s:
             break
     dofs = reps * nsamp * (N + 1) ** 3 * X.shape[0]
-    return {"value": dofs / el / 1e9, "unit": "GDOF/s", "cores": oracle.num_threads(), "kind": "oracle",
+    cores = oracle.num_threads()
+    # the same on one core, on a smaller sample
+    n1 = min(nsamp, 256)
+    oracle.set_num_threads(1)
+    reps1, t1 = 0, time.perf_counter()
+    while True:
+        G, _, _ = oracle.geom_factors(V[:n1], N, xi, w)
+        oracle.ax_local(D, G, Xs[:, :n1])
+        reps1 += 1
+        el1 = time.perf_counter() - t1
+        if el1 >= budget_s / 4:
+            break
+    oracle.set_num_threads(cores)
+    aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None
+    return {"value": dofs / el / 1e9, "unit": "GDOF/s", "cores": cores, "kind": "oracle",
             "sample": f"{nsamp} of {mesh.E} elements (first {nsamp}), N={N}, nrhs={X.shape[0]}, "
-                      f"geometric factors + AxLocal, {reps} repetitions in {el:.1f} s"}
+                      f"geometric factors + AxLocal, {reps} repetitions in {el:.1f} s",
+            "single_core_GDOFs": reps1 * n1 * (N + 1) ** 3 * X.shape[0] / el1 / 1e9,
+            "os_cpu_count": os.cpu_count(), "affinity_cpus": aff}
 
 
 def cg_solves(ax, meshgen, dev, N=7, grid=(32, 32, 32), rtol=1e-10, check_with_oracle=True):

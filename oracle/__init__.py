@@ -48,6 +48,8 @@ def _load():
                            ctypes.c_double, ctypes.c_int, _dp]
     lib.orc_cg.restype = ctypes.c_int
     lib.orc_num_threads.restype = ctypes.c_int
+    lib.orc_set_num_threads.argtypes = [ctypes.c_int]
+    lib.orc_set_num_threads.restype = None
     _lib = lib
     return lib
 
@@ -63,6 +65,11 @@ def _c64(a):
 
 def num_threads() -> int:
     return _load().orc_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on."""
+    _load().orc_set_num_threads(int(n))
 
 
 def legendre(N: int, x: float):
