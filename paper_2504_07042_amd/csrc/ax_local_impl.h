@@ -430,9 +430,10 @@ int tri_item_dispatch_f64(int N1, int64_t E, int nrhs, const double* verts, cons
                           const Basis<double>& bs, int grid_mult, hipStream_t st);
 
 // Trilinear FP64 orders served by the per-item kernel (see batched.hip); measured on gfx950
-// it is faster than the prefetching kernel for 9 <= N1 <= 15 and slower at N1 = 8 and 16.
+// it is faster than the prefetching kernel for N1 = 6, 7 and 9..15, about even at N1 = 5 and
+// slower at N1 <= 4, 8 and 16.
 #ifndef AX_ITEM_LO
-#define AX_ITEM_LO 9
+#define AX_ITEM_LO 6
 #endif
 template <int N1, int GEO, typename T>
 constexpr bool use_item_kernel() { return GEO == GEO_TRI && sizeof(T) == 8 && N1 >= AX_ITEM_LO && N1 <= 15 && N1 != 8; }
