@@ -427,7 +427,7 @@ static int launch_tile(int64_t E, int nrhs, const double* geo, const T* Gs, cons
 }
 
 int tri_item_dispatch_f64(int N1, int64_t E, int nrhs, const double* verts, const double* X, double* Y,
-                          const Basis<double>& bs, int grid_mult, hipStream_t st);
+                          const Basis<double>& bs, int grid_mult, hipStream_t st, const double* lam);
 
 // Trilinear FP64 orders served by the per-item kernel (see batched.hip); measured on gfx950
 // it is faster than the prefetching kernel for N1 = 6, 7 and 9..15, about even at N1 = 5 and
@@ -436,7 +436,13 @@ int tri_item_dispatch_f64(int N1, int64_t E, int nrhs, const double* verts, cons
 #define AX_ITEM_LO 6
 #endif
 template <int N1, int GEO, typename T>
-constexpr bool use_item_kernel() { return GEO == GEO_TRI && sizeof(T) == 8 && N1 >= AX_ITEM_LO && N1 <= 15 && N1 != 8; }
+constexpr bool use_item_kernel()
+{
+    // the partial-recomputation form (fewer live registers) stays on the prefetching kernel
+    // below N1 = 9 (measured faster there at N1 = 6)
+    return (GEO == GEO_TRI || GEO == GEO_TRIL) && sizeof(T) == 8 && N1 >= (GEO == GEO_TRIL ? 9 : AX_ITEM_LO) &&
+           N1 <= 15 && N1 != 8;
+}
 
 template <int N1, int GEO, typename T>
 static int launch_n1(int64_t E, int nrhs, const double* geo, const T* Gs, const T* X, T* Y,
@@ -457,7 +463,8 @@ static int launch_n1(int64_t E, int nrhs, const double* geo, const T* Gs, const 
     }
     if constexpr (use_item_kernel<N1, GEO, T>()) {
         if (eo && !l2g)
-            return tri_item_dispatch_f64(N1, E, nrhs, geo, (const double*)X, (double*)Y, bs, tu.grid_mult, st);
+            return tri_item_dispatch_f64(N1, E, nrhs, geo, (const double*)X, (double*)Y, bs, tu.grid_mult, st,
+                                         GEO == GEO_TRIL ? (const double*)Gs : nullptr);
     }
     if (!eo)
         return launch_tile<N1, GEO, false, false, S::EPB, T>(E, nrhs, geo, Gs, X, Y, bs, tu.grid_mult, st, nullptr, 0);

@@ -75,8 +75,10 @@ struct BHeader {
 };
 
 // cs: source of the basis tables (CoefResident or CoefReload)
-template <int N1, typename T, typename C>
-__device__ __forceinline__ void batched_item(const BMesh& m, int64_t eb, int nrhs, const C& cs, char* lds)
+// PL: partial recomputation (Sec. 4.2.1), the per-node scale read from lam [E][N1^3].
+template <int N1, typename T, bool PL = false, typename C>
+__device__ __forceinline__ void batched_item(const BMesh& m, int64_t eb, int nrhs, const C& cs, char* lds,
+                                             const T* __restrict__ lamp = nullptr)
 {
     using S = BShape<N1>;
     constexpr int NT = S::NT, EPB = S::EPB, FS = S::FS, NP = S::NP;
@@ -143,7 +145,12 @@ __device__ __forceinline__ void batched_item(const BMesh& m, int64_t eb, int nrh
                 T x0 = B[l], x1 = A[l], xx2 = x2[k];
                 T g[6], lam;
                 const C b = cs.row();
-                tri_adj<T>(tc, T(b.xi(k)), T(b.w(k)), g, lam);
+                if constexpr (PL) {
+                    lam = lamp[(active ? e : 0) * NP + i + j * N1 + k * NT];
+                    tri_adj_k<T>(tc, T(b.xi(k)), g);
+                } else {
+                    tri_adj<T>(tc, T(b.xi(k)), T(b.w(k)), g, lam);
+                }
                 x0 *= lam;
                 x1 *= lam;
                 xx2 *= lam;
@@ -253,36 +260,40 @@ static int order_dispatch(int N1, const char* ws, const BHeader& h, int64_t firs
 }
 
 // The per-item path above as a single-mesh persistent kernel (no work list): work-group g takes
-// element groups g, g + grid, ...  Used by ax_local for the trilinear FP64 orders whose register
-// footprint the prefetching kernel exceeds (N1 = 9..15: 118-162 VGPRs here against 256 plus
-// spills there; measured 1.4-3.2x faster), with the tables reloaded per output row.
+// element groups g, g + grid, ...  Used by ax_local (and its partial-recomputation form) for the
+// trilinear FP64 orders whose register footprint the prefetching kernel exceeds (N1 = 9..15:
+// 118-162 VGPRs here against 256 plus spills there; measured 1.4-3.2x faster) or fills only at
+// two waves per SIMD (N1 = 6, 7), with the tables reloaded per output row.
 template <typename T>
 struct ItemArgs {
     BMesh m;
     int nrhs;
     Basis<T> bs;
+    const T* lam;  // per-node scale of the partial recomputation (PL), else unused
 };
 
-template <int N1, typename T>
+template <int N1, typename T, bool PL>
 __global__ void __launch_bounds__(kBBlock, 2)
 tri_item_kernel(const ItemArgs<T> a)
 {
     __shared__ __attribute__((aligned(16))) char lds[BShape<N1>::template lds_bytes<T>()];
     const int64_t ng = (a.m.E + BShape<N1>::EPB - 1) / BShape<N1>::EPB;
     const CoefReload<T> cs = karg_coefs<T, ItemArgs<T>>();
-    for (int64_t eb = blockIdx.x; eb < ng; eb += gridDim.x) batched_item<N1, T>(a.m, eb, a.nrhs, cs, lds);
+    for (int64_t eb = blockIdx.x; eb < ng; eb += gridDim.x)
+        batched_item<N1, T, PL>(a.m, eb, a.nrhs, cs, lds, a.lam);
 }
 
-template <int N1, typename T>
+template <int N1, typename T, bool PL>
 static int tri_item_launch(int64_t E, int nrhs, const double* verts, const T* X, T* Y, const Basis<T>& bs,
-                           int grid_mult, hipStream_t st)
+                           const T* lam, int grid_mult, hipStream_t st)
 {
     static int per = 0, cus = 0;
     if (per == 0) {
         int dev = 0, c = 256, q = 0;
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev);
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&q, tri_item_kernel<N1, T>, kBBlock, 0) != hipSuccess || q < 1)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&q, tri_item_kernel<N1, T, PL>, kBBlock, 0) != hipSuccess ||
+            q < 1)
             q = 1;
         cus = c;
         per = q;
@@ -291,17 +302,28 @@ static int tri_item_launch(int64_t E, int nrhs, const double* verts, const T* X,
     const int64_t cap = (int64_t)cus * per * (grid_mult > 0 ? grid_mult : 1);
     const int64_t blocks = ng < cap ? ng : cap;
     if (blocks <= 0) return AX_OK;
-    const ItemArgs<T> a{BMesh{E, E * N1 * N1 * N1, verts, X, Y, N1, 0}, nrhs, bs};
-    hipLaunchKernelGGL((tri_item_kernel<N1, T>), dim3((unsigned)blocks), dim3(kBBlock), 0, st, a);
+    const ItemArgs<T> a{BMesh{E, E * N1 * N1 * N1, verts, X, Y, N1, 0}, nrhs, bs, lam};
+    hipLaunchKernelGGL((tri_item_kernel<N1, T, PL>), dim3((unsigned)blocks), dim3(kBBlock), 0, st, a);
     return hip_check(hipGetLastError(), "ax_local (item kernel) launch");
 }
 
+// lam != nullptr: the partial-recomputation form (orders 9..15).
 int tri_item_dispatch_f64(int N1, int64_t E, int nrhs, const double* verts, const double* X, double* Y,
-                          const Basis<double>& bs, int grid_mult, hipStream_t st)
+                          const Basis<double>& bs, int grid_mult, hipStream_t st, const double* lam)
 {
+    if (lam) {
+        switch (N1) {
+#define AX_ITEM_CASE(n) \
+    case n: return tri_item_launch<n, double, true>(E, nrhs, verts, X, Y, bs, lam, grid_mult, st);
+            AX_ITEM_CASE(9) AX_ITEM_CASE(10) AX_ITEM_CASE(11) AX_ITEM_CASE(12) AX_ITEM_CASE(13) AX_ITEM_CASE(14)
+            AX_ITEM_CASE(15)
+#undef AX_ITEM_CASE
+        default: return fail(AX_ERR_UNSUPPORTED, "partial item kernel for N1=%d", N1);
+        }
+    }
     switch (N1) {
 #define AX_ITEM_CASE(n) \
-    case n: return tri_item_launch<n, double>(E, nrhs, verts, X, Y, bs, grid_mult, st);
+    case n: return tri_item_launch<n, double, false>(E, nrhs, verts, X, Y, bs, nullptr, grid_mult, st);
         AX_ITEM_CASE(2) AX_ITEM_CASE(3) AX_ITEM_CASE(4) AX_ITEM_CASE(5) AX_ITEM_CASE(6) AX_ITEM_CASE(7)
         AX_ITEM_CASE(8) AX_ITEM_CASE(9) AX_ITEM_CASE(10) AX_ITEM_CASE(11) AX_ITEM_CASE(12) AX_ITEM_CASE(13)
         AX_ITEM_CASE(14) AX_ITEM_CASE(15) AX_ITEM_CASE(16)
