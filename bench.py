@@ -371,8 +371,8 @@ def main(argv=None):
     args = ap.parse_args(argv)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build measures one GPU only; run with --gpus 1 "
-              "(the element-parallel operator shards by element slabs; see DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only; run with --gpus 1 "
+              "(the element-parallel operator would shard by element slabs, one per GPU)", file=sys.stderr)
         return 2
 
     import torch
