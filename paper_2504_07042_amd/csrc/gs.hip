@@ -21,7 +21,7 @@ gs_qt_kernel(int64_t n_local, int64_t n_global, const IP* __restrict__ gptr,
     const int c = blockIdx.y;
     const T* x = in + (int64_t)c * n_local;
     T* o = out + (int64_t)c * n_global;
-    for (int64_t g0 = (int64_t)blockIdx.x * 256 * kUnroll + threadIdx.x; g0 < n_global;
+    for (int64_t g0 = xcd_tile(blockIdx.x, gridDim.x) * 256 * kUnroll + threadIdx.x; g0 < n_global;
          g0 += (int64_t)gridDim.x * 256 * kUnroll) {
         T s[kUnroll];
         int64_t g[kUnroll];
@@ -46,7 +46,7 @@ gs_q_kernel(int64_t n_local, int64_t n_global, const int32_t* __restrict__ l2g,
     const int c = blockIdx.y;
     const T* x = in + (int64_t)c * n_global;
     T* o = out + (int64_t)c * n_local;
-    for (int64_t l0 = (int64_t)blockIdx.x * 256 * kUnroll + threadIdx.x; l0 < n_local;
+    for (int64_t l0 = xcd_tile(blockIdx.x, gridDim.x) * 256 * kUnroll + threadIdx.x; l0 < n_local;
          l0 += (int64_t)gridDim.x * 256 * kUnroll) {
         int32_t id[kUnroll];
 #pragma unroll

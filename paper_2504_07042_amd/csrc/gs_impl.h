@@ -32,4 +32,15 @@ __device__ __forceinline__ void gather_sums(const IP* __restrict__ gptr, const i
 // nodes (or local entries) per thread and tile in the gather-scatter kernels
 constexpr int kUnroll = 4;
 
+// XCD-aware tile order.  Work-groups are dispatched round-robin over the 8 XCDs of the chip,
+// each with its own L2, so tile b and tile b + 1 (which gather from the same cache lines of the
+// source vector) would land on different L2s.  Tile index of work-group b in a grid of G: the
+// work-groups of one XCD (b = x, x + 8, x + 16, ...) take the contiguous tiles x G/8 ... (grids
+// not divisible by 8 keep the plain order).
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t G)
+{
+    constexpr int64_t kXcd = 8;
+    return (G % kXcd) ? b : (b % kXcd) * (G / kXcd) + b / kXcd;
+}
+
 }  // namespace ax
