@@ -178,12 +178,13 @@ def cg_solves(ax, meshgen, dev, N=7, grid=(32, 32, 32), rtol=1e-10, check_with_o
     return res
 
 
-def roofline_gdofs(N, geom, fpsize=8, peak_tf=PEAK_FP64_TFS, peak_gbs=PEAK_HBM_GBS):
-    """Time-based roofline (Sec. 3.4) in local DOFs per second: max(T_cmp, T_mem) per element."""
-    f_ax, f_geo = flops_per_element(N, geom)
+def roofline_gdofs(N, geom, fpsize=8, peak_tf=PEAK_FP64_TFS, peak_gbs=PEAK_HBM_GBS, nrhs=1):
+    """Time-based roofline (Sec. 3.4) in local DOFs per second (nrhs columns count nrhs DOFs
+    per node): max(T_cmp, T_mem) per element."""
+    f_ax, f_geo = flops_per_element(N, geom, nrhs)
     t_cmp = (f_ax + f_geo) / (peak_tf * 1e12)
-    t_mem = bytes_per_element(N, geom, fpsize=fpsize) / (peak_gbs * 1e9)
-    return (N + 1) ** 3 / max(t_cmp, t_mem) / 1e9, ("alu" if t_cmp >= t_mem else "hbm")
+    t_mem = bytes_per_element(N, geom, nrhs=nrhs, fpsize=fpsize) / (peak_gbs * 1e9)
+    return nrhs * (N + 1) ** 3 / max(t_cmp, t_mem) / 1e9, ("alu" if t_cmp >= t_mem else "hbm")
 
 
 def order_sweep(ax, meshgen, dev, orders=(3, 5, 7, 9, 11, 15), steps=20, warmup=3):
@@ -511,6 +512,20 @@ def main(argv=None):
         wall32, _ = time_steps(step32, args.steps, args.warmup, NBUF)
         extras["trilinear_fp32_GDOFs"] = round(dofs * args.steps / wall32 / 1e9, 3)
         del X32, Y32
+        # vector field (n_col = 3, Sec. 4.1): three columns per node share the recomputed factors
+        X3 = meshgen.random_nodal_device(E, N, nrhs=3, seed=N + 3, device=dev)
+        Y3 = torch.empty_like(X3)
+        wall3, per3 = time_steps(lambda q: ax.ax_local(X3, V, b, ax.AX_TRILINEAR, ax.AX_FP64, out=Y3),
+                                 max(20, args.steps // 4), max(20, args.warmup // 4), 1)
+        fa3, fg3 = flops_per_element(N, "tri", nrhs=3)
+        r3, bound3 = roofline_gdofs(N, "tri", nrhs=3)
+        extras["vector_field_ncol3_fp64"] = {
+            "GDOFs": round(3 * dofs / per3.mean() / 1e9, 3),
+            "TFLOPs": round((fa3 + fg3) * E / per3.mean() / 1e12, 3),
+            "hbm_GBs": round(bytes_per_element(N, "tri", nrhs=3) * E / per3.mean() / 1e9, 1),
+            "R_eff_GDOFs": round(r3, 1), "bound": bound3,
+            "pct_of_R_eff": round(3 * dofs / per3.mean() / 1e9 / r3, 4)}
+        del X3, Y3
         # parallelepiped elements (32^3 sheared cube, N = 7)
         pm, _ = meshgen.parallelepiped_hex(*grid, seed=2)
         h = ax.parallelepiped_factors(torch.from_numpy(pm.verts).to(dev))
