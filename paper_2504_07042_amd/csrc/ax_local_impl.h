@@ -428,6 +428,13 @@ static int launch_tile(int64_t E, int nrhs, const double* geo, const T* Gs, cons
 
 int tri_item_dispatch_f64(int N1, int64_t E, int nrhs, const double* verts, const double* X, double* Y,
                           const Basis<double>& bs, int grid_mult, hipStream_t st, const double* lam);
+int tri_item_dispatch_f32(int N1, int64_t E, int nrhs, const double* verts, const float* X, float* Y,
+                          const Basis<float>& bs, int grid_mult, hipStream_t st);
+// FP32: the per-item kernel from N1 = 10 (measured: even at N1 = 10, +13-15 % at N1 = 12, 15,
+// where the prefetching kernel runs at two waves per SIMD)
+#ifndef AX_ITEM_LO_F32
+#define AX_ITEM_LO_F32 10
+#endif
 
 // Trilinear FP64 orders served by the per-item kernel (see batched.hip); measured on gfx950
 // it is faster than the prefetching kernel for N1 = 6, 7 and 9..15, about even at N1 = 5 and
@@ -440,8 +447,9 @@ constexpr bool use_item_kernel()
 {
     // the partial-recomputation form (fewer live registers) stays on the prefetching kernel
     // below N1 = 9 (measured faster there at N1 = 6)
-    return (GEO == GEO_TRI || GEO == GEO_TRIL) && sizeof(T) == 8 && N1 >= (GEO == GEO_TRIL ? 9 : AX_ITEM_LO) &&
-           N1 <= 15 && N1 != 8;
+    if constexpr (sizeof(T) == 4)
+        return GEO == GEO_TRI && N1 >= AX_ITEM_LO_F32 && N1 >= 9 && N1 <= 15;
+    return (GEO == GEO_TRI || GEO == GEO_TRIL) && N1 >= (GEO == GEO_TRIL ? 9 : AX_ITEM_LO) && N1 <= 15 && N1 != 8;
 }
 
 template <int N1, int GEO, typename T>
@@ -462,9 +470,13 @@ static int launch_n1(int64_t E, int nrhs, const double* geo, const T* Gs, const 
         return fail(AX_ERR_UNSUPPORTED, "gathering AxLocal needs on-the-fly factors");
     }
     if constexpr (use_item_kernel<N1, GEO, T>()) {
-        if (eo && !l2g)
-            return tri_item_dispatch_f64(N1, E, nrhs, geo, (const double*)X, (double*)Y, bs, tu.grid_mult, st,
-                                         GEO == GEO_TRIL ? (const double*)Gs : nullptr);
+        if (eo && !l2g) {
+            if constexpr (sizeof(T) == 8)
+                return tri_item_dispatch_f64(N1, E, nrhs, geo, (const double*)X, (double*)Y, bs, tu.grid_mult, st,
+                                             GEO == GEO_TRIL ? (const double*)Gs : nullptr);
+            else
+                return tri_item_dispatch_f32(N1, E, nrhs, geo, X, Y, bs, tu.grid_mult, st);
+        }
     }
     if (!eo)
         return launch_tile<N1, GEO, false, false, S::EPB, T>(E, nrhs, geo, Gs, X, Y, bs, tu.grid_mult, st, nullptr, 0);

@@ -332,6 +332,20 @@ int tri_item_dispatch_f64(int N1, int64_t E, int nrhs, const double* verts, cons
     }
 }
 
+// FP32 orders served by the per-item kernel (see use_item_kernel in ax_local_impl.h).
+int tri_item_dispatch_f32(int N1, int64_t E, int nrhs, const double* verts, const float* X, float* Y,
+                          const Basis<float>& bs, int grid_mult, hipStream_t st)
+{
+    switch (N1) {
+#define AX_ITEM_CASE(n) \
+    case n: return tri_item_launch<n, float, false>(E, nrhs, verts, X, Y, bs, nullptr, grid_mult, st);
+        AX_ITEM_CASE(9) AX_ITEM_CASE(10) AX_ITEM_CASE(11) AX_ITEM_CASE(12) AX_ITEM_CASE(13) AX_ITEM_CASE(14)
+        AX_ITEM_CASE(15)
+#undef AX_ITEM_CASE
+    default: return fail(AX_ERR_UNSUPPORTED, "FP32 item kernel for N1=%d", N1);
+    }
+}
+
 static int64_t n_items_of(int n_mesh, const ax_problem* meshes)
 {
     int64_t n = 0;
