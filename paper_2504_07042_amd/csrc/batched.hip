@@ -191,8 +191,12 @@ __device__ __forceinline__ void batched_item(const BMesh& m, int64_t eb, int nrh
 }
 
 // Per-order persistent kernel over the items [0, n) of one order.
+// Waves per SIMD the register allocation targets (FP32 per-order kernels fit five)
+#ifndef AX_BATCH_MINW_F32
+#define AX_BATCH_MINW_F32 5
+#endif
 template <int N1, typename T>
-__global__ void __launch_bounds__(kBBlock, 2)
+__global__ void __launch_bounds__(kBBlock, (sizeof(T) == 4 ? AX_BATCH_MINW_F32 : 2))
 order_item_kernel(const BItem* __restrict__ items, const BMesh* __restrict__ meshes, int64_t n, int nrhs,
                   const Basis<T>* __restrict__ bsp)
 {
