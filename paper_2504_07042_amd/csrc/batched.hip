@@ -276,8 +276,13 @@ struct ItemArgs {
     const T* lam;  // per-node scale of the partial recomputation (PL), else unused
 };
 
+// Waves per SIMD the register allocation of the single-mesh kernel targets: FP32 fits five
+// (88-96 VGPRs; measured 3-8% faster than four at N1 = 10, 11, 12, 14, 15, 2% slower at 13).
+template <int N1, typename T>
+constexpr int item_minw() { return sizeof(T) == 4 && N1 != 13 ? 5 : 2; }
+
 template <int N1, typename T, bool PL>
-__global__ void __launch_bounds__(kBBlock, 2)
+__global__ void __launch_bounds__(kBBlock, (item_minw<N1, T>()))
 tri_item_kernel(const ItemArgs<T> a)
 {
     __shared__ __attribute__((aligned(16))) char lds[BShape<N1>::template lds_bytes<T>()];
