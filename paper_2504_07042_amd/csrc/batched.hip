@@ -276,13 +276,15 @@ struct ItemArgs {
     const T* lam;  // per-node scale of the partial recomputation (PL), else unused
 };
 
-// Waves per SIMD the register allocation of the single-mesh kernel targets: FP32 fits five
-// (88-96 VGPRs; measured 3-8% faster than four at N1 = 10, 11, 12, 14, 15, 2% slower at 13).
-template <int N1, typename T>
-constexpr int item_minw() { return sizeof(T) == 4 && N1 != 13 ? 5 : 2; }
+// Waves per SIMD the register allocation of the single-mesh kernel targets: the FP32 full form
+// fits five (88-96 VGPRs; measured 3-8% faster than four at N1 = 10, 11, 12, 14, 15, 2% slower
+// at 13); the FP32 partial form spills at five and keeps the default budget (measured 12% faster
+// at N1 = 14, even at 13 and 15).
+template <int N1, typename T, bool PL>
+constexpr int item_minw() { return sizeof(T) == 4 && !PL && N1 != 13 ? 5 : 2; }
 
 template <int N1, typename T, bool PL>
-__global__ void __launch_bounds__(kBBlock, (item_minw<N1, T>()))
+__global__ void __launch_bounds__(kBBlock, (item_minw<N1, T, PL>()))
 tri_item_kernel(const ItemArgs<T> a)
 {
     __shared__ __attribute__((aligned(16))) char lds[BShape<N1>::template lds_bytes<T>()];
@@ -341,10 +343,20 @@ int tri_item_dispatch_f64(int N1, int64_t E, int nrhs, const double* verts, cons
     }
 }
 
-// FP32 orders served by the per-item kernel (see use_item_kernel in ax_local_impl.h).
+// FP32 orders served by the per-item kernel (see use_item_kernel in ax_local_impl.h);
+// lam != nullptr: the partial-recomputation form.
 int tri_item_dispatch_f32(int N1, int64_t E, int nrhs, const double* verts, const float* X, float* Y,
-                          const Basis<float>& bs, int grid_mult, hipStream_t st)
+                          const Basis<float>& bs, int grid_mult, hipStream_t st, const float* lam)
 {
+    if (lam) {
+        switch (N1) {
+#define AX_ITEM_CASE(n) \
+    case n: return tri_item_launch<n, float, true>(E, nrhs, verts, X, Y, bs, lam, grid_mult, st);
+            AX_ITEM_CASE(13) AX_ITEM_CASE(14) AX_ITEM_CASE(15)
+#undef AX_ITEM_CASE
+        default: return fail(AX_ERR_UNSUPPORTED, "FP32 partial item kernel for N1=%d", N1);
+        }
+    }
     switch (N1) {
 #define AX_ITEM_CASE(n) \
     case n: return tri_item_launch<n, float, false>(E, nrhs, verts, X, Y, bs, nullptr, grid_mult, st);

@@ -66,7 +66,7 @@ def test_partial_multi_rhs(ax, N):
         check_fp64(Y[c], oracle.ax_local(D, G, X[c:c + 1])[0], oracle.ax_envelope(D, G, X[c:c + 1])[0])
 
 
-@pytest.mark.parametrize("N", [1, 3, 7, 11])
+@pytest.mark.parametrize("N", [1, 3, 7, 11, 12, 13, 14])
 def test_partial_fp32(ax, N):
     import torch
     m = meshgen.jittered_hex(3, 2, 2, alpha=0.15, seed=200 + N)
