@@ -430,10 +430,10 @@ int tri_item_dispatch_f64(int N1, int64_t E, int nrhs, const double* verts, cons
                           const Basis<double>& bs, int grid_mult, hipStream_t st, const double* lam);
 int tri_item_dispatch_f32(int N1, int64_t E, int nrhs, const double* verts, const float* X, float* Y,
                           const Basis<float>& bs, int grid_mult, hipStream_t st, const float* lam);
-// FP32: the per-item kernel from N1 = 10 (measured: even at N1 = 10, +13-15 % at N1 = 12, 15,
-// where the prefetching kernel runs at two waves per SIMD)
+// FP32: the per-item kernel from N1 = 9 (measured with it at five waves per SIMD: +7-8 % at
+// N1 = 9 and 10, +13-15 % at N1 = 12, 15, where the prefetching kernel runs at two)
 #ifndef AX_ITEM_LO_F32
-#define AX_ITEM_LO_F32 10
+#define AX_ITEM_LO_F32 9
 #endif
 // FP32 partial recomputation: the per-item kernel from N1 = 13 (measured interleaved: +18 % at
 // N1 = 13, +7 % at 14, +2 % at 15; even at 10 and 8-10 % behind at 11, 12)
@@ -453,7 +453,7 @@ constexpr bool use_item_kernel()
     // the partial-recomputation form (fewer live registers) stays on the prefetching kernel
     // below N1 = 9 (measured faster there at N1 = 6)
     if constexpr (sizeof(T) == 4)
-        return ((GEO == GEO_TRI && N1 >= AX_ITEM_LO_F32 && N1 >= 10) ||
+        return ((GEO == GEO_TRI && N1 >= AX_ITEM_LO_F32 && N1 >= 9) ||
                 (GEO == GEO_TRIL && N1 >= AX_ITEM_PL_LO_F32 && N1 >= 13)) && N1 <= 15;
     return (GEO == GEO_TRI || GEO == GEO_TRIL) && N1 >= (GEO == GEO_TRIL ? 9 : AX_ITEM_LO) && N1 <= 15 && N1 != 8;
 }
