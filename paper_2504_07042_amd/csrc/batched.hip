@@ -131,6 +131,16 @@ __device__ __forceinline__ void batched_item(const BMesh& m, int64_t eb, int nrh
             for (int n = 0; n < N1; ++n) p[n] = A[Shape<N1>::pos(pa, n, pb)];
             contract<N1, false, true>(cs, p, o1);
         }
+        // Partial recomputation, FP64: all N1 scale loads of the column issued before the
+        // barrier instead of one per node inside the loop below, so their latency overlaps the
+        // barrier wait (measured interleaved: +12 % at N1 = 9, +28-30 % at N1 = 10, 11, 14, 15;
+        // at N1 = 12, 13 the extra registers cost a wave per SIMD and it is 9-10 % slower).
+        constexpr bool kEarly = PL && sizeof(T) == 8 && N1 != 12 && N1 != 13;
+        T lv[N1];
+        if constexpr (kEarly) {
+#pragma unroll
+            for (int k = 0; k < N1; ++k) lv[k] = lamp[(active ? e : 0) * NP + i + j * N1 + k * NT];
+        }
         __syncthreads();
         if (inslot) {
 #pragma unroll
@@ -146,7 +156,7 @@ __device__ __forceinline__ void batched_item(const BMesh& m, int64_t eb, int nrh
                 T g[6], lam;
                 const C b = cs.row();
                 if constexpr (PL) {
-                    lam = lamp[(active ? e : 0) * NP + i + j * N1 + k * NT];
+                    lam = kEarly ? lv[k] : lamp[(active ? e : 0) * NP + i + j * N1 + k * NT];
                     tri_adj_k<T>(tc, T(b.xi(k)), g);
                 } else {
                     tri_adj<T>(tc, T(b.xi(k)), T(b.w(k)), g, lam);
