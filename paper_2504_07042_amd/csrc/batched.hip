@@ -131,11 +131,12 @@ __device__ __forceinline__ void batched_item(const BMesh& m, int64_t eb, int nrh
             for (int n = 0; n < N1; ++n) p[n] = A[Shape<N1>::pos(pa, n, pb)];
             contract<N1, false, true>(cs, p, o1);
         }
-        // Partial recomputation, FP64: all N1 scale loads of the column issued before the
-        // barrier instead of one per node inside the loop below, so their latency overlaps the
-        // barrier wait (measured interleaved: +12 % at N1 = 9, +28-30 % at N1 = 10, 11, 14, 15;
-        // at N1 = 12, 13 the extra registers cost a wave per SIMD and it is 9-10 % slower).
-        constexpr bool kEarly = PL && sizeof(T) == 8 && N1 != 12 && N1 != 13;
+        // Partial recomputation: all N1 scale loads of the column issued before the barrier
+        // instead of one per node inside the loop below, so their latency overlaps the barrier
+        // wait (measured interleaved, FP64: +12 % at N1 = 9, +28-30 % at N1 = 10, 11, 14, 15, and
+        // at N1 = 12, 13 the extra registers cost a wave per SIMD and it is 9-10 % slower; FP32:
+        // +16-20 % at N1 = 13..15).
+        constexpr bool kEarly = PL && (sizeof(T) == 4 || (N1 != 12 && N1 != 13));
         T lv[N1];
         if constexpr (kEarly) {
 #pragma unroll
