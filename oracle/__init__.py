@@ -148,7 +148,8 @@ def parallelepiped_h(verts) -> np.ndarray:
 
 
 def ax_local(D, G, X) -> np.ndarray:
-    """Y = AxLocal(X) per Algorithm 1 (Poisson).  G [E][6][N1^3], X [nrhs][E][N1^3]."""
+    """Y = AxLocal(X) = D^T G D X per element (Eq. 3, Poisson; D of Table 1).  G [E][6][N1^3],
+    X [nrhs][E][N1^3]."""
     D = _c64(D)
     G = _c64(G)
     X = _c64(X)
@@ -164,7 +165,7 @@ def ax_local(D, G, X) -> np.ndarray:
 
 
 def ax_envelope(D, G, X) -> np.ndarray:
-    """|D|^T |G| |D| |X| (the entrywise error envelope of AxLocal), by Algorithm 1 on the
+    """|D|^T |G| |D| |X| (the entrywise error envelope of AxLocal): Eq. 3 evaluated on the
     absolute values."""
     return ax_local(np.abs(D), np.abs(G), np.abs(X))
 

@@ -14,8 +14,8 @@
  *     Sec. 3.2 Eq. (5)-(6).
  *   - Geometric factors: Sec. 3.2 Eq. (7), by an explicit 3x3 inverse (NOT the adjugate-of-K
  *     factoring of Sec. 3.3 Eq. (12); that is what the GPU does).
- *   - AxLocal: Sec. 2.2 Eq. (3) with Lambda0 = I, Lambda1 = 0 (Poisson), in the loop order of
- *     Algorithm 1 (sum factorisation, one column at a time).
+ *   - AxLocal: Sec. 2.2 Eq. (3) with Lambda0 = I, Lambda1 = 0 (Poisson): the gradient blocks
+ *     D_r, D_s, D_t of Table 1 applied to the whole element, the factor block, then D^T.
  *   - Gather/scatter: Sec. 2.1 (the binary matrix Q) and Eq. (1).
  *
  * Readings where the paper is silent:
@@ -250,56 +250,73 @@ void orc_parallelepiped_h(int64_t E, const double* verts, double* h)
     }
 }
 
-/* AxLocal, Algorithm 1, Poisson case (Lambda0 = 1, Lambda1 = 0; Sec. 2.2 Eq. 3):
- *   x0 = sum_n D[i][n] x[n,j,k],  x1 = sum_n D[j][n] x[i,n,k],  x2 = sum_n D[k][n] x[i,j,n]
- *   r = g00 x0 + g01 x1 + g02 x2,  s = g01 x0 + g11 x1 + g12 x2,  t = g02 x0 + g12 x1 + g22 x2
- *   y[i,j,k] = sum_n D[n][i] r[n,j,k] + sum_n D[n][j] s[i,n,k] + sum_n D[n][k] t[i,j,n]
- * G [E][6][N1^3] (weights included), X, Y [nrhs][E][N1^3]. */
+/* One block of the discrete gradient of Table 1 applied to a whole element vector:
+ *   dir 0: D_r = I (x) I (x) Dh   (acts on the fastest index i of node [i,j,k]),
+ *   dir 1: D_s = I (x) Dh (x) I   (acts on j),
+ *   dir 2: D_t = Dh (x) I (x) I   (acts on k),
+ * or its transpose (trans != 0), written out from the Kronecker definition:
+ *   out[a, b, c] = sum_n M[.][n] in[...]  with M = Dh or Dh^T on the direction's index. */
+static void grad_block(int N1, const double* Dh, int dir, int trans, const double* in, double* out)
+{
+    const int st[3] = {1, N1, N1 * N1};
+    const int sd = st[dir];
+    for (int k = 0; k < N1; ++k)
+        for (int j = 0; j < N1; ++j)
+            for (int i = 0; i < N1; ++i) {
+                const int node[3] = {i, j, k};
+                const int a = node[dir];
+                const int base = i + j * N1 + k * N1 * N1 - a * sd;
+                double acc = 0.0;
+                for (int n = 0; n < N1; ++n) {
+                    const double m = trans ? Dh[n * N1 + a] : Dh[a * N1 + n];
+                    acc += m * in[base + n * sd];
+                }
+                out[i + j * N1 + k * N1 * N1] = acc;
+            }
+}
+
+/* AxLocal, Poisson case of Sec. 2.2 Eq. (3) (Lambda0 = I, Lambda1 = 0):
+ *   Y_e = D^T G_e D X_e,  D = [D_r; D_s; D_t] (Table 1),
+ * evaluated in the order the equation is written, one column at a time:
+ *   (1) the reference gradient u = D x: three whole-element vectors u_r, u_s, u_t;
+ *   (2) the block of diagonal factor matrices, per node v = G u with the symmetric 3x3 matrix
+ *       [[G00, G01, G02], [G01, G11, G12], [G02, G12, G22]];
+ *   (3) y = D^T v = D_r^T v_r + D_s^T v_s + D_t^T v_t.
+ * G [E][6][N1^3] (weights included, order 00,01,02,11,12,22), X, Y [nrhs][E][N1^3]. */
 void orc_ax_local(int64_t E, int N, const double* D, const double* G, int nrhs, const double* X,
                   double* Y)
 {
     const int N1 = N + 1, Np = N1 * N1 * N1;
 #pragma omp parallel
     {
-        double* r = (double*)malloc(sizeof(double) * 3 * Np);
-        double* s = r + Np;
-        double* t = s + Np;
+        double* u = (double*)malloc(sizeof(double) * 7 * Np);
+        double* v = u + 3 * Np;
+        double* tmp = v + 3 * Np;
 #pragma omp for schedule(static)
         for (int64_t e = 0; e < E; ++e) {
             const double* g = G + e * 6 * Np;
             for (int c = 0; c < nrhs; ++c) {
                 const double* x = X + ((int64_t)c * E + e) * Np;
                 double* y = Y + ((int64_t)c * E + e) * Np;
-                for (int k = 0; k < N1; ++k)
-                    for (int j = 0; j < N1; ++j)
-                        for (int i = 0; i < N1; ++i) {
-                            const int l = i + j * N1 + k * N1 * N1;
-                            double x0 = 0.0, x1 = 0.0, x2 = 0.0;
-                            for (int n = 0; n < N1; ++n) {
-                                x0 += D[i * N1 + n] * x[n + j * N1 + k * N1 * N1];
-                                x1 += D[j * N1 + n] * x[i + n * N1 + k * N1 * N1];
-                                x2 += D[k * N1 + n] * x[i + j * N1 + n * N1 * N1];
-                            }
-                            const double g00 = g[0 * Np + l], g01 = g[1 * Np + l], g02 = g[2 * Np + l];
-                            const double g11 = g[3 * Np + l], g12 = g[4 * Np + l], g22 = g[5 * Np + l];
-                            r[l] = g00 * x0 + g01 * x1 + g02 * x2;
-                            s[l] = g01 * x0 + g11 * x1 + g12 * x2;
-                            t[l] = g02 * x0 + g12 * x1 + g22 * x2;
-                        }
-                for (int k = 0; k < N1; ++k)
-                    for (int j = 0; j < N1; ++j)
-                        for (int i = 0; i < N1; ++i) {
-                            double y0 = 0.0, y1 = 0.0, y2 = 0.0;
-                            for (int n = 0; n < N1; ++n) {
-                                y0 += D[n * N1 + i] * r[n + j * N1 + k * N1 * N1];
-                                y1 += D[n * N1 + j] * s[i + n * N1 + k * N1 * N1];
-                                y2 += D[n * N1 + k] * t[i + j * N1 + n * N1 * N1];
-                            }
-                            y[i + j * N1 + k * N1 * N1] = y0 + y1 + y2;
-                        }
+                for (int d = 0; d < 3; ++d) grad_block(N1, D, d, 0, x, u + d * Np);
+                for (int l = 0; l < Np; ++l) {
+                    const double M[3][3] = {{g[0 * Np + l], g[1 * Np + l], g[2 * Np + l]},
+                                            {g[1 * Np + l], g[3 * Np + l], g[4 * Np + l]},
+                                            {g[2 * Np + l], g[4 * Np + l], g[5 * Np + l]}};
+                    for (int a = 0; a < 3; ++a) {
+                        double acc = 0.0;
+                        for (int b = 0; b < 3; ++b) acc += M[a][b] * u[b * Np + l];
+                        v[a * Np + l] = acc;
+                    }
+                }
+                for (int l = 0; l < Np; ++l) y[l] = 0.0;
+                for (int d = 0; d < 3; ++d) {
+                    grad_block(N1, D, d, 1, v + d * Np, tmp);
+                    for (int l = 0; l < Np; ++l) y[l] += tmp[l];
+                }
             }
         }
-        free(r);
+        free(u);
     }
 }
 
