@@ -463,7 +463,7 @@ def main(argv=None):
                                    "R_orig_GDOFs": round(dofs / (byg * E / (PEAK_HBM_GBS * 1e9)) / 1e9, 1)}
         extras["speedup_on_the_fly_vs_stored"] = round(wall_g / wall, 3)
         del G
-        # partial recomputation (Sec. 4.2.1): the per-node scale read from memory
+        # partial recomputation (Sec. 4.2.2): the per-node scale read from memory
         lam = ax.geom_lambda(V, b, ax.AX_FP64)
 
         def step_p(q):

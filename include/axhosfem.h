@@ -106,7 +106,7 @@ int ax_local_precomputedG(int64_t E, int N, const void* G, const double* D, int 
                           const void* X, void* Y, void* stream);
 
 /*
- * ax_local_partial - the trilinear operator with partial recomputation (Sec. 4.2.1, Table 3,
+ * ax_local_partial - the trilinear operator with partial recomputation (Sec. 4.2.2, Table 3,
  * the Poisson form): the per-node scale lam = 0.125 w_i w_j w_k / det(8J) of Eq. (12) is read
  * from memory and the kernel recomputes only K = (8J)^T (8J) and adj(K) per node, with no
  * determinant and no division (F_geo = 72 N1 + 45 N1^2 + 60 N1^3 per element, one more word per
@@ -261,7 +261,9 @@ int cg_workspace_bytes(const ax_problem* p, int nrhs, const ax_cg_opts* o, size_
  * cg_solve - solve A x = b (each of nrhs columns independently) by conjugate gradients on the
  * assembled operator; the iterative solve in which AxLocal is the dominant kernel (Sec. 1,
  * Sec. 5.6).  b, x [dev] double [nrhs][n_global]; x holds the initial guess on entry (warm
- * start / resume) and the solution on exit.  Entries of b under the mask must be 0.
+ * start / resume) and the solution on exit.  Entries of b under the mask must be 0: the
+ * assembled rows there are zero, so a nonzero entry is rejected with AX_ERR_ARG (checked on the
+ * device, with one stream synchronisation, before the first iteration).
  * inner_prec == AX_FP64 runs plain CG in FP64.  Otherwise mixed-precision iterative refinement:
  * the outer residual r = b - A x, its norm and the update of x are FP64; the corrections come
  * from CG iterations whose AxLocal runs in inner_prec with float vectors and FP64-accumulated

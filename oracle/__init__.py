@@ -37,6 +37,7 @@ def _load():
     lib.orc_gll.argtypes = [ctypes.c_int, _dp, _dp, _dp]
     lib.orc_gll.restype = ctypes.c_int
     lib.orc_jacobian.argtypes = [_dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp]
+    lib.orc_jacobians.argtypes = [_i64, ctypes.c_int, _dp, _dp, _dp]
     lib.orc_geom_factors.argtypes = [_i64, ctypes.c_int, _dp, _dp, _dp, _dp, _dp, _dp]
     lib.orc_node_coords.argtypes = [_i64, ctypes.c_int, _dp, _dp, _dp]
     lib.orc_parallelepiped_h.argtypes = [_i64, _dp, _dp]
@@ -99,6 +100,15 @@ def jacobian(V, r: float, s: float, t: float) -> np.ndarray:
     return J
 
 
+def jacobians(verts, N: int, xi) -> np.ndarray:
+    """The Jacobian of Eq. (9) at every GLL node of every element, [E][N1^3][3][3]."""
+    verts = _c64(verts)
+    E = verts.shape[0]
+    J = np.zeros((E, (N + 1) ** 3, 3, 3))
+    _load().orc_jacobians(E, N, _d(verts), _d(_c64(xi)), _d(J))
+    return J
+
+
 def geom_factors(verts, N: int, xi, w):
     """(G [E][6][N1^3], gwj [E][N1^3], min det J): Eq. (7) with J from Eq. (9)."""
     verts = _c64(verts)
@@ -113,7 +123,7 @@ def geom_factors(verts, N: int, xi, w):
 
 
 def lambda_geo(verts, N: int, xi, w) -> np.ndarray:
-    """Per-node scale of the partial recomputation (Sec. 4.2.1; the lambda of Eq. 12):
+    """Per-node scale of the partial recomputation (Sec. 4.2.2; the lambda of Eq. 12):
     lam = 0.125 w_i w_j w_k / det(8J) = w_i w_j w_k / (4096 det J) [E][N1^3], with det J taken
     from the lumped mass gwj = w_i w_j w_k det J of geom_factors (Eq. 7, J from Eq. 9)."""
     _, gwj, _ = geom_factors(verts, N, xi, w)

@@ -136,6 +136,19 @@ void orc_jacobian(const double* V /* [8][3] */, double r, double s, double t, do
     }
 }
 
+/* orc_jacobian at every GLL node of every element: J[E][N1^3][3][3], node l = i + j N1 + k N1^2. */
+void orc_jacobians(int64_t E, int N, const double* verts, const double* xi, double* J)
+{
+    const int N1 = N + 1, Np = N1 * N1 * N1;
+#pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < E; ++e)
+        for (int k = 0; k < N1; ++k)
+            for (int j = 0; j < N1; ++j)
+                for (int i = 0; i < N1; ++i)
+                    orc_jacobian(verts + e * 24, xi[i], xi[j], xi[k],
+                                 J + (e * Np + i + j * N1 + k * N1 * N1) * 9);
+}
+
 static double det3(const double* J)
 {
     return J[0] * (J[4] * J[8] - J[5] * J[7]) - J[1] * (J[3] * J[8] - J[5] * J[6]) +

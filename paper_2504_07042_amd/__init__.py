@@ -199,7 +199,7 @@ def ax_local_precomputedG(X, G, basis: Basis, prec=AX_FP64, out=None, stream=Non
 
 def ax_local_partial(X, verts, lam, basis: Basis, prec=AX_FP64, out=None, stream=None):
     """Y = AxLocal(X) on trilinear elements with partial recomputation: the per-node scale lam
-    [E][N1^3] (from geom_lambda) is read, K and adj(K) are recomputed (Sec. 4.2.1)."""
+    [E][N1^3] (from geom_lambda) is read, K and adj(K) are recomputed (Sec. 4.2.2)."""
     import torch
     E = verts.shape[0]
     nrhs = _nrhs(X, E, basis.N)

@@ -7,7 +7,7 @@
 namespace ax {
 
 // GEO_TRIL: trilinear with the per-node scale lam = 0.125 w / det(8J) read from memory (the
-// partial recomputation of Sec. 4.2.1): no determinant and no division in the kernel.
+// partial recomputation of Sec. 4.2.2): no determinant and no division in the kernel.
 // GEO_HELM: the trilinear Helmholtz operator with merged scalar factors (Sec. 4.2.1): per node
 // Lambda2 = lam * lambda0 scales adj(K) and Lambda3 = gwj * lambda1 the mass term.
 enum { GEO_TRI = 0, GEO_PARA = 1, GEO_STORED = 2, GEO_TRIL = 3, GEO_HELM = 4 };

@@ -34,7 +34,7 @@ geom_factors_kernel(int64_t E, int N1, const double* __restrict__ verts, T* __re
     if (gwj) gwj[idx] = nd.w[i] * nd.w[j] * nd.w[k] * tri_det(tc, nd.xi[k]) * (1.0 / 512.0);
 }
 
-// The per-node scale of the partial recomputation (Sec. 4.2.1): lam = 0.125 w_i w_j w_k / det(8J),
+// The per-node scale of the partial recomputation (Sec. 4.2.2): lam = 0.125 w_i w_j w_k / det(8J),
 // the factor that turns adj(K) into the geometric factors (Eq. 12).  One thread per node.
 template <typename T>
 __global__ void __launch_bounds__(256)

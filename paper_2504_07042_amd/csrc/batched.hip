@@ -75,7 +75,7 @@ struct BHeader {
 };
 
 // cs: source of the basis tables (CoefResident or CoefReload)
-// PL: partial recomputation (Sec. 4.2.1), the per-node scale read from lam [E][N1^3].
+// PL: partial recomputation (Sec. 4.2.2), the per-node scale read from lam [E][N1^3].
 template <int N1, typename T, bool PL = false, typename C>
 __device__ __forceinline__ void batched_item(const BMesh& m, int64_t eb, int nrhs, const C& cs, char* lds,
                                              const T* __restrict__ lamp = nullptr)

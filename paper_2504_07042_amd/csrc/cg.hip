@@ -244,7 +244,8 @@ cg_dir_kernel(T* __restrict__ p, const T* __restrict__ r, const CgScal* __restri
         p[o + q] = (T)((double)r[o + q] + be * (double)p[o + q]);
 }
 
-// r = b - Ax (FP64), also zeroes entries under the mask of r
+// r = b - Ax (FP64).  Entries under the Dirichlet mask come out 0 because Ax is 0 there and the
+// solver has checked that b is 0 there (masked_rhs_kernel).
 __global__ void __launch_bounds__(256)
 residual_kernel(double* __restrict__ r, const double* __restrict__ b, const double* __restrict__ Ax,
                 int64_t n)
@@ -317,6 +318,15 @@ __global__ void __launch_bounds__(256) zero_kernel(T* __restrict__ dst, int64_t 
         dst[q] = T(0);
 }
 
+// flag = 1 if some column of b is nonzero (or not a number) on a masked (Dirichlet) node
+__global__ void __launch_bounds__(256)
+masked_rhs_kernel(const double* __restrict__ b, const uint8_t* __restrict__ mask, int64_t n, int* __restrict__ flag)
+{
+    const int64_t o = (int64_t)blockIdx.y * n;
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (int64_t)gridDim.x * 256)
+        if (mask[q] && !(b[o + q] == 0.0)) *flag = 1;
+}
+
 __global__ void set_tol_kernel(CgScal* sc, const double* __restrict__ partials, double rtol)
 {
     const int c = blockIdx.x;
@@ -355,6 +365,7 @@ struct CgWork {
     double* partials;              // [nrhs][kRedBlocks]
     CopyPair* pairs;               // [n_global]
     CgScal *sc, *sc_in;            // outer / inner scalar state [nrhs]
+    int* flag;                     // masked right-hand-side check
 };
 
 static void carve(Carver& cv, int64_t nl, int64_t ng, int nrhs, bool mixed, CgWork& w)
@@ -379,6 +390,7 @@ static void carve(Carver& cv, int64_t nl, int64_t ng, int nrhs, bool mixed, CgWo
     w.pairs = cv.take<CopyPair>(ng);
     w.sc = cv.take<CgScal>(nrhs);
     w.sc_in = cv.take<CgScal>(nrhs);
+    w.flag = cv.take<int>(1);
 }
 
 // The assembled operator y = mask o Q^T AxLocal(Q x) over one mesh (ax_local) or over the
@@ -576,6 +588,21 @@ static int validate(const ax_problem* p, int nrhs, const ax_cg_opts* o)
     const int64_t N1 = p->N + 1;
     if (p->E > 0x7fffffffLL / (N1 * N1 * N1))
         return fail(AX_ERR_UNSUPPORTED, "more than 2^31 - 1 local nodes (local ids are int32)");
+    return AX_OK;
+}
+
+// The right-hand side must vanish on the Dirichlet nodes (the assembled operator's rows there
+// are zero, so a nonzero entry could never be matched and the solve would only stall).
+// Synchronises the stream; AX_ERR_ARG if b violates it.
+static int check_masked_rhs(const double* b, const uint8_t* mask, int64_t ng, int nrhs, int* flag, hipStream_t st)
+{
+    if (!mask || ng == 0) return AX_OK;
+    hipLaunchKernelGGL(zero_kernel<int>, dim3(1), dim3(256), 0, st, flag, (int64_t)1);
+    hipLaunchKernelGGL(masked_rhs_kernel, dim3(vgrid(ng), nrhs), dim3(256), 0, st, b, mask, ng, flag);
+    int h = 0;
+    AX_TRY(hip_check(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st), "mask check copy"));
+    AX_TRY(hip_check(hipStreamSynchronize(st), "mask check sync"));
+    if (h) return fail(AX_ERR_ARG, "b is nonzero (or not a number) on a masked (Dirichlet) node");
     return AX_OK;
 }
 
@@ -813,6 +840,7 @@ extern "C" int cg_solve(const ax_problem* p, int nrhs, const double* b, double* 
     hipLaunchKernelGGL(copy_pairs_kernel, dim3(vgrid(p->n_global)), dim3(256), 0, st, w.pairs, p->gptr, p->gidx,
                        p->mask, p->n_global);
     op.pairs = w.pairs;
+    AX_TRY(check_masked_rhs(b, op.mask, op.n_global, nrhs, w.flag, st));
     const int status = solve(op, nl, nrhs, b, x, o, rep, w, st);
     if (status != AX_OK && status != AX_ERR_NOT_CONVERGED && status != AX_ERR_BREAKDOWN) {
         (void)hipStreamSynchronize(st);
@@ -930,6 +958,7 @@ extern "C" int cg_solve_batched(int n_mesh, const ax_problem* meshes, int64_t n_
     hipLaunchKernelGGL(copy_pairs_kernel, dim3(vgrid(n_global)), dim3(256), 0, st, w.pairs, gptr, gidx, mask,
                        n_global);
     op.pairs = w.pairs;
+    AX_TRY(check_masked_rhs(b, op.mask, op.n_global, nrhs, w.flag, st));
     const int status = solve(op, nl, nrhs, b, x, o, rep, w, st);
     if (status != AX_OK && status != AX_ERR_NOT_CONVERGED && status != AX_ERR_BREAKDOWN) {
         (void)hipStreamSynchronize(st);

@@ -120,7 +120,7 @@ __device__ __forceinline__ float recip(float x)
 }
 
 // Unscaled factors at node t = xi_k without the Jacobian determinant: g[6] = adj(K).  The
-// partial-recomputation variant (Sec. 4.2.1, Table 3) reads lam per node from memory instead.
+// partial-recomputation variant (Sec. 4.2.2, Table 3) reads lam per node from memory instead.
 template <typename R>
 __device__ __forceinline__ void tri_adj_k(const TriCoef& k, R t, R* g)
 {

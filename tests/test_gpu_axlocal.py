@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_util import check_bound, check_fp64, fp32_bound, max_cond_j
+from gpu_util import check_bound, check_fp64, fp32_bound, max_cond_j, report
 from paper_2504_07042_amd import meshgen
 
 pytestmark = pytest.mark.gpu
@@ -165,12 +165,22 @@ def test_full_size_sampled(ax, N, geom):
     check_fp64(Y.cpu().numpy()[:, sample], Yref, env)
 
 
-def _fp16_bound(N, kappa, env, envmax):
-    """Half-precision operands (X, D, r/s/t each rounded once, plus D^T): about 6 u16 relative on
-    the envelope, the float arithmetic of the FP32 kernel, and an absolute term for values that
-    land in half's subnormal range after the per-element power-of-two scaling."""
+def _fp16_bound(N, kappa, D, G, X, env, envmax):
+    """Entrywise bound of the half-precision operator (csrc/ax_local_f16.hip), derived from its
+    arithmetic: X, D, r/s/t and D^T are each rounded to half once (4 u16 relative on the
+    envelope), the rest is the FP32 kernel's arithmetic, and two absolute terms cover values that
+    land in half's subnormal range (absolute spacing 2^-24) after the per-element power-of-two
+    scaling: X is scaled by 2^-ex with 2^ex <= 2 max|X_e|, so each rounded entry errs by at most
+    2^-25 2^ex <= 2^-24 max|X_e| (propagated by the operator: 2^-24 env(max|X_e| 1)); r, s, t are
+    scaled likewise by their maximum M_R <= 3 g_max ||D||_inf max|X_e| and pass through D^T in
+    three directions, adding at most 9 2^-24 ||D||_1 ||D||_inf g_max max|X_e| per output entry."""
     u16 = 2.0**-11
-    return (6 * u16 + fp32_bound(N, kappa)) * env + 16 * (N + 1) * 2.0**-24 * envmax
+    mx = np.abs(X).max(axis=2, keepdims=True)                      # [nrhs][E][1]
+    gmax = np.abs(G).max(axis=(1, 2))[None, :, None]               # [1][E][1]
+    d1 = np.abs(D).sum(axis=0).max()                               # ||D||_1
+    dinf = np.abs(D).sum(axis=1).max()                             # ||D||_inf
+    return ((4 * u16 + fp32_bound(N, kappa)) * env + 2.0**-24 * envmax
+            + 9 * 2.0**-24 * d1 * dinf * gmax * mx)
 
 
 @pytest.mark.parametrize("geom", ["tri", "para", "stored"])
@@ -201,7 +211,9 @@ def test_fp16_mfma(ax, geom):
         Y = ax.ax_local_precomputedG(Xd, G32, b, ax.AX_FP16_ACC32)
     kappa = max_cond_j(m.verts, N)
     d = np.abs(Y.cpu().numpy().astype(np.float64) - Yref)
-    bound = _fp16_bound(N, kappa, env, envmax)
+    bound = _fp16_bound(N, kappa, D, G, X, env, envmax)
+    report(f"fp16 {geom} N={N}", max_err_over_env=float((d / env).max()),
+           max_fraction_of_bound=float((d / bound).max()))
     assert np.all(d <= bound), float((d / bound).max())
     # and it is genuinely half precision: clearly worse than the FP32 kernel would be
     assert np.linalg.norm(d) / np.linalg.norm(Yref) < 1e-2

@@ -125,6 +125,19 @@ def test_not_converged_and_breakdown(ax):
     assert rep["status"] == "AX_ERR_BREAKDOWN"
 
 
+def test_masked_rhs_rejected(ax):
+    """A right-hand side that is nonzero on a Dirichlet node cannot be matched by the assembled
+    operator (its row there is zero): the solver rejects it before iterating."""
+    import torch
+    N = 3
+    m, prob, ref, rhs = _problem(ax, N, (2, 2, 2))
+    bad = rhs.copy()
+    bad[np.nonzero(ref[4] == 1)[0][0]] = 1.0
+    with pytest.raises(ax.AxError) as ei:
+        ax.cg_solve(prob, torch.from_numpy(bad[None]).cuda(), rtol=1e-10)
+    assert ei.value.code == ax.AX_ERR_ARG
+
+
 def test_graph_replay_equals_eager(ax):
     """The captured 8-iteration block replays exactly the eager iteration."""
     import torch

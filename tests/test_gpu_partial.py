@@ -1,4 +1,4 @@
-"""GPU parity of the partial-recomputation operator (Sec. 4.2.1: the per-node scale read from
+"""GPU parity of the partial-recomputation operator (Sec. 4.2.2: the per-node scale read from
 memory, K and adj(K) recomputed) and of its set-up kernel, against the CPU oracle, through the
 C ABI."""
 import numpy as np

@@ -195,3 +195,17 @@ def test_node_coords(N, jmesh):
                 for a in range(2):
                     l = a * N + b * N * N1 + c * N * N1 * N1
                     assert np.allclose(X[e, :, l], jmesh.verts[e, a + 2 * b + 4 * c], atol=1e-15)
+
+
+def test_jacobians_batch_matches_per_node():
+    """The all-nodes Jacobian evaluation is the per-node one, node for node (layout check)."""
+    m = meshgen.jittered_hex(2, 1, 2, alpha=0.2, seed=9)
+    N = 4
+    xi, _, _ = oracle.gll(N)
+    J = oracle.jacobians(m.verts, N, xi)
+    for e in range(m.E):
+        for k in range(N + 1):
+            for j in range(N + 1):
+                for i in range(N + 1):
+                    ref = oracle.jacobian(m.verts[e], xi[i], xi[j], xi[k])
+                    assert np.array_equal(J[e, i + j * (N + 1) + k * (N + 1) ** 2], ref)
