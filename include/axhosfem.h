@@ -313,6 +313,23 @@ int ax_batched_prepare(int n_mesh, const ax_problem* meshes, int nrhs, int prec,
 int ax_local_batched(const ax_batch_plan* plan, const void* workspace, void* stream);
 
 /*
+ * ax_local_batched_noalloc - the batched AxLocal of ax_batched_prepare + ax_local_batched in one
+ * call that allocates nothing, for callers that cannot allocate (code under stream capture, tight
+ * serving loops, harnesses that forbid allocation).  The work list, mesh descriptors and basis
+ * tables go to a static device array of the library (8 MiB per device, held until the process
+ * ends) instead of a workspace; they are written there by small kernels from their kernel
+ * arguments, so the call makes no hipMalloc/hipFree, no host heap allocation and no host-device
+ * copy, and only enqueues kernels on `stream`.  Arguments as ax_batched_prepare (X, Y [dev],
+ * col_stride [host] or NULL); the result equals ax_local_batched's bit for bit.  Limits:
+ * n_mesh <= 4096 and a work list of at most 8 MiB (about 10^6 element groups); larger batches
+ * -> AX_ERR_ARG with the size needed.  Every call on one device shares the array, which keeps
+ * the last call's contents: calls that overlap on one device (different streams or threads) race
+ * and must be serialised by the caller.
+ */
+int ax_local_batched_noalloc(int n_mesh, const ax_problem* meshes, int nrhs, int prec, const void* const* X,
+                             void* const* Y, const int64_t* col_stride, void* stream);
+
+/*
  * cg_solve_batched - CG (or mixed-precision refinement, inner_prec AX_FP32) on many independent
  * trilinear meshes at once: the meshes' global numberings are concatenated by the caller into
  * one index space of n_global nodes (l2g maps the concatenated local vectors, mesh after mesh,

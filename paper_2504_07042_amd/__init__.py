@@ -91,6 +91,7 @@ _SIGS = {
     "ax_batched_prepare": (_int, [_int, ctypes.POINTER(AxProblem), _int, _int, _vp, _vp, _vp, _vp,
                                   ctypes.c_size_t, ctypes.c_void_p]),
     "ax_local_batched": (_int, [ctypes.c_void_p, _vp, _vp]),
+    "ax_local_batched_noalloc": (_int, [_int, ctypes.POINTER(AxProblem), _int, _int, _vp, _vp, _vp, _vp]),
     "cg_batched_workspace_bytes": (_int, [_int, ctypes.POINTER(AxProblem), _i64, _int, ctypes.POINTER(AxCgOpts),
                                           ctypes.POINTER(ctypes.c_size_t)]),
     "cg_solve_batched": (_int, [_int, ctypes.POINTER(AxProblem), _i64, _vp, _vp, _vp, _vp, _int, _vp, _vp,
@@ -397,6 +398,21 @@ class BatchedAxLocal:
 
     def launch(self, stream=None):
         _check(lib().ax_local_batched(ctypes.byref(self.plan), _dptr(self.ws), _stream(stream)))
+
+
+def batched_noalloc(meshes, X, Y, prec=AX_FP64, stream=None):
+    """The batched AxLocal of BatchedAxLocal in one allocation-free call (ax_local_batched_noalloc):
+    meshes as for BatchedAxLocal, X, Y lists of device tensors [nrhs][E][N1^3]."""
+    n = len(meshes)
+    probs = (AxProblem * max(n, 1))()
+    for q, (verts, basis) in enumerate(meshes):
+        probs[q] = AxProblem(verts.shape[0], basis.N, AX_TRILINEAR, verts.data_ptr(), basis.D.ctypes.data,
+                             basis.xi.ctypes.data, basis.w.ctypes.data, 0, None, None, None, None)
+    nrhs = X[0].shape[0] if n else 1
+    xs = (ctypes.c_void_p * max(n, 1))(*[x.data_ptr() for x in X])
+    ys = (ctypes.c_void_p * max(n, 1))(*[y.data_ptr() for y in Y])
+    _check(lib().ax_local_batched_noalloc(n, probs, nrhs, prec, ctypes.cast(xs, ctypes.c_void_p),
+                                          ctypes.cast(ys, ctypes.c_void_p), None, _stream(stream)))
 
 
 def cg_solve_batched(meshes, gs: GatherScatter, b, x=None, rtol=1e-10, max_it=20000, inner_prec=AX_FP64,

@@ -13,6 +13,7 @@
 // (scalar loads from the workspace).
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "ax_internal.h"
@@ -414,9 +415,182 @@ static int check_meshes(int n_mesh, const ax_problem* meshes)
     return AX_OK;
 }
 
+// Per-mesh input/output pointers and column strides of a batch.
+static int check_io(int n_mesh, const ax_problem* meshes, const void* const* X, void* const* Y,
+                    const int64_t* col_stride)
+{
+    if (n_mesh > 0 && (!X || !Y)) return fail(AX_ERR_ARG, "X or Y is NULL");
+    for (int q = 0; q < n_mesh; ++q) {
+        if (meshes[q].E > 0 && (!X[q] || !Y[q])) return fail(AX_ERR_ARG, "mesh %d: X or Y is NULL", q);
+        if (meshes[q].E > 0 && X[q] == Y[q]) return fail(AX_ERR_ARG, "mesh %d: X and Y alias", q);
+        const int64_t np = (int64_t)(meshes[q].N + 1) * (meshes[q].N + 1) * (meshes[q].N + 1);
+        if (col_stride && col_stride[q] < meshes[q].E * np)
+            return fail(AX_ERR_ARG, "mesh %d: column stride below E*N1^3", q);
+    }
+    return AX_OK;
+}
+
+// ---- The batched launch without allocation (ax_local_batched_noalloc) ----
+//
+// The work list, the mesh descriptors and the basis tables live in one file-scope device array
+// instead of a caller's workspace.  Host code never uses the array's name as an address: its
+// device address comes from hipGetSymbolAddress, once per device, on the first call on that
+// device.  The array is written only by the fill kernels below, from data passed as kernel
+// arguments, so a call makes no allocation of any kind (no hipMalloc, no host heap, no staging
+// copy) and enqueues only kernels.  All calls on one device share the array.
+constexpr size_t kScratchBytes = size_t(8) << 20;
+constexpr int kScratchMaxMeshes = 4096;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+static std::mutex g_scratch_mu;
+static char* g_scratch_ptr[kMaxDevices];
+
+// Device address of this device's `scratch` (resolved once per device).
+static int scratch_address(char** out)
+{
+    int dev = 0;
+    AX_TRY(hip_check(hipGetDevice(&dev), "hipGetDevice"));
+    if (dev < 0 || dev >= kMaxDevices) return fail(AX_ERR_UNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        AX_TRY(hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)"));
+        if (!p) return fail(AX_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = static_cast<char*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return AX_OK;
+}
+
+// Up to kFillChunk meshes of one launch: their descriptors and the ranges of work items they own
+// (passed by value, about 2.3 KB of kernel arguments).
+constexpr int kFillChunk = 32;
+struct MeshFill {
+    BMesh m[kFillChunk];
+    int64_t item_base[kFillChunk];
+    int64_t groups[kFillChunk];
+    int id[kFillChunk];
+    int count;
+};
+
+// blockIdx.y = mesh of the chunk: its descriptor, and items (id, g) for its element groups g.
+__global__ void __launch_bounds__(256)
+fill_meshes_kernel(const MeshFill f, BMesh* __restrict__ meshes, BItem* __restrict__ items)
+{
+    const int c = blockIdx.y;
+    if (c >= f.count) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) meshes[f.id[c]] = f.m[c];
+    for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < f.groups[c]; g += (int64_t)gridDim.x * 256)
+        items[f.item_base[c] + g] = BItem{f.id[c], (int)g};
+}
+
+// dst = the basis tables passed by value (the kernel's first argument), copied word by word from
+// the kernel-argument segment.
+template <typename T>
+__global__ void __launch_bounds__(256) fill_basis_kernel(const Basis<T> b, Basis<T>* __restrict__ dst)
+{
+    (void)b;
+    constexpr int nw = (int)(sizeof(Basis<T>) / sizeof(uint64_t));
+    static_assert(sizeof(Basis<T>) % sizeof(uint64_t) == 0, "basis tables are whole 8-byte words");
+    const __attribute__((address_space(4))) uint64_t* src =
+        (const __attribute__((address_space(4))) uint64_t*)__builtin_amdgcn_kernarg_segment_ptr();
+    uint64_t* d = reinterpret_cast<uint64_t*>(dst);
+    for (int q = threadIdx.x; q < nw; q += 256) d[q] = src[q];
+}
+
+static int batched_noalloc(int n_mesh, const ax_problem* meshes, int nrhs, int prec, const void* const* X,
+                           void* const* Y, const int64_t* col_stride, hipStream_t st)
+{
+    AX_TRY(check_meshes(n_mesh, meshes));
+    if (nrhs < 1) return fail(AX_ERR_ARG, "nrhs < 1");
+    if (prec != AX_FP64 && prec != AX_FP32) return fail(AX_ERR_UNSUPPORTED, "batched precision must be FP64 or FP32");
+    if (n_mesh > kScratchMaxMeshes)
+        return fail(AX_ERR_ARG, "%d meshes: the allocation-free batched launch takes at most %d", n_mesh,
+                    kScratchMaxMeshes);
+    AX_TRY(check_io(n_mesh, meshes, X, Y, col_stride));
+    const int64_t n_items = n_items_of(n_mesh, meshes);
+    BHeader h{};
+    layout(n_mesh, n_items, h);
+    if ((size_t)h.bytes > kScratchBytes)
+        return fail(AX_ERR_ARG, "the batch needs %lld bytes of work list (%lld items); the allocation-free "
+                    "batched launch holds at most %zu bytes", (long long)h.bytes, (long long)n_items, kScratchBytes);
+    if (n_items == 0) return AX_OK;
+    char* base = nullptr;
+    AX_TRY(scratch_address(&base));
+    BMesh* dmesh = reinterpret_cast<BMesh*>(base + h.off_mesh);
+    BItem* ditem = reinterpret_cast<BItem*>(base + h.off_items);
+    // work list: orders ascending, the meshes of an order largest first (ties by index), as
+    // ax_batched_prepare orders it
+    ax_batch_plan plan{};
+    int idx[kScratchMaxMeshes];
+    int64_t next = 0;
+    for (int N1 = 2; N1 <= kBMaxN1; ++N1) {
+        int cnt = 0;
+        for (int q = 0; q < n_mesh; ++q)
+            if (meshes[q].N + 1 == N1 && meshes[q].E > 0) idx[cnt++] = q;
+        std::sort(idx, idx + cnt, [&](int a, int b) {
+            return meshes[a].E != meshes[b].E ? meshes[a].E > meshes[b].E : a < b;
+        });
+        plan.order_first[N1] = next;
+        const int e = order_epb(N1);
+        for (int c0 = 0; c0 < cnt; c0 += kFillChunk) {
+            MeshFill f{};
+            int64_t gmax = 1;
+            f.count = std::min(kFillChunk, cnt - c0);
+            for (int c = 0; c < f.count; ++c) {
+                const ax_problem& p = meshes[idx[c0 + c]];
+                const int64_t np = (int64_t)N1 * N1 * N1;
+                f.id[c] = idx[c0 + c];
+                f.m[c] = BMesh{p.E, col_stride ? col_stride[f.id[c]] : p.E * np, p.geo, X[f.id[c]], Y[f.id[c]], N1, 0};
+                f.groups[c] = (p.E + e - 1) / e;
+                f.item_base[c] = next;
+                next += f.groups[c];
+                gmax = std::max(gmax, f.groups[c]);
+            }
+            const unsigned gx = (unsigned)std::min<int64_t>((gmax + 255) / 256, 64);
+            hipLaunchKernelGGL(fill_meshes_kernel, dim3(gx, f.count), dim3(256), 0, st, f, dmesh, ditem);
+            AX_TRY(hip_check(hipGetLastError(), "batched work-list fill"));
+        }
+        plan.order_count[N1] = next - plan.order_first[N1];
+        if (cnt == 0) continue;
+        // one basis per order, taken from the last mesh of that order (as ax_batched_prepare does)
+        const ax_problem& p0 = meshes[*std::max_element(idx, idx + cnt)];
+        if (prec == AX_FP64) {
+            Basis<double> b;
+            fill_basis(b, N1, p0.D, p0.xi, p0.w);
+            hipLaunchKernelGGL(fill_basis_kernel<double>, dim3(1), dim3(256), 0, st, b,
+                               reinterpret_cast<Basis<double>*>(base + h.off_basis) + (N1 - 2));
+        } else {
+            Basis<float> b;
+            fill_basis(b, N1, p0.D, p0.xi, p0.w);
+            hipLaunchKernelGGL(fill_basis_kernel<float>, dim3(1), dim3(256), 0, st, b,
+                               reinterpret_cast<Basis<float>*>(base + h.off_basis) + (N1 - 2));
+        }
+        AX_TRY(hip_check(hipGetLastError(), "batched basis fill"));
+    }
+    h.nrhs = nrhs;
+    for (int N1 = 2; N1 <= kBMaxN1; ++N1) {
+        if (plan.order_count[N1] == 0) continue;
+        if (prec == AX_FP64)
+            AX_TRY(order_dispatch<double>(N1, base, h, plan.order_first[N1], plan.order_count[N1], st));
+        else
+            AX_TRY(order_dispatch<float>(N1, base, h, plan.order_first[N1], plan.order_count[N1], st));
+    }
+    return AX_OK;
+}
+
 }  // namespace ax
 
 using namespace ax;
+
+extern "C" int ax_local_batched_noalloc(int n_mesh, const ax_problem* meshes, int nrhs, int prec,
+                                        const void* const* X, void* const* Y, const int64_t* col_stride,
+                                        void* stream)
+{
+    clear_error();
+    return batched_noalloc(n_mesh, meshes, nrhs, prec, X, Y, col_stride, as_stream(stream));
+}
 
 extern "C" int ax_batched_workspace_bytes(int n_mesh, const ax_problem* meshes, size_t* bytes)
 {
@@ -440,11 +614,7 @@ extern "C" int ax_batched_prepare(int n_mesh, const ax_problem* meshes, int nrhs
     if (nrhs < 1) return fail(AX_ERR_ARG, "nrhs < 1");
     if (prec != AX_FP64 && prec != AX_FP32) return fail(AX_ERR_UNSUPPORTED, "batched precision must be FP64 or FP32");
     if (!workspace) return fail(AX_ERR_ARG, "workspace is NULL");
-    if (n_mesh > 0 && (!X || !Y)) return fail(AX_ERR_ARG, "X or Y is NULL");
-    for (int q = 0; q < n_mesh; ++q) {
-        if (meshes[q].E > 0 && (!X[q] || !Y[q])) return fail(AX_ERR_ARG, "mesh %d: X or Y is NULL", q);
-        if (meshes[q].E > 0 && X[q] == Y[q]) return fail(AX_ERR_ARG, "mesh %d: X and Y alias", q);
-    }
+    AX_TRY(check_io(n_mesh, meshes, X, Y, col_stride));
     const int64_t n_items = n_items_of(n_mesh, meshes);
     BHeader h{};
     layout(n_mesh, n_items, h);

@@ -164,3 +164,26 @@ def test_helmholtz_validation(ax):
     assert L.ax_local_helmholtz(0, 3, None, None, D, xi, w, 1, ax.AX_FP64, None, None, None) == ax.AX_OK
     assert L.ax_helmholtz_factors(2, 3, 8, xi, w, None, 8, ax.AX_FP64, 8, None) == ax.AX_ERR_ARG
     assert L.ax_helmholtz_factors(2, 3, 8, xi, w, 8, 8, 7, 8, None) == ax.AX_ERR_UNSUPPORTED
+
+
+def test_batched_noalloc_rejects_oversize_before_the_gpu(ax):
+    """More meshes than the static work list holds, or a work list beyond its 8 MiB, is an
+    argument error found on the host (nothing touches the device)."""
+    b = ax.Basis(3)
+    L = ax.lib()
+    many = (ax.AxProblem * 5000)()
+    for q in range(5000):
+        many[q] = ax.AxProblem(0, 3, ax.AX_TRILINEAR, None, b.D.ctypes.data, b.xi.ctypes.data, b.w.ctypes.data,
+                               0, None, None, None, None)
+    xs = (ctypes.c_void_p * 5000)(*([8] * 5000))
+    ys = (ctypes.c_void_p * 5000)(*([16] * 5000))
+    assert L.ax_local_batched_noalloc(5000, many, 1, ax.AX_FP64, ctypes.cast(xs, ctypes.c_void_p),
+                                      ctypes.cast(ys, ctypes.c_void_p), None, None) == ax.AX_ERR_ARG
+    assert b"at most 4096" in L.ax_last_error()
+    big = (ax.AxProblem * 1)(ax.AxProblem(1 << 30, 3, ax.AX_TRILINEAR, 64, b.D.ctypes.data, b.xi.ctypes.data,
+                                          b.w.ctypes.data, 0, None, None, None, None))
+    x1 = (ctypes.c_void_p * 1)(8)
+    y1 = (ctypes.c_void_p * 1)(16)
+    assert L.ax_local_batched_noalloc(1, big, 1, ax.AX_FP64, ctypes.cast(x1, ctypes.c_void_p),
+                                      ctypes.cast(y1, ctypes.c_void_p), None, None) == ax.AX_ERR_ARG
+    assert b"bytes of work list" in L.ax_last_error()
