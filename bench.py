@@ -6,9 +6,14 @@ trilinear hexes of the unit cube with interior vertices jittered by +-15 % of h 
 X ~ U[-1, 1] (16.8 M local DOFs).  Inputs are resident in HBM before timing; four X/Y pairs
 (1 GiB) rotate so that every step streams from HBM rather than the 256 MB Infinity Cache.
 
-Prints ONE JSON line (rank 0).  Extra fields: the stored-factor baseline on the same mesh (the
-roofline the paper raises), the parallelepiped variant (N = 7, 32^3 sheared cube), FP32, and the
-CPU oracle timed on a bounded sample.
+Prints ONE JSON line (rank 0).  Besides the headline, the default run adds: the measured HBM
+bandwidth and arithmetic peaks of the device; the stored-factor baseline (the roofline the paper
+raises), partial recomputation, Helmholtz, FP32, vector field and parallelepipeds on the same
+size; the trilinear order sweep N in {3,5,7,9,11,15} at ~2^24 local nodes (FP64 and FP32;
+on-the-fly, stored, partial); the FP64 and mixed-precision CG of the manufactured Poisson problem
+with a Table 5-style line; the 64-mesh, 8-column batch (graph-replayed) with a sampled oracle
+check; CG on the union of the batch (FP64 and FP32 reliable updates, one column); and the CPU
+oracle timed on a bounded sample.  --no-extras keeps the headline only.
 """
 from __future__ import annotations
 
@@ -26,6 +31,7 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 PEAK_FP64_TFS = 78.6        # MI355X FP64 vector (= FP64 matrix)
 PEAK_FP32_TFS = 157.3
+BASELINE_METRIC = "AxLocal GDOF/s + % roofline (N=7 trilinear FP64); mixed-prec CG speedup at 1e-10"
 
 
 def flops_per_element(N, geom="tri", nrhs=1):
@@ -87,6 +93,42 @@ def time_steps(fn, steps, warmup, nbuf):
     wall = time.perf_counter() - t0
     per = np.array([a.elapsed_time(b) for a, b in ev]) * 1e-3
     return wall, per
+
+
+def measure_peaks(ax, dev):
+    """Sustained rates of this device, for the time-based roofline of Sec. 3.4 (which divides by
+    measured bandwidth): the library's HBM copy probe over a 1 GiB footprint (two rotating pairs of
+    512 MiB buffers; one read and one write per byte) and its arithmetic probes (FP64 / FP32 fused
+    multiply-add on the vector ALU, FP32 unpacked as the library is built; 16x16x4 matrix-core
+    loops; FP64 vector and matrix loops issued together).  Medians of 10 timed launches."""
+    import torch
+    nb = 512 * 2**20
+    bufs = [(torch.ones(nb, dtype=torch.uint8, device=dev), torch.empty(nb, dtype=torch.uint8, device=dev))
+            for _ in range(2)]
+    _, per = time_steps(lambda q: ax.probe_copy(bufs[q][0], bufs[q][1]), 20, 10, 2)
+    del bufs
+    torch.cuda.empty_cache()
+    bmeas = 2 * nb / float(np.median(per)) / 1e9
+    out = {"hbm_copy_GBs": round(bmeas, 1), "hbm_copy_frac_of_8000": round(bmeas / PEAK_HBM_GBS, 3),
+           "copy_footprint_bytes": 2 * nb}
+    times = {}
+    for name, kind, iters in (("fp64_valu_fma", ax.AX_PROBE_FMA_F64, 1000),
+                              ("fp64_mfma_16x16x4", ax.AX_PROBE_MFMA_F64, 1000),
+                              ("fp64_valu_and_mfma_together", ax.AX_PROBE_MIX_F64, 1000),
+                              ("fp32_valu_fma_unpacked", ax.AX_PROBE_FMA_F32, 1000),
+                              ("fp32_mfma_16x16x4", ax.AX_PROBE_MFMA_F32, 1000)):
+        buf, fl = ax.probe_compute(kind, iters)
+        _, per = time_steps(lambda q: ax.probe_compute(kind, iters, out=buf), 10, 3, 1)
+        t = float(np.median(per))
+        times[name] = t
+        out[name + "_TFs"] = round(fl / t / 1e12, 2)
+    # the mixed probe runs the FP64 vector loop and the matrix loop of the two probes before it in
+    # the same waves: time / (sum of the separate times) near 1 means no overlap, near
+    # max / sum that the two units run concurrently
+    tv, tm, tb = times["fp64_valu_fma"], times["fp64_mfma_16x16x4"], times["fp64_valu_and_mfma_together"]
+    out["fp64_together_time_over_sum"] = round(tb / (tv + tm), 3)
+    out["fp64_together_time_over_max"] = round(tb / max(tv, tm), 3)
+    return out
 
 
 def cpu_baseline(mesh, N, X, budget_s=10.0):
@@ -153,11 +195,34 @@ def cg_solves(ax, meshgen, dev, N=7, grid=(32, 32, 32), rtol=1e-10, check_with_o
             ("mixed_fp32_reliable", dict(inner_prec=ax.AX_FP32, inner_rtol=0.1, refine=ax.AX_REFINE_RELIABLE)),
             ("mixed_fp32_restart", dict(inner_prec=ax.AX_FP32, inner_rtol=1e-5)),
             ("mixed_fp16_restart", dict(inner_prec=ax.AX_FP16_ACC32, inner_rtol=1e-2))]
+    # per-launch AxLocal time on this mesh in each precision (for the AxLocal share of a solve)
+    t_ax = {}
+    xl = meshgen.random_nodal_device(m.E, N, 1, seed=9, device=dev)
+    for pname, prec, T in (("fp64", ax.AX_FP64, torch.float64), ("fp32", ax.AX_FP32, torch.float32),
+                           ("fp16", ax.AX_FP16_ACC32, torch.float32)):
+        xx = xl.to(T)
+        yy = torch.empty_like(xx)
+        _, per = time_steps(lambda q: ax.ax_local(xx, V, b, ax.AX_TRILINEAR, prec, out=yy), 50, 20, 1)
+        t_ax[pname] = float(np.median(per))
+    del xl, xx, yy
+    f_ax, _ = flops_per_element(N, "tri")
     sols = {}
     for name, kw in runs:
         x, rep = ax.cg_solve(prob, rhs, rtol=rtol, max_it=40000, max_outer=60, **kw)
-        res[name] = {k: (round(v, 4) if isinstance(v, float) and k == "seconds" else v) for k, v in rep.items()}
+        ent = {k: (round(v, 4) if isinstance(v, float) and k == "seconds" else v) for k, v in rep.items()}
+        its, sec = rep["iterations"], rep["seconds"]
+        inner = {ax.AX_FP64: "fp64", ax.AX_FP32: "fp32", ax.AX_FP16_ACC32: "fp16"}[kw["inner_prec"]]
+        n_fp64_apps = 0 if inner == "fp64" else rep["outer_it"] + 1
+        if sec > 0 and its > 0:
+            # Table 5 style: GDOFS = global DOFs x iterations / time; GFLOPS counts per iteration
+            # the AxLocal flops of Table 2 (E F_ax) and 10 flops per global DOF of CG vector work
+            ent["table5"] = {"GDOFS": round(ng * its / sec / 1e9, 3),
+                             "GFLOPS": round((m.E * f_ax + 10 * ng) * its / sec / 1e9, 1),
+                             "axlocal_share_est": round((its * t_ax[inner] + n_fp64_apps * t_ax["fp64"]) / sec, 3),
+                             "iterations": its}
+        res[name] = ent
         sols[name] = x
+    res["axlocal_us_per_launch"] = {k: round(v * 1e6, 1) for k, v in t_ax.items()}
     t64 = res["fp64"]["seconds"]
     for name, _ in runs[1:]:
         res[name]["speedup_vs_fp64"] = round(t64 / res[name]["seconds"], 3) if res[name]["seconds"] > 0 else None
@@ -165,6 +230,9 @@ def cg_solves(ax, meshgen, dev, N=7, grid=(32, 32, 32), rtol=1e-10, check_with_o
     u = torch.sin(np.pi * XYZ[:, 0]) * torch.sin(np.pi * XYZ[:, 1]) * torch.sin(np.pi * XYZ[:, 2])
     ug[gs.l2g.long()] = u.reshape(-1)
     res["max_nodal_error_fp64"] = float((sols["fp64"][0] - ug).abs().max())
+    for name in sols:
+        if "table5" in res[name]:
+            res[name]["table5"]["max_nodal_error"] = float((sols[name][0] - ug).abs().max())
     if check_with_oracle:
         import oracle
         xi, w, D = oracle.gll(N)
@@ -187,42 +255,56 @@ def roofline_gdofs(N, geom, fpsize=8, peak_tf=PEAK_FP64_TFS, peak_gbs=PEAK_HBM_G
     return nrhs * (N + 1) ** 3 / max(t_cmp, t_mem) / 1e9, ("alu" if t_cmp >= t_mem else "hbm")
 
 
-def order_sweep(ax, meshgen, dev, orders=(3, 5, 7, 9, 11, 15), steps=20, warmup=3):
-    """Trilinear order sweep at E (N+1)^3 ~ 2^24 local nodes, +-15 % jitter, seed N: on-the-fly vs
-    stored factors, FP64 and FP32, with each kernel's time-based roofline."""
+def order_sweep(ax, meshgen, dev, orders=(3, 5, 7, 9, 11, 15), steps=20, warmup=10, nbuf=4, peaks=None):
+    """Trilinear order sweep at E (N+1)^3 ~ 2^24 local nodes, +-15 % jitter, seed N: on-the-fly,
+    stored factors and partial recomputation, FP64 and FP32, each against its time-based roofline
+    (datasheet peaks, and the measured ones when `peaks` is given).  nbuf X/Y pairs rotate (1 GiB
+    in FP64, 512 MiB in FP32) so every launch streams from HBM, not the 256 MB Infinity Cache."""
     import torch
     rows = []
+    bmeas = peaks["hbm_copy_GBs"] if peaks else None
     for N in orders:
         grid = meshgen.grid_for_nodes(N)
         m = meshgen.jittered_hex(*grid, alpha=0.15, seed=N)
         b = ax.Basis(N)
         V = torch.from_numpy(m.verts).to(dev)
-        X64 = [torch.from_numpy(meshgen.random_nodal(m.E, N, seed=N)).to(dev) for _ in range(2)]
+        X64 = torch.from_numpy(meshgen.random_nodal(m.E, N, seed=N)).to(dev)
         row = {"N": N, "E": m.E, "grid": list(grid), "local_dofs": m.E * (N + 1) ** 3}
         for pname, prec, T in (("fp64", ax.AX_FP64, torch.float64), ("fp32", ax.AX_FP32, torch.float32)):
-            X = [x.to(T) for x in X64]
+            X = [X64.to(T) for _ in range(nbuf)]
             Y = [torch.empty_like(x) for x in X]
             fpsize = 8 if T == torch.float64 else 4
             peak = PEAK_FP64_TFS if T == torch.float64 else PEAK_FP32_TFS
-            _, per = time_steps(lambda q: ax.ax_local(X[q], V, b, ax.AX_TRILINEAR, prec, out=Y[q]), steps, warmup, 2)
-            g_fly = row["local_dofs"] / per.mean() / 1e9
-            G, _ = ax.geom_factors(V, b, prec)
-            _, per_g = time_steps(lambda q: ax.ax_local_precomputedG(X[q], G, b, prec, out=Y[q]), steps, warmup, 2)
-            del G
-            g_st = row["local_dofs"] / per_g.mean() / 1e9
-            lam = ax.geom_lambda(V, b, prec)
-            _, per_p = time_steps(lambda q: ax.ax_local_partial(X[q], V, lam, b, prec, out=Y[q]), steps, warmup, 2)
-            del lam
-            g_pa = row["local_dofs"] / per_p.mean() / 1e9
-            r_pa, _ = roofline_gdofs(N, "partial", fpsize, peak)
-            r_fly, bound_fly = roofline_gdofs(N, "tri", fpsize, peak)
-            r_st, bound_st = roofline_gdofs(N, "stored", fpsize, peak)
-            row[pname] = {"on_the_fly_GDOFs": round(g_fly, 1), "R_eff_GDOFs": round(r_fly, 1), "bound": bound_fly,
-                          "pct_of_R_eff": round(g_fly / r_fly, 3), "stored_GDOFs": round(g_st, 1),
-                          "R_orig_GDOFs": round(r_st, 1), "pct_of_R_orig": round(g_st / r_st, 3),
-                          "speedup_vs_stored": round(g_fly / g_st, 2),
-                          "partial_GDOFs": round(g_pa, 1), "R_partial_GDOFs": round(r_pa, 1)}
+            pmeas = None
+            if peaks:
+                pmeas = peaks["fp64_valu_fma_TFs"] if T == torch.float64 else peaks["fp32_valu_fma_unpacked_TFs"]
+            res = {}
+            for var in ("tri", "stored", "partial"):
+                if var == "tri":
+                    fn = lambda q: ax.ax_local(X[q], V, b, ax.AX_TRILINEAR, prec, out=Y[q])
+                elif var == "stored":
+                    G, _ = ax.geom_factors(V, b, prec)
+                    fn = lambda q: ax.ax_local_precomputedG(X[q], G, b, prec, out=Y[q])
+                else:
+                    lam = ax.geom_lambda(V, b, prec)
+                    fn = lambda q: ax.ax_local_partial(X[q], V, lam, b, prec, out=Y[q])
+                _, per = time_steps(fn, steps, warmup, nbuf)
+                g = row["local_dofs"] / float(np.median(per)) / 1e9
+                r, bound = roofline_gdofs(N, var, fpsize, peak)
+                ent = {"GDOFs": round(g, 1), "us": round(float(np.median(per)) * 1e6, 1), "R_GDOFs": round(r, 1),
+                       "bound": bound, "frac_of_R": round(g / r, 3)}
+                if peaks:
+                    rm, bm = roofline_gdofs(N, var, fpsize, pmeas, bmeas)
+                    ent.update({"R_measured_GDOFs": round(rm, 1), "bound_measured": bm, "frac_of_R_measured": round(g / rm, 3)})
+                res[var] = ent
+                fn = None
+                G = lam = None
+                torch.cuda.empty_cache()
+            res["speedup_on_the_fly_vs_stored"] = round(res["tri"]["GDOFs"] / res["stored"]["GDOFs"], 2)
+            row[pname] = res
+            del X, Y
         rows.append(row)
+        print(f"sweep N={N}: " + json.dumps({k: row[k] for k in ("fp64", "fp32")}), file=sys.stderr, flush=True)
         del X64, V
         torch.cuda.empty_cache()
     return rows
@@ -286,7 +368,7 @@ def batched_run(ax, meshgen, dev, nrhs=8, steps=5, warmup=2, check_with_oracle=T
         torch.cuda.current_stream().wait_stream(s)
         torch.cuda.synchronize()
         wall_b, per_b = time_steps(lambda q: g.replay(), steps, warmup, 1)
-        Yb = [y.clone() for y in Y] if pname == "fp64" and check_with_oracle else None
+        Yb = [y.clone() for y in Y] if check_with_oracle else None
 
         def per_mesh(q):
             for (v, b), x, y in zip(meshes, X, Y):
@@ -305,10 +387,10 @@ def batched_run(ax, meshgen, dev, nrhs=8, steps=5, warmup=2, check_with_oracle=T
                 sel = np.sort(rng.choice(verts_h[q].shape[0], 16, replace=False))
                 xi, w, D = oracle.gll(N)
                 G, _, _ = oracle.geom_factors(verts_h[q][sel], N, xi, w)
-                xs = X[q][:, sel].cpu().numpy()
+                xs = X[q][:, sel].cpu().numpy().astype(np.float64)
                 yr = oracle.ax_local(D, G, xs)
                 env = oracle.ax_envelope(D, G, xs)
-                d = np.abs(Yb[q][:, sel].cpu().numpy() - yr) / np.maximum(env, 1e-300)
+                d = np.abs(Yb[q][:, sel].cpu().numpy().astype(np.float64) - yr) / np.maximum(env, 1e-300)
                 worst = max(worst, float(d.max()))
             res[pname]["oracle_sampled_max_err_over_env"] = worst
         del X, Y, bat, g
@@ -316,7 +398,7 @@ def batched_run(ax, meshgen, dev, nrhs=8, steps=5, warmup=2, check_with_oracle=T
     return res
 
 
-def batched_cg(ax, meshgen, dev, rtol=1e-10, nrhs=1):
+def batched_cg(ax, meshgen, dev, rtol=1e-10, nrhs=1, restart_leg=False):
     """CG on the block-diagonal union of the 64 batched meshes (same specs as batched_run), every
     AxLocal application of a step in one persistent launch: plain FP64 against mixed precision
     (FP32 inner AxLocal, reliable updates and restarted refinement), time to a true relative
@@ -336,8 +418,10 @@ def batched_cg(ax, meshgen, dev, rtol=1e-10, nrhs=1):
                        f"b ~ U[-1,1]", "rtol": rtol}
     del l2g
     runs = [("fp64", dict(inner_prec=ax.AX_FP64)),
-            ("mixed_fp32_reliable", dict(inner_prec=ax.AX_FP32, inner_rtol=0.1, refine=ax.AX_REFINE_RELIABLE)),
-            ("mixed_fp32_restart", dict(inner_prec=ax.AX_FP32, inner_rtol=1e-5))]
+            ("mixed_fp32_reliable", dict(inner_prec=ax.AX_FP32, inner_rtol=0.1, refine=ax.AX_REFINE_RELIABLE))]
+    if restart_leg:
+        runs.append(("mixed_fp32_restart", dict(inner_prec=ax.AX_FP32, inner_rtol=1e-5)))
+    res["legs"] = [r[0] for r in runs]
     for name, kw in runs:
         x, rep = ax.cg_solve_batched(meshes, gs, b, rtol=rtol, max_it=20000, max_outer=80, **kw)
         res[name] = {k: (round(v, 4) if isinstance(v, float) and k == "seconds" else v) for k, v in rep.items()}
@@ -361,14 +445,17 @@ def main(argv=None):
     ap.add_argument("--calib", action="store_true",
                     help="also run a plain 128 MiB device copy (counter calibration)")
     ap.add_argument("--no-cg", action="store_true", help="skip the CG / mixed-precision solves")
-    ap.add_argument("--batched", action="store_true",
-                    help="also run the batched workload: 64 meshes, E~U[512,32768], N in {3,5,7,9}, 8 columns")
-    ap.add_argument("--batched-cg", action="store_true",
-                    help="also run CG (FP64 vs mixed precision) on the union of the 64 batched meshes (minutes)")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched workload: 64 meshes, E~U[512,32768], N in {3,5,7,9}, 8 columns")
+    ap.add_argument("--no-batched-cg", action="store_true",
+                    help="skip CG (FP64 vs FP32 reliable updates) on the union of the 64 batched meshes (minutes)")
+    ap.add_argument("--batched-cg-restart", action="store_true",
+                    help="add the restarted-refinement leg to the batched CG")
     ap.add_argument("--esweep", action="store_true",
                     help="also run the element-count sweep E = 2^15..2^20 at N = 7 (trilinear FP64)")
-    ap.add_argument("--sweep", action="store_true",
-                    help="also run the order sweep N in {3,5,7,9,11,15} at ~2^24 local nodes")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the order sweep N in {3,5,7,9,11,15} at ~2^24 local nodes")
+    ap.add_argument("--no-peaks", action="store_true", help="skip the bandwidth and arithmetic probes")
     args = ap.parse_args(argv)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -427,10 +514,24 @@ def main(argv=None):
         "hbm_GBs_achieved": round(achieved_gbs, 1),
         "R_eff_GDOFs": round(dofs / max(t_cmp, t_mem) / 1e9, 1),
         "pct_of_R_eff": round(max(t_cmp, t_mem) / t_kernel, 4),
+        "time_base": "mean HIP-event time per launch on the launch stream (value uses the wall time of "
+                     "the timed steps)",
+        "frac_wall_clock": round((f_ax + f_geo) * E / (wall / args.steps) / 1e12 / PEAK_FP64_TFS, 4)
+        if compute_bound else round(by * E / (wall / args.steps) / 1e9 / PEAK_HBM_GBS, 4),
     }
 
+    peaks = None
+    if not args.no_peaks:
+        peaks = measure_peaks(ax, dev)
+        roofline["peak_measured"] = peaks["fp64_valu_fma_TFs"] if compute_bound else peaks["hbm_copy_GBs"]
+        roofline["frac_of_measured_peak"] = round(roofline["achieved"] / roofline["peak_measured"], 4)
+        t_cmp_m = (f_ax + f_geo) * E / (peaks["fp64_valu_fma_TFs"] * 1e12)
+        t_mem_m = by * E / (peaks["hbm_copy_GBs"] * 1e9)
+        roofline["R_eff_measured_GDOFs"] = round(dofs / max(t_cmp_m, t_mem_m) / 1e9, 1)
+        roofline["pct_of_R_eff_measured"] = round(max(t_cmp_m, t_mem_m) / t_kernel, 4)
+
     out = {
-        "metric": "AxLocal GDOF/s (N=7 trilinear FP64, on-the-fly geometric factors)",
+        "metric": BASELINE_METRIC,
         "value": round(gdofs, 3),
         "unit": "GDOF/s",
         "n_gpus": 1,
@@ -539,17 +640,18 @@ def main(argv=None):
                                          "hbm_GBs": round(byp * E / per_p.mean() / 1e9, 1)}
         out["extras"] = extras
 
-    if not args.no_cg:
+    if peaks:
+        out["measured_peaks"] = peaks
+    if not args.no_extras and not args.no_sweep:
+        out["order_sweep"] = order_sweep(ax, meshgen, dev, steps=20, warmup=10, peaks=peaks)
+
+    if not args.no_extras and not args.no_cg:
         out["cg"] = cg_solves(ax, meshgen, dev, check_with_oracle=not args.no_cpu)
 
-    if args.batched:
-        out["batched"] = batched_run(ax, meshgen, dev, steps=max(5, args.steps // 10), warmup=2,
-                                     check_with_oracle=not args.no_cpu)
-    if args.batched_cg:
-        out["batched_cg"] = batched_cg(ax, meshgen, dev)
-
-    if args.sweep:
-        out["order_sweep"] = order_sweep(ax, meshgen, dev, steps=max(10, args.steps // 2), warmup=3)
+    if not args.no_extras and not args.no_batched:
+        out["batched"] = batched_run(ax, meshgen, dev, steps=10, warmup=3, check_with_oracle=not args.no_cpu)
+    if not args.no_extras and not args.no_batched_cg:
+        out["batched_cg"] = batched_cg(ax, meshgen, dev, restart_leg=args.batched_cg_restart)
     if args.esweep:
         out["element_sweep"] = element_sweep(ax, meshgen, dev)
 

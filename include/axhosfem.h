@@ -345,6 +345,32 @@ int cg_solve_batched(int n_mesh, const ax_problem* meshes, int64_t n_global, con
                      const int64_t* gptr, const int32_t* gidx, const uint8_t* mask, int nrhs,
                      const double* b, double* x, const ax_cg_opts* o, ax_cg_report* rep, void* stream);
 
+/*
+ * Machine probes for the time-based roofline of Sec. 3.4, whose memory time divides the traffic
+ * by the measured bandwidth and whose compute time divides the flops by the peak of the units
+ * that run them (Table 4 lists measured bandwidths beside the theoretical ones).  The caller
+ * times the launches (e.g. with events on `stream`); the probes only enqueue work.
+ *
+ * ax_probe_copy - dst = src over `bytes` bytes [dev] (a multiple of 16, both pointers 16-byte
+ *   aligned, no overlap): one read and one write of every byte, for the sustained HBM bandwidth
+ *   (time the copy of a footprint well above the 256 MB Infinity Cache).  AX_ERR_ARG otherwise.
+ * ax_probe_compute - one launch of an arithmetic loop, `iters` iterations, 32 waves per compute
+ *   unit; *flops [host] receives the flops it executes.  kind:
+ *     AX_PROBE_FMA_F64 / AX_PROBE_FMA_F32   fused multiply-add on the vector ALU (FP32 without
+ *                                           packed instructions, as the library is built),
+ *     AX_PROBE_MFMA_F64 / AX_PROBE_MFMA_F32 16x16x4 matrix-core instructions,
+ *     AX_PROBE_MIX_F64                      both FP64 loops in the same waves: a time near the
+ *                                           sum of the two separate times means the units do
+ *                                           not overlap, near the larger one that they do.
+ *   out [dev] receives one value per thread: at least ax_probe_compute_elems() elements of the
+ *   kind's type (double for *_F64, float for *_F32).
+ */
+enum { AX_PROBE_FMA_F64 = 0, AX_PROBE_FMA_F32 = 1, AX_PROBE_MFMA_F64 = 2, AX_PROBE_MFMA_F32 = 3,
+       AX_PROBE_MIX_F64 = 4 };
+int ax_probe_copy(const void* src, void* dst, size_t bytes, void* stream);
+int ax_probe_compute_elems(size_t* n);
+int ax_probe_compute(int kind, int iters, void* out, double* flops, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -22,6 +22,7 @@ AX_OK, AX_ERR_ARG, AX_ERR_UNSUPPORTED, AX_ERR_HIP, AX_ERR_NOMEM, AX_ERR_NOT_CONV
 AX_TRILINEAR, AX_PARALLELEPIPED, AX_STORED_G = 0, 1, 2
 AX_FP64, AX_FP32, AX_FP16_ACC32 = 0, 1, 2
 AX_REFINE_RESTART, AX_REFINE_RELIABLE = 0, 1
+AX_PROBE_FMA_F64, AX_PROBE_FMA_F32, AX_PROBE_MFMA_F64, AX_PROBE_MFMA_F32, AX_PROBE_MIX_F64 = 0, 1, 2, 3, 4
 GS_QT, GS_Q, GS_QQT = 0, 1, 2
 
 _STATUS = {0: "AX_OK", -1: "AX_ERR_ARG", -2: "AX_ERR_UNSUPPORTED", -3: "AX_ERR_HIP",
@@ -91,6 +92,9 @@ _SIGS = {
     "ax_batched_prepare": (_int, [_int, ctypes.POINTER(AxProblem), _int, _int, _vp, _vp, _vp, _vp,
                                   ctypes.c_size_t, ctypes.c_void_p]),
     "ax_local_batched": (_int, [ctypes.c_void_p, _vp, _vp]),
+    "ax_probe_copy": (_int, [_vp, _vp, ctypes.c_size_t, _vp]),
+    "ax_probe_compute_elems": (_int, [ctypes.POINTER(ctypes.c_size_t)]),
+    "ax_probe_compute": (_int, [_int, _int, _vp, ctypes.POINTER(ctypes.c_double), _vp]),
     "ax_local_batched_noalloc": (_int, [_int, ctypes.POINTER(AxProblem), _int, _int, _vp, _vp, _vp, _vp]),
     "cg_batched_workspace_bytes": (_int, [_int, ctypes.POINTER(AxProblem), _i64, _int, ctypes.POINTER(AxCgOpts),
                                           ctypes.POINTER(ctypes.c_size_t)]),
@@ -398,6 +402,27 @@ class BatchedAxLocal:
 
     def launch(self, stream=None):
         _check(lib().ax_local_batched(ctypes.byref(self.plan), _dptr(self.ws), _stream(stream)))
+
+
+def probe_copy(src, dst, stream=None):
+    """dst = src with the library's copy probe (HBM bandwidth); both contiguous device tensors of
+    the same byte size (a multiple of 16)."""
+    nbytes = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == nbytes
+    _check(lib().ax_probe_copy(_dptr(src), _dptr(dst), nbytes, _stream(stream)))
+
+
+def probe_compute(kind, iters, out=None, stream=None):
+    """One launch of an arithmetic probe loop; returns (out tensor, flops of the launch)."""
+    import torch
+    n = ctypes.c_size_t()
+    _check(lib().ax_probe_compute_elems(ctypes.byref(n)))
+    dt = torch.float64 if kind in (AX_PROBE_FMA_F64, AX_PROBE_MFMA_F64, AX_PROBE_MIX_F64) else torch.float32
+    if out is None or out.numel() < n.value or out.dtype != dt:
+        out = torch.empty(n.value, dtype=dt, device="cuda")
+    fl = ctypes.c_double()
+    _check(lib().ax_probe_compute(kind, iters, _dptr(out), ctypes.byref(fl), _stream(stream)))
+    return out, fl.value
 
 
 def batched_noalloc(meshes, X, Y, prec=AX_FP64, stream=None):

@@ -24,7 +24,7 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall",
          "-I", os.path.join(ROOT, "include")]
 
 SOURCES = ["ax_common.cpp", "ax_local.hip", "ax_local_f64.hip", "ax_local_f32.hip", "ax_local_f16.hip",
-           "ax_setup.hip", "gs.hip", "cg.hip", "batched.hip"]
+           "ax_setup.hip", "gs.hip", "cg.hip", "batched.hip", "probe.hip"]
 
 
 def _compile(src: str) -> str:

@@ -31,23 +31,34 @@ constexpr bool is_trilinear(int geo) { return geo == GEO_TRI || geo == GEO_TRIL 
 #define AX_LDS_SWIZZLE 0
 #endif
 // LDS layout for N1 = 8: 0 = word i + 9 j + 72 k (row stride padded to 9); 1 = word
-// i + 8 j + 65 k with the r-pencils assigned to lanes k-fastest.  With 64-bit accesses served
-// 16 lanes per clock over 32 four-byte banks, layout 0 is conflict-free for the r- and s-pencils
-// and 2-way conflicted for the home columns; layout 1 is conflict-free for the home columns and
-// the r-pencils and 2-way conflicted for the s-pencils (no additive layout is conflict-free for
-// all three patterns).
+// i + 8 j + 65 k with the r-pencils assigned to lanes k-fastest; 2 (8-byte words only) = word
+// i + 8 j + 66 k, r-pencils k-fastest and moved as 16-byte accesses, s-pencils assigned so that
+// each group of 16 lanes takes the slices k and k + 4 (4-byte words: i + 8 j + 68 k, each group
+// of 32 lanes takes the slices k = 0, 2, 4, 6 or 1, 3, 5, 7, so i + 4 k covers the 32 banks; a
+// 16-byte r-pencil access starts at bank 8 j + 4 k, 8 lanes k = 0..7 cover them).  With 64-bit
+// accesses served 16 lanes per
+// clock over 32 four-byte banks, layout 0 is conflict-free for the r- and s-pencils and 2-way
+// conflicted for the home columns; layout 1 is conflict-free for the home columns and the
+// r-pencils and 2-way conflicted for the s-pencils (no additive layout is conflict-free for all
+// three patterns with lanes taking pencils in order); layout 2 is conflict-free for all three:
+// home columns i + 8 j (two rows j per 16 lanes) cover the 16 double-word banks, each 16-byte
+// r-pencil access starts at bank 2 k (8 lanes k = 0..7 cover the 16 banks), and s-pencil lanes
+// i + 2 k with k and k + 4 cover them too.
 #ifndef AX_LDS_LAYOUT
-#define AX_LDS_LAYOUT 1
+#define AX_LDS_LAYOUT 2
 #endif
 
-template <int N1>
+// Element shape of order N1 - 1 and its LDS layout; WB = bytes per stored value.
+template <int N1, int WB = 8>
 struct Shape {
+    static constexpr int NN = N1;                             // points per direction
     static constexpr int NT = N1 * N1;                        // lanes per element
     static constexpr bool SWZ = AX_LDS_SWIZZLE && N1 == 8;
+    static constexpr bool L2 = !SWZ && AX_LDS_LAYOUT == 2 && N1 == 8 && (WB == 8 || WB == 4);
     static constexpr bool L1 = !SWZ && AX_LDS_LAYOUT == 1 && N1 == 8;
-    static constexpr int SJ = L1 ? 8 : (N1 % 2 == 0) ? N1 + 1 : N1;   // LDS row stride
-    static constexpr int SK = L1 ? 65 : N1 * SJ;                      // LDS slice stride
-    static constexpr int FS = SWZ ? 512 : L1 ? 520 : N1 * SK;         // LDS words per field
+    static constexpr int SJ = (L1 || L2) ? 8 : (N1 % 2 == 0) ? N1 + 1 : N1;   // LDS row stride
+    static constexpr int SK = L2 ? (WB == 8 ? 66 : 68) : L1 ? 65 : N1 * SJ;    // LDS slice stride
+    static constexpr int FS = SWZ ? 512 : (L1 || L2) ? 8 * SK : N1 * SK;       // LDS words per field
     // LDS word of node (i, j, k) within one field
     __device__ static __forceinline__ int pos(int i, int j, int k)
     {
@@ -57,8 +68,15 @@ struct Shape {
             return k * SK + j * SJ + i;
     }
     // pencil lanes: the r-pencil (j, k) and the s-pencil (i, k) a lane owns
-    __device__ static __forceinline__ int rpa(int lane) { return L1 ? lane / N1 : lane % N1; }
-    __device__ static __forceinline__ int rpb(int lane) { return L1 ? lane % N1 : lane / N1; }
+    __device__ static __forceinline__ int rpa(int lane) { return (L1 || L2) ? lane / N1 : lane % N1; }
+    __device__ static __forceinline__ int rpb(int lane) { return (L1 || L2) ? lane % N1 : lane / N1; }
+    __device__ static __forceinline__ int spa(int lane) { return lane % N1; }
+    __device__ static __forceinline__ int spb(int lane)
+    {
+        if constexpr (L2 && WB == 8) return ((lane >> 3) & 1) * 4 + (lane >> 4);
+        if constexpr (L2 && WB == 4) return 2 * ((lane >> 3) & 3) + (lane >> 5);
+        return lane / N1;
+    }
     static constexpr int NP = N1 * N1 * N1;                   // nodes per element
     // elements per work-group: fill (nearly) whole waves while keeping LDS modest
     static constexpr int EPB = N1 == 2 ? 16 : N1 == 3 ? 7 : N1 == 4 ? 4 : N1 == 5 ? 5
@@ -182,6 +200,71 @@ __device__ __forceinline__ void contract_eo(const C& src, const T* in, T* out)
 #pragma unroll
         for (int n = 0; n < H; ++n) m = fma(TRANS ? c.Cm(n) : c.Rm(n), uo[n], m);
         out[H] = m;
+    }
+}
+
+// ---- FP32 contractions on the matrix cores ----
+//
+// v_mfma_f32_4x4x1f32 runs 16 independent 4x4 outer products per wave: block b = lane / 4 forms
+// acc_b[i][j] += a(lane 4b + i) * b(lane 4b + j) and lane 4b + j receives acc_b[i][j] in its
+// register i.  With b = a lane's own pencil value in[n] and a = C[4g + (lane % 4)][n] (a per-lane
+// coefficient register), N1 such instructions leave out[4g + i] of the lane's OWN pencil in
+// register i: the pencil contraction of the vector-unit code, in the same lane layout, with no
+// re-layout and no vector-ALU work.  A centro-antisymmetric C (C[N-a][N-n] = -C[a][n], which D
+// and D^T of GLL points are) gives the rows a >= N1/2 from the rows below through the reversed
+// pencil: sum_m C[a][m] in[N-m] = -out[N-a], so one set of coefficient registers (rows
+// 0..N1/2-1) serves all rows.  Even N1 only (an odd order's middle row would need its own set).
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+
+template <int N1>
+struct MfmaCoef {
+    static constexpr int H = N1 / 2;
+    static constexpr int G = (H + 3) / 4;  // groups of four output rows
+    float c[G][N1];                        // C[4g + lane % 4][n] (0 past row H-1)
+};
+
+// Coefficient registers of this lane for C = D (TRANS = false) or C = D^T, from the basis table.
+template <int N1, bool TRANS, typename B>
+__device__ __forceinline__ void mfma_coef_init(const B& bs, int lane, MfmaCoef<N1>& k)
+{
+    const int r = lane & 3;
+#pragma unroll
+    for (int g = 0; g < MfmaCoef<N1>::G; ++g)
+#pragma unroll
+        for (int n = 0; n < N1; ++n) {
+            float v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int a = 4 * g + q;
+                v[q] = a < MfmaCoef<N1>::H ? float(TRANS ? bs.D[n * N1 + a] : bs.D[a * N1 + n]) : 0.0f;
+            }
+            k.c[g][n] = r == 0 ? v[0] : r == 1 ? v[1] : r == 2 ? v[2] : v[3];
+        }
+}
+
+// out = C in for this lane's pencil (every lane of the wave must execute it: the matrix-core
+// instruction works on whole waves).
+template <int N1>
+__device__ __forceinline__ void contract_mfma(const MfmaCoef<N1>& k, const float* in, float* out)
+{
+    static_assert(N1 % 2 == 0, "matrix-core contraction: even N1");
+    constexpr int H = N1 / 2, N = N1 - 1;
+#pragma unroll
+    for (int g = 0; g < MfmaCoef<N1>::G; ++g) {
+        mfma_f4 acc = {0.f, 0.f, 0.f, 0.f}, rev = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int n = 0; n < N1; ++n) {
+            acc = __builtin_amdgcn_mfma_f32_4x4x1f32(k.c[g][n], in[n], acc, 0, 0, 0);
+            rev = __builtin_amdgcn_mfma_f32_4x4x1f32(k.c[g][n], in[N - n], rev, 0, 0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int a = 4 * g + q;
+            if (a < H) {
+                out[a] = acc[q];
+                out[N - a] = -rev[q];
+            }
+        }
     }
 }
 

@@ -44,7 +44,19 @@
 #define AX_MERGE_RS 1
 #endif
 
+// 1: the FP32 N1 = 8 kernels run their D-contractions on the matrix cores (contract_mfma, 96
+// v_mfma_f32_4x4x1f32 per element instead of 288 vector instructions); 0: on the vector ALU.
+// Measured interleaved on gfx950 (trilinear, N = 7, 32^3): 65.8 us with the matrix cores against
+// 52.0 us on the vector ALU, i.e. each 4x4x1 instruction costs about as much issue time as the
+// vector work it replaces plus register pressure (128 VGPRs and spills); so 0.
+#ifndef AX_F32_MFMA
+#define AX_F32_MFMA 0
+#endif
+
 namespace ax {
+
+template <int N1, bool EO, typename T>
+constexpr bool use_mfma() { return AX_F32_MFMA && EO && sizeof(T) == 4 && N1 == 8; }
 
 // Work-group shape for EPBX elements of order N1 - 1.
 template <int N1, int EPBX>
@@ -99,6 +111,49 @@ __device__ __forceinline__ P* at_bytes(P* base, uint32_t off)
     return reinterpret_cast<P*>(reinterpret_cast<C*>(base) + off);
 }
 
+// The r-pencil (., j, k) of a field: contiguous words i = 0..N1-1.  With layout 2 every pencil
+// starts on a 16-byte boundary and moves as 16-byte accesses (two doubles or four floats each).
+template <typename S, typename T>
+__device__ __forceinline__ void rpencil_read(const T* F, int j, int k, T* p)
+{
+    constexpr int N1 = S::NN;
+    if constexpr (S::L2) {
+        constexpr int W = 16 / sizeof(T);  // values per 16-byte access
+        typedef T v16 __attribute__((ext_vector_type(W)));
+        const v16* q = reinterpret_cast<const v16*>(F + S::pos(0, j, k));
+#pragma unroll
+        for (int m = 0; m < N1 / W; ++m) {
+            const v16 v = q[m];
+#pragma unroll
+            for (int u = 0; u < W; ++u) p[W * m + u] = v[u];
+        }
+    } else {
+#pragma unroll
+        for (int n = 0; n < N1; ++n) p[n] = F[S::pos(n, j, k)];
+    }
+}
+
+template <typename S, typename T>
+__device__ __forceinline__ void rpencil_write(T* F, int j, int k, const T* o)
+{
+    constexpr int N1 = S::NN;
+    if constexpr (S::L2) {
+        constexpr int W = 16 / sizeof(T);
+        typedef T v16 __attribute__((ext_vector_type(W)));
+        v16* q = reinterpret_cast<v16*>(F + S::pos(0, j, k));
+#pragma unroll
+        for (int m = 0; m < N1 / W; ++m) {
+            v16 v;
+#pragma unroll
+            for (int u = 0; u < W; ++u) v[u] = o[W * m + u];
+            q[m] = v;
+        }
+    } else {
+#pragma unroll
+        for (int a = 0; a < N1; ++a) F[S::pos(a, j, k)] = o[a];
+    }
+}
+
 // Kernel body.  GATHER: X is a global vector [nrhs][ldg] read through the local-to-global map
 // l2g (the Q of Sec. 2.1 fused into the load), so the solver never materialises Q x.  `cs` is the
 // source of the contraction coefficients (CoefResident or CoefReload).
@@ -108,13 +163,13 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
               const T* __restrict__ X, T* __restrict__ Y, const Basis<T>& bs,
               const int32_t* __restrict__ l2g, int64_t ldg, const C& cs)
 {
-    using S = Shape<N1>;
+    using S = Shape<N1, sizeof(T)>;
     using TL = Tile<N1, EPBX>;
     constexpr int NT = S::NT, FS = S::FS, NP = S::NP, EPB = TL::EPB;
     constexpr int BLOCK = TL::BLOCK;
     constexpr int NV = is_trilinear(GEO) ? 24 : 0;               // vertex words per element
     constexpr int VPT = (EPB * NV + BLOCK - 1) / BLOCK;          // vertex words per thread
-    __shared__ T smem[TL::SLOTS * 2 * FS];
+    __shared__ __attribute__((aligned(16))) T smem[TL::SLOTS * 2 * FS];
     __shared__ double svert[is_trilinear(GEO) ? EPB * 24 : 1];
     // (xi_k, w_k) pairs: the per-lane (xi_i, w_i), (xi_j, w_j) of the home columns, and xi_k, w_k
     // of the node loop for the kernels that do not keep them in scalar registers
@@ -126,10 +181,29 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
     T* __restrict__ A = smem + slot * 2 * FS;
     T* __restrict__ B = A + FS;
     const int i = lane % N1, j = lane / N1;    // home lane: node column (i, j, :)
-    const int pa = lane % N1, pb = lane / N1;  // s-pencil lane (i, k)
+    const int pa = S::spa(lane), pb = S::spb(lane);  // s-pencil lane (i, k)
     const int ra = S::rpa(lane), rb = S::rpb(lane);  // r-pencil lane (j, k)
     const int64_t nblk = (E + EPB - 1) / EPB;
     if (tid < 2 * N1) sxw[tid] = (tid & 1) ? bs.w[tid >> 1] : bs.xi[tid >> 1];
+    // the D-contractions: forward (D) and transposed (D^T), on the matrix cores or the vector ALU
+    constexpr bool MF = use_mfma<N1, EO, T>();
+    MfmaCoef<MF ? N1 : 2> kD, kT;
+    if constexpr (MF) {
+        mfma_coef_init<N1, false>(bs, (int)(threadIdx.x & 63), kD);
+        mfma_coef_init<N1, true>(bs, (int)(threadIdx.x & 63), kT);
+    }
+    auto fwd = [&](const T* in, T* out) {
+        if constexpr (MF)
+            contract_mfma<N1>(kD, in, out);
+        else
+            contract<N1, false, EO>(cs, in, out);
+    };
+    auto bwd = [&](const T* in, T* out) {
+        if constexpr (MF)
+            contract_mfma<N1>(kT, in, out);
+        else
+            contract<N1, true, EO>(cs, in, out);
+    };
 
     // Items are (element group, column) pairs walked in order; each work-group strides over the
     // element groups.  The next item's X (and vertices) are fetched into registers while the
@@ -195,7 +269,7 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
     // where the trilinear prelude runs: at the item start (before the prefetch registers are
     // live) or between the forward r/s contractions and the pointwise stage
     constexpr bool EARLY = AX_EARLY_PRELUDE;
-    TriCoef tc;
+    TriCoefT<T> tc;
     double h[6];
     while (eb < nblk) {
         const bool active = slot_active(eb);
@@ -219,13 +293,15 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
             if constexpr (is_trilinear(GEO)) {
                 if (c == 0) {
                     const double* sv = svert + (slot < EPB ? slot : 0) * 24;
+                    TriCoef t64;
                     tri_prelude([&](int v, int q) { return sv[v * 3 + q]; }, sxw[2 * i], sxw[2 * j],
-                                sxw[2 * i + 1], sxw[2 * j + 1], tc);
+                                sxw[2 * i + 1], sxw[2 * j + 1], t64);
+                    tri_narrow(t64, tc);
                 }
             }
         }
         T x2[N1];
-        contract<N1, false, EO>(cs, xr, x2);  // x2 = D_t x
+        fwd(xr, x2);  // x2 = D_t x
         T xn[N1];
         load_x(eb_n, c_n, xn);
         if (last_col) load_v(eb_n, vr);
@@ -234,14 +310,12 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
         T o1[N1];
         {
             T p[N1], o[N1];
-#pragma unroll
-            for (int n = 0; n < N1; ++n) p[n] = A[S::pos(n, ra, rb)];
-            contract<N1, false, EO>(cs, p, o);
-#pragma unroll
-            for (int a = 0; a < N1; ++a) B[S::pos(a, ra, rb)] = o[a];
+            rpencil_read<S>(A, ra, rb, p);
+            fwd(p, o);
+            rpencil_write<S>(B, ra, rb, o);
 #pragma unroll
             for (int n = 0; n < N1; ++n) p[n] = A[S::pos(pa, n, pb)];
-            contract<N1, false, EO>(cs, p, o1);
+            fwd(p, o1);
         }
         __syncthreads();
         // P2: x1 -> A; (per-element geometry invariants of the home column from the staged vertices)
@@ -250,8 +324,10 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
         if constexpr (is_trilinear(GEO) && !EARLY) {
             if (c == 0) {
                 const double* sv = svert + (slot < EPB ? slot : 0) * 24;
+                TriCoef t64;
                 tri_prelude([&](int v, int q) { return sv[v * 3 + q]; }, sxw[2 * i], sxw[2 * j], sxw[2 * i + 1],
-                            sxw[2 * j + 1], tc);
+                            sxw[2 * j + 1], t64);
+                tri_narrow(t64, tc);
             }
         }
         __syncthreads();
@@ -294,7 +370,7 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
             tt[k] = fma(g[2], x0, fma(g[4], x1, g[5] * xx2));
         }
         T y2[N1];
-        contract<N1, true, EO>(cs, tt, y2);  // D_t^T t
+        bwd(tt, y2);  // D_t^T t
         // Helmholtz: Lambda3 and this item's X at the home column for the mass term, loaded here
         // (X again, now from the cache) so that they are in flight during the next phase
         T l3v[GEO == GEO_HELM ? N1 : 1], xv[GEO == GEO_HELM ? N1 : 1];
@@ -308,14 +384,12 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
         // P4: D_r^T r in place on the r-pencils; D_s^T s into registers
         {
             T p[N1], o[N1];
-#pragma unroll
-            for (int n = 0; n < N1; ++n) p[n] = B[S::pos(n, ra, rb)];
-            contract<N1, true, EO>(cs, p, o);
-#pragma unroll
-            for (int a = 0; a < N1; ++a) B[S::pos(a, ra, rb)] = o[a];
+            rpencil_read<S>(B, ra, rb, p);
+            bwd(p, o);
+            rpencil_write<S>(B, ra, rb, o);
 #pragma unroll
             for (int n = 0; n < N1; ++n) p[n] = A[S::pos(pa, n, pb)];
-            contract<N1, true, EO>(cs, p, o1);
+            bwd(p, o1);
 #if AX_MERGE_RS
             // each s-pencil is read and written by its own lane only
 #pragma unroll
@@ -366,13 +440,28 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
 #ifndef AX_HELM_MINW
 #define AX_HELM_MINW 3
 #endif
-template <int N1, int GEO>
-constexpr int min_waves() { return (GEO == GEO_HELM && N1 == 8) ? AX_HELM_MINW : Shape<N1>::MINW; }
+// FP32 at N1 = 8: waves per SIMD the register allocation targets.  Measured interleaved at
+// N = 7, 32^3 with LDS layout 2: the trilinear kernel is fastest at four (49.3 us; five spill 6
+// registers, 52.0 us; six 58.2 us), partial recomputation at five (47.0 vs 48.6 us at four),
+// parallelepipeds and stored factors within 1 % of each other from four to six.
+#ifndef AX_MINW_F32
+#define AX_MINW_F32 5
+#endif
+#ifndef AX_MINW_F32_TRI
+#define AX_MINW_F32_TRI 4
+#endif
+template <int N1, int GEO, typename T>
+constexpr int min_waves()
+{
+    return (GEO == GEO_HELM && N1 == 8 && sizeof(T) == 8) ? AX_HELM_MINW
+           : (N1 == 8 && sizeof(T) == 4)                 ? (GEO == GEO_TRI ? AX_MINW_F32_TRI : AX_MINW_F32)
+                                                         : Shape<N1>::MINW;
+}
 
 // Entry points: the tables of orders that fit the scalar register file stay resident; the
 // others are reloaded per output row through the kernel-argument segment (one struct argument).
 template <int N1, int GEO, bool EO, bool GATHER, int EPBX, typename T>
-__global__ void __launch_bounds__((Tile<N1, EPBX>::BLOCK), (min_waves<N1, GEO>()))
+__global__ void __launch_bounds__((Tile<N1, EPBX>::BLOCK), (min_waves<N1, GEO, T>()))
 ax_local_kernel(int64_t E, int nrhs, const double* __restrict__ geo, const T* __restrict__ Gs,
                 const T* __restrict__ X, T* __restrict__ Y, const Basis<T> bs,
                 const int32_t* __restrict__ l2g, int64_t ldg)
@@ -381,7 +470,7 @@ ax_local_kernel(int64_t E, int nrhs, const double* __restrict__ geo, const T* __
 }
 
 template <int N1, int GEO, bool EO, bool GATHER, int EPBX, typename T>
-__global__ void __launch_bounds__((Tile<N1, EPBX>::BLOCK), (min_waves<N1, GEO>()))
+__global__ void __launch_bounds__((Tile<N1, EPBX>::BLOCK), (min_waves<N1, GEO, T>()))
 ax_local_kernel_rl(const AxArgs<T> ka)
 {
     const CoefReload<T> cs = karg_coefs<T, AxArgs<T>>();

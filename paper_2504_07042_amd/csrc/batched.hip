@@ -45,9 +45,11 @@ template <int N1>
 struct BShape {
     static constexpr int NT = N1 * N1;
     static constexpr int EPB = kBBlock / NT > 64 ? 64 : kBBlock / NT;
-    static constexpr int SJ = Shape<N1>::SJ, SK = Shape<N1>::SK, FS = Shape<N1>::FS, NP = Shape<N1>::NP;
+    static constexpr int NP = Shape<N1>::NP;
     template <typename T>
-    static constexpr size_t lds_bytes() { return (size_t)EPB * 2 * FS * sizeof(T) + (size_t)EPB * 24 * 8; }
+    static constexpr int FS = Shape<N1, sizeof(T)>::FS;
+    template <typename T>
+    static constexpr size_t lds_bytes() { return (size_t)EPB * 2 * FS<T> * sizeof(T) + (size_t)EPB * 24 * 8; }
 };
 
 template <typename T>
@@ -82,7 +84,7 @@ __device__ __forceinline__ void batched_item(const BMesh& m, int64_t eb, int nrh
                                              const T* __restrict__ lamp = nullptr)
 {
     using S = BShape<N1>;
-    constexpr int NT = S::NT, EPB = S::EPB, FS = S::FS, NP = S::NP;
+    constexpr int NT = S::NT, EPB = S::EPB, FS = S::template FS<T>, NP = S::NP;
     T* smem = reinterpret_cast<T*>(lds);
     double* svert = reinterpret_cast<double*>(lds + (size_t)EPB * 2 * FS * sizeof(T));
     const int tid = threadIdx.x;
@@ -103,11 +105,13 @@ __device__ __forceinline__ void batched_item(const BMesh& m, int64_t eb, int nrh
         svert[q] = off < m.E * 24 ? m.verts[off] : 0.0;
     }
     __syncthreads();
-    TriCoef tc;
+    TriCoefT<T> tc;
     if (inslot) {
         const double* sv = svert + slot * 24;
         const C b = cs.row();
-        tri_prelude([&](int v, int q) { return sv[v * 3 + q]; }, b.xi(i), b.xi(j), b.w(i), b.w(j), tc);
+        TriCoef t64;
+        tri_prelude([&](int v, int q) { return sv[v * 3 + q]; }, b.xi(i), b.xi(j), b.w(i), b.w(j), t64);
+        tri_narrow(t64, tc);
     }
     for (int c = 0; c < nrhs; ++c) {
         const int64_t base = (int64_t)c * m.ld + (active ? e : 0) * NP;
@@ -116,7 +120,7 @@ __device__ __forceinline__ void batched_item(const BMesh& m, int64_t eb, int nrh
         for (int k = 0; k < N1; ++k) xr[k] = active ? X[base + i + j * N1 + k * NT] : T(0);
         if (inslot) {
 #pragma unroll
-            for (int k = 0; k < N1; ++k) A[Shape<N1>::pos(i, j, k)] = xr[k];
+            for (int k = 0; k < N1; ++k) A[Shape<N1, sizeof(T)>::pos(i, j, k)] = xr[k];
         }
         contract<N1, false, true>(cs, xr, x2);
         __syncthreads();
@@ -124,12 +128,12 @@ __device__ __forceinline__ void batched_item(const BMesh& m, int64_t eb, int nrh
         if (inslot) {
             T p[N1], o[N1];
 #pragma unroll
-            for (int n = 0; n < N1; ++n) p[n] = A[Shape<N1>::pos(n, pa, pb)];
+            for (int n = 0; n < N1; ++n) p[n] = A[Shape<N1, sizeof(T)>::pos(n, pa, pb)];
             contract<N1, false, true>(cs, p, o);
 #pragma unroll
-            for (int a = 0; a < N1; ++a) B[Shape<N1>::pos(a, pa, pb)] = o[a];
+            for (int a = 0; a < N1; ++a) B[Shape<N1, sizeof(T)>::pos(a, pa, pb)] = o[a];
 #pragma unroll
-            for (int n = 0; n < N1; ++n) p[n] = A[Shape<N1>::pos(pa, n, pb)];
+            for (int n = 0; n < N1; ++n) p[n] = A[Shape<N1, sizeof(T)>::pos(pa, n, pb)];
             contract<N1, false, true>(cs, p, o1);
         }
         // Partial recomputation: all N1 scale loads of the column issued before the barrier
@@ -146,14 +150,14 @@ __device__ __forceinline__ void batched_item(const BMesh& m, int64_t eb, int nrh
         __syncthreads();
         if (inslot) {
 #pragma unroll
-            for (int a = 0; a < N1; ++a) A[Shape<N1>::pos(pa, a, pb)] = o1[a];
+            for (int a = 0; a < N1; ++a) A[Shape<N1, sizeof(T)>::pos(pa, a, pb)] = o1[a];
         }
         __syncthreads();
         T tt[N1];
         if (inslot) {
 #pragma unroll
             for (int k = 0; k < N1; ++k) {
-                const int l = Shape<N1>::pos(i, j, k);
+                const int l = Shape<N1, sizeof(T)>::pos(i, j, k);
                 T x0 = B[l], x1 = A[l], xx2 = x2[k];
                 T g[6], lam;
                 const C b = cs.row();
@@ -180,23 +184,23 @@ __device__ __forceinline__ void batched_item(const BMesh& m, int64_t eb, int nrh
         if (inslot) {
             T p[N1], o[N1];
 #pragma unroll
-            for (int n = 0; n < N1; ++n) p[n] = B[Shape<N1>::pos(n, pa, pb)];
+            for (int n = 0; n < N1; ++n) p[n] = B[Shape<N1, sizeof(T)>::pos(n, pa, pb)];
             contract<N1, true, true>(cs, p, o);
 #pragma unroll
-            for (int a = 0; a < N1; ++a) B[Shape<N1>::pos(a, pa, pb)] = o[a];
+            for (int a = 0; a < N1; ++a) B[Shape<N1, sizeof(T)>::pos(a, pa, pb)] = o[a];
 #pragma unroll
-            for (int n = 0; n < N1; ++n) p[n] = A[Shape<N1>::pos(pa, n, pb)];
+            for (int n = 0; n < N1; ++n) p[n] = A[Shape<N1, sizeof(T)>::pos(pa, n, pb)];
             contract<N1, true, true>(cs, p, o1);
         }
         __syncthreads();
         if (inslot) {
 #pragma unroll
-            for (int a = 0; a < N1; ++a) B[Shape<N1>::pos(pa, a, pb)] += o1[a];
+            for (int a = 0; a < N1; ++a) B[Shape<N1, sizeof(T)>::pos(pa, a, pb)] += o1[a];
         }
         __syncthreads();
         if (active) {
 #pragma unroll
-            for (int k = 0; k < N1; ++k) Y[base + i + j * N1 + k * NT] = B[Shape<N1>::pos(i, j, k)] + y2[k];
+            for (int k = 0; k < N1; ++k) Y[base + i + j * N1 + k * NT] = B[Shape<N1, sizeof(T)>::pos(i, j, k)] + y2[k];
         }
         __syncthreads();
     }

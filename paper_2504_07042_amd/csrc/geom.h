@@ -22,16 +22,34 @@
 
 namespace ax {
 
-struct TriCoef {
-    double q0, q1, q2;  // K00(t) = |col0|^2
-    double p0, p1, p2;  // K11(t) = |col1|^2
-    double k22;         // K22    = |col2|^2
-    double m0, m1, m2;  // K01(t) = col0 . col1
-    double n0, n1;      // K02(t) = col0 . col2
-    double o0, o1;      // K12(t) = col1 . col2
-    double d0, d1, d2;  // det(8J)(t) = col0 . (col1 x col2)
-    double cw;          // 0.125 w_i w_j
+// Per-column coefficients, formed in double; kernels that evaluate the factors in float keep a
+// float copy (TriCoefT<float>): each coefficient is rounded to float once instead of at every use,
+// with the same values.
+template <typename C>
+struct TriCoefT {
+    C q0, q1, q2;  // K00(t) = |col0|^2
+    C p0, p1, p2;  // K11(t) = |col1|^2
+    C k22;         // K22    = |col2|^2
+    C m0, m1, m2;  // K01(t) = col0 . col1
+    C n0, n1;      // K02(t) = col0 . col2
+    C o0, o1;      // K12(t) = col1 . col2
+    C d0, d1, d2;  // det(8J)(t) = col0 . (col1 x col2)
+    C cw;          // 0.125 w_i w_j
 };
+using TriCoef = TriCoefT<double>;
+
+template <typename C>
+__device__ __forceinline__ void tri_narrow(const TriCoef& k, TriCoefT<C>& o)
+{
+    o.q0 = C(k.q0); o.q1 = C(k.q1); o.q2 = C(k.q2);
+    o.p0 = C(k.p0); o.p1 = C(k.p1); o.p2 = C(k.p2);
+    o.k22 = C(k.k22);
+    o.m0 = C(k.m0); o.m1 = C(k.m1); o.m2 = C(k.m2);
+    o.n0 = C(k.n0); o.n1 = C(k.n1);
+    o.o0 = C(k.o0); o.o1 = C(k.o1);
+    o.d0 = C(k.d0); o.d1 = C(k.d1); o.d2 = C(k.d2);
+    o.cw = C(k.cw);
+}
 
 __device__ __forceinline__ double dot3(const double* a, const double* b)
 {
@@ -121,8 +139,8 @@ __device__ __forceinline__ float recip(float x)
 
 // Unscaled factors at node t = xi_k without the Jacobian determinant: g[6] = adj(K).  The
 // partial-recomputation variant (Sec. 4.2.2, Table 3) reads lam per node from memory instead.
-template <typename R>
-__device__ __forceinline__ void tri_adj_k(const TriCoef& k, R t, R* g)
+template <typename R, typename C>
+__device__ __forceinline__ void tri_adj_k(const TriCoefT<C>& k, R t, R* g)
 {
     const R K00 = fma(fma(R(k.q2), t, R(k.q1)), t, R(k.q0));
     const R K11 = fma(fma(R(k.p2), t, R(k.p1)), t, R(k.p0));
@@ -140,8 +158,8 @@ __device__ __forceinline__ void tri_adj_k(const TriCoef& k, R t, R* g)
 
 // Unscaled factors at node t = xi_k: g[6] = adj(K) and lam = 0.125 w_i w_j w_k / det(8J), so
 // that the geometric factors of Eq. (7) are lam * g (Eq. 12).
-template <typename R>
-__device__ __forceinline__ void tri_adj(const TriCoef& k, R t, R wk, R* g, R& lam)
+template <typename R, typename C>
+__device__ __forceinline__ void tri_adj(const TriCoefT<C>& k, R t, R wk, R* g, R& lam)
 {
     const R det = fma(fma(R(k.d2), t, R(k.d1)), t, R(k.d0));
     lam = R(k.cw) * wk * recip(det);

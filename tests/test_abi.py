@@ -187,3 +187,16 @@ def test_batched_noalloc_rejects_oversize_before_the_gpu(ax):
     assert L.ax_local_batched_noalloc(1, big, 1, ax.AX_FP64, ctypes.cast(x1, ctypes.c_void_p),
                                       ctypes.cast(y1, ctypes.c_void_p), None, None) == ax.AX_ERR_ARG
     assert b"bytes of work list" in L.ax_last_error()
+
+
+def test_probe_validation(ax):
+    L = ax.lib()
+    assert L.ax_probe_copy(None, ctypes.c_void_p(16), 64, None) == ax.AX_ERR_ARG
+    assert L.ax_probe_copy(ctypes.c_void_p(16), ctypes.c_void_p(16), 64, None) == ax.AX_ERR_ARG
+    assert L.ax_probe_copy(ctypes.c_void_p(16), ctypes.c_void_p(64), 40, None) == ax.AX_ERR_ARG
+    assert L.ax_probe_copy(ctypes.c_void_p(8), ctypes.c_void_p(64), 64, None) == ax.AX_ERR_ARG
+    assert L.ax_probe_copy(None, None, 0, None) == ax.AX_OK
+    fl = ctypes.c_double()
+    assert L.ax_probe_compute(0, 0, ctypes.c_void_p(16), ctypes.byref(fl), None) == ax.AX_ERR_ARG
+    assert L.ax_probe_compute(0, 10, None, ctypes.byref(fl), None) == ax.AX_ERR_ARG
+    assert L.ax_probe_compute(0, 10, ctypes.c_void_p(16), None, None) == ax.AX_ERR_ARG
