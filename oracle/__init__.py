@@ -48,6 +48,10 @@ def _load():
     lib.orc_cg.argtypes = [_i64, ctypes.c_int, _dp, _dp, _i64, _ip, _up, _dp, _dp,
                            ctypes.c_double, ctypes.c_int, _dp]
     lib.orc_cg.restype = ctypes.c_int
+    lib.orc_pcg.argtypes = [_i64, ctypes.c_int, _dp, _dp, _i64, _ip, _up, _dp, _dp, _dp,
+                            ctypes.c_double, ctypes.c_int, _dp]
+    lib.orc_pcg.restype = ctypes.c_int
+    lib.orc_ax_diag.argtypes = [_i64, ctypes.c_int, _dp, _dp, _dp]
     lib.orc_num_threads.restype = ctypes.c_int
     lib.orc_set_num_threads.argtypes = [ctypes.c_int]
     lib.orc_set_num_threads.restype = None
@@ -222,6 +226,38 @@ def cg(N, D, G, l2g, n_global, mask, b, x0=None, rtol=1e-10, max_it=10000):
     mp = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8).ctypes.data_as(_up)
     it = _load().orc_cg(G.shape[0], N, _d(_c64(D)), _d(_c64(G)), n_global, l2g.ctypes.data_as(_ip),
                         mp, _d(b), _d(x), float(rtol), int(max_it), ctypes.byref(rel))
+    return x, it, rel.value
+
+
+def ax_diag(D, G) -> np.ndarray:
+    """Diagonal of every element matrix D^T G_e D of Eq. (3) (Poisson), [E][N1^3]."""
+    D = _c64(D)
+    G = _c64(G)
+    N1 = D.shape[0]
+    out = np.zeros((G.shape[0], N1**3))
+    _load().orc_ax_diag(G.shape[0], N1 - 1, _d(D), _d(G), _d(out))
+    return out
+
+
+def jacobi_dinv(D, G, l2g, n_global, mask) -> np.ndarray:
+    """Inverse diagonal of the assembled operator (Q^T of the element diagonals, Eq. 1), zero on
+    the Dirichlet nodes (their rows of the assembled operator are zero)."""
+    dg = gs_qt(l2g, n_global, ax_diag(D, G).reshape(1, -1))[0]
+    m = np.zeros(n_global, dtype=bool) if mask is None else np.asarray(mask, dtype=bool)
+    out = np.zeros(n_global)
+    out[~m] = 1.0 / dg[~m]
+    return out
+
+
+def pcg(N, D, G, l2g, n_global, mask, b, dinv, x0=None, rtol=1e-10, max_it=10000):
+    """Jacobi-preconditioned CG (M^-1 = diag(dinv)).  Returns (x, iterations, true rel. residual)."""
+    l2g = np.ascontiguousarray(l2g, dtype=np.int32)
+    b = _c64(b)
+    x = np.zeros(n_global) if x0 is None else _c64(x0).copy()
+    rel = ctypes.c_double()
+    mp = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8).ctypes.data_as(_up)
+    it = _load().orc_pcg(G.shape[0], N, _d(_c64(D)), _d(_c64(G)), n_global, l2g.ctypes.data_as(_ip), mp,
+                         _d(b), _d(_c64(dinv)), _d(x), float(rtol), int(max_it), ctypes.byref(rel))
     return x, it, rel.value
 
 

@@ -333,6 +333,42 @@ void orc_ax_local(int64_t E, int N, const double* D, const double* G, int nrhs, 
     }
 }
 
+/* Diagonal of each element matrix A^(e) = D^T G D of Eq. (3) (Poisson), the Jacobi
+ * preconditioner's ingredient.  With D = [D_r; D_s; D_t] (Table 1), (D_r e_q)[p] = Dh[p_i][q_i]
+ * when p and q share j and k (zero otherwise), and likewise for D_s, D_t; so
+ *   e_q^T D_a^T G_aa D_a e_q = sum_n G_aa[node q with its a-index set to n] Dh[n][q_a]^2,
+ *   e_q^T D_a^T G_ab D_b e_q = G_ab[q] Dh[q_a][q_a] Dh[q_b][q_b]   (a != b: only p = q survives),
+ * and the diagonal is the sum over a, b.  G [E][6][N1^3], out [E][N1^3]. */
+void orc_ax_diag(int64_t E, int N, const double* D, const double* G, double* out)
+{
+    const int N1 = N + 1, Np = N1 * N1 * N1;
+    const int st[3] = {1, N1, N1 * N1};
+    const int gaa[3] = {0, 3, 5};                       /* G00, G11, G22 */
+    const int gab[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+#pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < E; ++e) {
+        const double* g = G + e * 6 * Np;
+        for (int k = 0; k < N1; ++k)
+            for (int j = 0; j < N1; ++j)
+                for (int i = 0; i < N1; ++i) {
+                    const int q[3] = {i, j, k};
+                    const int l = i + j * N1 + k * N1 * N1;
+                    double acc = 0.0;
+                    for (int a = 0; a < 3; ++a) {
+                        const int base = l - q[a] * st[a];
+                        for (int n = 0; n < N1; ++n) {
+                            const double d = D[n * N1 + q[a]];
+                            acc += g[gaa[a] * Np + base + n * st[a]] * d * d;
+                        }
+                        for (int b = 0; b < 3; ++b)
+                            if (b != a)
+                                acc += g[gab[a][b] * Np + l] * D[q[a] * N1 + q[a]] * D[q[b] * N1 + q[b]];
+                    }
+                    out[e * Np + l] = acc;
+                }
+    }
+}
+
 /* Q^T (Sec. 2.1, Eq. 1): out[g] = sum over local l with l2g[l] = g of in[l], summed in
  * ascending l.  Local [nrhs][n_local], global [nrhs][n_global]. */
 void orc_gs_qt(int64_t n_local, int64_t n_global, const int32_t* l2g, int nrhs, const double* in,
@@ -422,6 +458,57 @@ int orc_cg(int64_t E, int N, const double* D, const double* G, int64_t n_global,
     if (rel_res) *rel_res = sqrt(dot(n_global, r, r)) / bnorm;
     free(work);
     free(r);
+    free(p);
+    free(Ap);
+    return status ? -1 : it;
+}
+
+/* Preconditioned conjugate gradients with the diagonal preconditioner M^-1 = diag(dinv) (the
+ * textbook algorithm; the paper's Nekbone benchmark of Sec. 5.6 runs a Jacobi-preconditioned
+ * CG).  Same stopping rule, return values and residual report as orc_cg. */
+int orc_pcg(int64_t E, int N, const double* D, const double* G, int64_t n_global,
+            const int32_t* l2g, const uint8_t* mask, const double* b, const double* dinv, double* x,
+            double rtol, int max_it, double* rel_res)
+{
+    const int N1 = N + 1;
+    const int64_t n_local = E * N1 * N1 * N1;
+    double* work = (double*)malloc(sizeof(double) * 2 * n_local);
+    double* r = (double*)malloc(sizeof(double) * n_global);
+    double* z = (double*)malloc(sizeof(double) * n_global);
+    double* p = (double*)malloc(sizeof(double) * n_global);
+    double* Ap = (double*)malloc(sizeof(double) * n_global);
+    orc_apply_A(E, N, D, G, n_global, l2g, mask, x, Ap, work);
+    for (int64_t g = 0; g < n_global; ++g) {
+        r[g] = b[g] - Ap[g];
+        z[g] = dinv[g] * r[g];
+        p[g] = z[g];
+    }
+    const double bnorm = sqrt(dot(n_global, b, b));
+    double rr = dot(n_global, r, r), rz = dot(n_global, r, z);
+    int it = 0, status = isfinite(bnorm) ? 0 : -1;
+    while (status == 0 && it < max_it && !(sqrt(rr) <= rtol * bnorm)) {
+        orc_apply_A(E, N, D, G, n_global, l2g, mask, p, Ap, work);
+        const double pAp = dot(n_global, p, Ap);
+        if (!(pAp > 0.0) || !isfinite(pAp)) { status = -1; break; }
+        const double alpha = rz / pAp;
+        for (int64_t g = 0; g < n_global; ++g) {
+            x[g] += alpha * p[g];
+            r[g] -= alpha * Ap[g];
+            z[g] = dinv[g] * r[g];
+        }
+        const double rz_new = dot(n_global, r, z);
+        const double beta = rz_new / rz;
+        for (int64_t g = 0; g < n_global; ++g) p[g] = z[g] + beta * p[g];
+        rz = rz_new;
+        rr = dot(n_global, r, r);
+        ++it;
+    }
+    orc_apply_A(E, N, D, G, n_global, l2g, mask, x, Ap, work);
+    for (int64_t g = 0; g < n_global; ++g) r[g] = b[g] - Ap[g];
+    if (rel_res) *rel_res = sqrt(dot(n_global, r, r)) / bnorm;
+    free(work);
+    free(r);
+    free(z);
     free(p);
     free(Ap);
     return status ? -1 : it;

@@ -131,3 +131,66 @@ def test_cg_breakdown_on_nan():
     b[ng // 2] = np.nan
     _, it, _ = oracle.cg(N, D, G, l2g, ng, mask, b)
     assert it == -1
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4])
+def test_element_diagonal_vs_dense(N):
+    """The element diagonal is the diagonal of the brute-force Kronecker element matrix."""
+    m = meshgen.jittered_hex(2, 1, 2, alpha=0.2, seed=30 + N)
+    xi, w, D = oracle.gll(N)
+    G, _, _ = oracle.geom_factors(m.verts, N, xi, w)
+    dg = oracle.ax_diag(D, G)
+    for e in range(m.E):
+        ref = np.diag(dense.element_matrix(D, G[e]))
+        assert np.abs(dg[e] - ref).max() <= 1e-13 * np.abs(ref).max()
+        assert (dg[e] > 0).all()
+
+
+@pytest.mark.parametrize("N", [2, 3])
+def test_jacobi_inverse_vs_dense_assembly(N):
+    """Q^T of the element diagonals is the diagonal of the assembled operator (Eq. 1) on the free
+    nodes; the inverse is zero on the Dirichlet nodes."""
+    m = meshgen.jittered_hex(2, 2, 2, alpha=0.15, seed=40 + N)
+    xi, w, D = oracle.gll(N)
+    G, _, _ = oracle.geom_factors(m.verts, N, xi, w)
+    l2g, ng, mask = meshgen.global_numbering(2, 2, 2, N)
+    dinv = oracle.jacobi_dinv(D, G, l2g, ng, mask)
+    A = dense.assembled_matrix(D, G, l2g, ng, mask)
+    free = mask == 0
+    assert np.abs(dinv[free] * np.diag(A)[free] - 1.0).max() <= 1e-13
+    assert (dinv[~free] == 0).all()
+
+
+def test_pcg_matches_direct_solve_in_fewer_iterations():
+    N = 3
+    m = meshgen.jittered_hex(3, 3, 3, alpha=0.1, seed=4)
+    xi, w, D = oracle.gll(N)
+    G, _, _ = oracle.geom_factors(m.verts, N, xi, w)
+    l2g, ng, mask = meshgen.global_numbering(3, 3, 3, N)
+    b, _ = oracle.poisson_rhs(N, m.verts, xi, w, l2g, ng, mask)
+    dinv = oracle.jacobi_dinv(D, G, l2g, ng, mask)
+    x, it, rel = oracle.pcg(N, D, G, l2g, ng, mask, b, dinv, rtol=1e-12)
+    assert it > 0 and rel <= 1e-11
+    A = dense.assembled_matrix(D, G, l2g, ng, mask)
+    free = mask == 0
+    xd = np.zeros(ng)
+    xd[free] = np.linalg.solve(A[np.ix_(free, free)], b[free])
+    assert np.abs(x - xd).max() <= 1e-9 * np.abs(xd).max()
+    _, it_cg, _ = oracle.cg(N, D, G, l2g, ng, mask, b, rtol=1e-12)
+    assert it < it_cg
+
+
+def test_pcg_with_identity_is_cg():
+    """With M = I on the free nodes the preconditioned recurrence is plain CG's: same iteration
+    count and the same iterate up to rounding."""
+    N = 2
+    m = meshgen.jittered_hex(2, 2, 3, alpha=0.1, seed=8)
+    xi, w, D = oracle.gll(N)
+    G, _, _ = oracle.geom_factors(m.verts, N, xi, w)
+    l2g, ng, mask = meshgen.global_numbering(2, 2, 3, N)
+    b, _ = oracle.poisson_rhs(N, m.verts, xi, w, l2g, ng, mask)
+    one = np.where(mask == 1, 0.0, 1.0)
+    x1, it1, _ = oracle.pcg(N, D, G, l2g, ng, mask, b, one, rtol=1e-10)
+    x0, it0, _ = oracle.cg(N, D, G, l2g, ng, mask, b, rtol=1e-10)
+    assert it1 == it0
+    assert np.abs(x1 - x0).max() <= 1e-12 * np.abs(x0).max()
