@@ -175,7 +175,8 @@ def cg_solves(ax, meshgen, dev, N=7, grid=(32, 32, 32), rtol=1e-10, check_with_o
     """-Lap u = f on the unit cube (homogeneous Dirichlet), N = 7, 32^3 trilinear hexes with
     +-10 % jitter (seed 4), f from u = sin(pi x) sin(pi y) sin(pi z).  Time to a true relative
     residual of 1e-10: plain FP64 CG against mixed precision with an FP32 inner AxLocal (reliable
-    updates, and restarted refinement) and an FP16 (matrix-core) inner AxLocal (restarted)."""
+    updates, and restarted refinement) and an FP16 (matrix-core) inner AxLocal (restarted); and
+    the Jacobi-preconditioned solves (FP64, FP32 reliable updates)."""
     import torch
     m = meshgen.jittered_hex(*grid, alpha=0.10, seed=4)
     l2g, ng, mask = meshgen.global_numbering(*grid, N)
@@ -194,7 +195,11 @@ def cg_solves(ax, meshgen, dev, N=7, grid=(32, 32, 32), rtol=1e-10, check_with_o
     runs = [("fp64", dict(inner_prec=ax.AX_FP64)),
             ("mixed_fp32_reliable", dict(inner_prec=ax.AX_FP32, inner_rtol=0.1, refine=ax.AX_REFINE_RELIABLE)),
             ("mixed_fp32_restart", dict(inner_prec=ax.AX_FP32, inner_rtol=1e-5)),
-            ("mixed_fp16_restart", dict(inner_prec=ax.AX_FP16_ACC32, inner_rtol=1e-2))]
+            ("mixed_fp16_restart", dict(inner_prec=ax.AX_FP16_ACC32, inner_rtol=1e-2)),
+            # Jacobi-preconditioned CG (Nekbone's solver, Sec. 5.6), FP64 and mixed
+            ("jacobi_fp64", dict(inner_prec=ax.AX_FP64, precond=ax.AX_PRECOND_JACOBI)),
+            ("jacobi_mixed_fp32_reliable", dict(inner_prec=ax.AX_FP32, inner_rtol=0.1, refine=ax.AX_REFINE_RELIABLE,
+                                                precond=ax.AX_PRECOND_JACOBI))]
     # per-launch AxLocal time on this mesh in each precision (for the AxLocal share of a solve)
     t_ax = {}
     xl = meshgen.random_nodal_device(m.E, N, 1, seed=9, device=dev)
@@ -226,6 +231,10 @@ def cg_solves(ax, meshgen, dev, N=7, grid=(32, 32, 32), rtol=1e-10, check_with_o
     t64 = res["fp64"]["seconds"]
     for name, _ in runs[1:]:
         res[name]["speedup_vs_fp64"] = round(t64 / res[name]["seconds"], 3) if res[name]["seconds"] > 0 else None
+    tj = res["jacobi_fp64"]["seconds"]
+    res["jacobi_mixed_fp32_reliable"]["speedup_vs_jacobi_fp64"] = (
+        round(tj / res["jacobi_mixed_fp32_reliable"]["seconds"], 3) if res["jacobi_mixed_fp32_reliable"]["seconds"] > 0
+        else None)
     ug = torch.zeros(ng, dtype=torch.float64, device=dev)
     u = torch.sin(np.pi * XYZ[:, 0]) * torch.sin(np.pi * XYZ[:, 1]) * torch.sin(np.pi * XYZ[:, 2])
     ug[gs.l2g.long()] = u.reshape(-1)

@@ -154,6 +154,17 @@ int ax_geom_lambda(int64_t E, int N, const double* verts, const double* xi, cons
                    void* lam, void* stream);
 
 /*
+ * ax_local_diag - the diagonal of every element matrix D^T G_e D of Eq. (3) (Poisson), with the
+ * factors recomputed as in ax_local (trilinear: from the vertices, Eq. 12; parallelepiped: w h).
+ * Only the GLL line through a node in each direction contributes to its diagonal (the gradient
+ * blocks of Table 1 act on one index each), plus the off-diagonal factors at the node itself.
+ * out [dev] double [E][N1^3]; D [host] N1*N1, xi, w [host] N1 (xi may be NULL for
+ * AX_PARALLELEPIPED); geo as ax_local.  Errors as ax_local.  Asynchronous on `stream`.
+ */
+int ax_local_diag(int64_t E, int N, int geom, const double* geo, const double* D, const double* xi,
+                  const double* w, double* out, void* stream);
+
+/*
  * ax_geom_factors - set-up: write the stored factors of Eq. (7) for trilinear elements,
  * G [dev] [E][6][N1^3] (double if prec == AX_FP64, float if AX_FP32) and, if gwj is not NULL,
  * gwj [dev] double [E][N1^3] = w_i w_j w_k det J (the lumped mass, second factor of Eq. 7).
@@ -234,7 +245,17 @@ typedef struct {
     size_t workspace_bytes;
     int use_graph;         /* 1: capture the CG iteration block in a HIP graph and replay it */
     int refine;            /* AX_REFINE_RESTART or AX_REFINE_RELIABLE (refinement only)    */
+    int precond;           /* AX_PRECOND_NONE or AX_PRECOND_JACOBI                         */
 } ax_cg_opts;
+
+/* Preconditioners of the CG iterations (ax_cg_opts.precond):
+ * AX_PRECOND_NONE   - plain CG;
+ * AX_PRECOND_JACOBI - z = diag(A)^-1 r with the diagonal of the assembled operator (the element
+ *                     diagonals of ax_local_diag, factors recomputed, assembled by Q^T; zero on
+ *                     the Dirichlet nodes), the preconditioner of the Nekbone CG of Sec. 5.6.
+ *                     The same diagonal (in float) serves the reduced-precision iterations of
+ *                     the mixed-precision solves.  The convergence test stays on ||r||_2. */
+enum { AX_PRECOND_NONE = 0, AX_PRECOND_JACOBI = 1 };
 
 /* Refinement schemes of the mixed-precision solves (ax_cg_opts.refine):
  * AX_REFINE_RESTART  - each correction A d = r / ||r|| is an inner CG started from scratch and

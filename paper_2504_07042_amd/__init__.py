@@ -22,6 +22,7 @@ AX_OK, AX_ERR_ARG, AX_ERR_UNSUPPORTED, AX_ERR_HIP, AX_ERR_NOMEM, AX_ERR_NOT_CONV
 AX_TRILINEAR, AX_PARALLELEPIPED, AX_STORED_G = 0, 1, 2
 AX_FP64, AX_FP32, AX_FP16_ACC32 = 0, 1, 2
 AX_REFINE_RESTART, AX_REFINE_RELIABLE = 0, 1
+AX_PRECOND_NONE, AX_PRECOND_JACOBI = 0, 1
 AX_PROBE_FMA_F64, AX_PROBE_FMA_F32, AX_PROBE_MFMA_F64, AX_PROBE_MFMA_F32, AX_PROBE_MIX_F64 = 0, 1, 2, 3, 4
 GS_QT, GS_Q, GS_QQT = 0, 1, 2
 
@@ -50,7 +51,7 @@ class AxProblem(ctypes.Structure):
 class AxCgOpts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("max_it", _int), ("inner_prec", _int),
                 ("inner_rtol", ctypes.c_double), ("max_outer", _int), ("workspace", _vp),
-                ("workspace_bytes", ctypes.c_size_t), ("use_graph", _int), ("refine", _int)]
+                ("workspace_bytes", ctypes.c_size_t), ("use_graph", _int), ("refine", _int), ("precond", _int)]
 
 
 class AxBatchPlan(ctypes.Structure):
@@ -80,6 +81,7 @@ _SIGS = {
     "ax_local_helmholtz": (_int, [_i64, _int, _vp, _vp, _vp, _vp, _vp, _int, _int, _vp, _vp, _vp]),
     "ax_helmholtz_factors": (_int, [_i64, _int, _vp, _vp, _vp, _vp, _vp, _int, _vp, _vp]),
     "ax_parallelepiped_factors": (_int, [_i64, _vp, _vp, _vp]),
+    "ax_local_diag": (_int, [_i64, _int, _int, _vp, _vp, _vp, _vp, _vp, _vp]),
     "ax_node_coords": (_int, [_i64, _int, _vp, _vp, _vp, _vp]),
     "gs_build_csr": (_int, [_i64, _i64, _vp, _vp, _vp]),
     "gs_assemble": (_int, [_i64, _i64, _vp, _vp, _vp, _vp, _int, _int, _int, _vp, _vp, _vp]),
@@ -265,6 +267,16 @@ def geom_factors(verts, basis: Basis, prec=AX_FP64, want_G=True, want_gwj=False,
     return G, gwj
 
 
+def local_diag(geo, basis: Basis, geom=AX_TRILINEAR, stream=None):
+    """Diagonal of every element matrix D^T G_e D (Eq. 3), factors recomputed: [E][N1^3] FP64."""
+    import torch
+    E = geo.shape[0]
+    out = torch.empty((E, (basis.N + 1) ** 3), dtype=torch.float64, device=geo.device)
+    _check(lib().ax_local_diag(E, basis.N, geom, _dptr(geo), _np_ptr(basis.D), _np_ptr(basis.xi),
+                               _np_ptr(basis.w), _dptr(out), _stream(stream)))
+    return out
+
+
 def parallelepiped_factors(verts, stream=None):
     import torch
     h = torch.empty((verts.shape[0], 6), dtype=torch.float64, device=verts.device)
@@ -348,7 +360,7 @@ class Problem:
 
 
 def cg_solve(prob: Problem, b, x=None, rtol=1e-10, max_it=20000, inner_prec=AX_FP64, inner_rtol=1e-6,
-             max_outer=50, use_graph=True, refine=None, stream=None):
+             max_outer=50, use_graph=True, refine=None, precond=AX_PRECOND_NONE, stream=None):
     """Solve A x = b by CG (inner_prec = AX_FP64) or mixed-precision iterative refinement
     (refine = AX_REFINE_RESTART, the default, or AX_REFINE_RELIABLE).  b [nrhs][n_global]
     float64 device.  Returns (x, report dict); raises AxError only on argument or launch errors
@@ -359,7 +371,7 @@ def cg_solve(prob: Problem, b, x=None, rtol=1e-10, max_it=20000, inner_prec=AX_F
         x = torch.zeros_like(b)
     p = prob.c_struct()
     opts = AxCgOpts(rtol, max_it, inner_prec, inner_rtol, max_outer, None, 0, 1 if use_graph else 0,
-                    AX_REFINE_RESTART if refine is None else refine)
+                    AX_REFINE_RESTART if refine is None else refine, precond)
     nbytes = ctypes.c_size_t()
     _check(lib().cg_workspace_bytes(ctypes.byref(p), nrhs, ctypes.byref(opts), ctypes.byref(nbytes)))
     ws = torch.empty(nbytes.value, dtype=torch.uint8, device=b.device)
@@ -441,7 +453,8 @@ def batched_noalloc(meshes, X, Y, prec=AX_FP64, stream=None):
 
 
 def cg_solve_batched(meshes, gs: GatherScatter, b, x=None, rtol=1e-10, max_it=20000, inner_prec=AX_FP64,
-                     inner_rtol=1e-6, max_outer=50, use_graph=True, refine=None, stream=None):
+                     inner_rtol=1e-6, max_outer=50, use_graph=True, refine=None, precond=AX_PRECOND_NONE,
+                     stream=None):
     """CG / mixed refinement over the union of many trilinear meshes (block-diagonal system).
     meshes: list of (verts device tensor, Basis) in the order of the concatenated local vectors;
     gs: gather-scatter of the concatenated numbering; b [nrhs][n_global] float64 device."""
@@ -455,7 +468,7 @@ def cg_solve_batched(meshes, gs: GatherScatter, b, x=None, rtol=1e-10, max_it=20
     if x is None:
         x = torch.zeros_like(b)
     opts = AxCgOpts(rtol, max_it, inner_prec, inner_rtol, max_outer, None, 0, 1 if use_graph else 0,
-                    AX_REFINE_RESTART if refine is None else refine)
+                    AX_REFINE_RESTART if refine is None else refine, precond)
     nbytes = ctypes.c_size_t()
     _check(lib().cg_batched_workspace_bytes(n, probs, gs.n_global, nrhs, ctypes.byref(opts), ctypes.byref(nbytes)))
     ws = torch.empty(nbytes.value, dtype=torch.uint8, device=b.device)

@@ -127,6 +127,60 @@ node_coords_kernel(int64_t E, int N1, const double* __restrict__ verts, double* 
     }
 }
 
+// Tables of the diagonal kernel: the differentiation matrix and the nodes.
+struct DiagTables {
+    double D[kMaxN1 * kMaxN1];
+    Nodes nd;
+};
+
+// Diagonal of the element matrix D^T G D of Eq. (3) at node q = (i, j, k), one thread per node.
+// With the gradient blocks of Table 1, (D_a e_q) is nonzero only on the GLL line through q in
+// direction a, so the diagonal is
+//   sum_a sum_n G_aa(q with index a set to n) D[n][q_a]^2 + sum_{a != b} G_ab(q) D[q_a][q_a] D[q_b][q_b].
+// Trilinear: the factors at the 3 N1 line nodes are recomputed from the vertices (Eq. 12 via the
+// per-column polynomials); parallelepiped: G = w_i w_j w_k h.
+template <bool TRI>
+__global__ void __launch_bounds__(256)
+local_diag_kernel(int64_t E, int N1, const double* __restrict__ geo, double* __restrict__ out, const DiagTables tb)
+{
+    const int NP = N1 * N1 * N1;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= E * NP) return;
+    const int64_t e = idx / NP;
+    const int l = (int)(idx - e * NP);
+    const int i = l % N1, j = (l / N1) % N1, k = l / (N1 * N1);
+    const int q[3] = {i, j, k};
+    const Nodes& nd = tb.nd;
+    auto Dm = [&](int a, int b) { return tb.D[a * N1 + b]; };
+    // factors at node (a, b, c): g[6] in order 00, 01, 02, 11, 12, 22
+    auto factors = [&](int a, int b, int c, double* g) {
+        if constexpr (TRI) {
+            const double* Ve = geo + e * 24;
+            TriCoef tc;
+            tri_prelude([&](int v, int qq) { return Ve[v * 3 + qq]; }, nd.xi[a], nd.xi[b], nd.w[a], nd.w[b], tc);
+            double lam;
+            tri_adj<double>(tc, nd.xi[c], nd.w[c], g, lam);
+            for (int m = 0; m < 6; ++m) g[m] *= lam;
+        } else {
+            const double W = nd.w[a] * nd.w[b] * nd.w[c];
+            for (int m = 0; m < 6; ++m) g[m] = W * geo[e * 6 + m];
+        }
+    };
+    double acc = 0.0, g[6];
+    for (int n = 0; n < N1; ++n) {
+        factors(n, j, k, g);
+        acc += g[0] * Dm(n, i) * Dm(n, i);
+        factors(i, n, k, g);
+        acc += g[3] * Dm(n, j) * Dm(n, j);
+        factors(i, j, n, g);
+        acc += g[5] * Dm(n, k) * Dm(n, k);
+    }
+    factors(i, j, k, g);
+    const double di = Dm(q[0], q[0]), dj = Dm(q[1], q[1]), dk = Dm(q[2], q[2]);
+    acc += 2.0 * (g[1] * di * dj + g[2] * di * dk + g[4] * dj * dk);
+    out[idx] = acc;
+}
+
 static void fill_nodes(Nodes& nd, int N1, const double* xi, const double* w)
 {
     for (int q = 0; q < kMaxN1; ++q) {
@@ -244,4 +298,28 @@ extern "C" int ax_node_coords(int64_t E, int N, const double* verts, const doubl
     hipLaunchKernelGGL(node_coords_kernel, dim3(grid_for(n, 256)), dim3(256), 0, as_stream(stream), E,
                        N1, verts, XYZ, nd);
     return hip_check(hipGetLastError(), "ax_node_coords launch");
+}
+
+extern "C" int ax_local_diag(int64_t E, int N, int geom, const double* geo, const double* D, const double* xi,
+                             const double* w, double* out, void* stream)
+{
+    clear_error();
+    if (E < 0) return fail(AX_ERR_ARG, "E < 0");
+    if (N < 1 || N > 15) return fail(AX_ERR_UNSUPPORTED, "order N=%d outside [1,15]", N);
+    if (geom != AX_TRILINEAR && geom != AX_PARALLELEPIPED) return fail(AX_ERR_UNSUPPORTED, "unknown geometry %d", geom);
+    if (!D || !w || (geom == AX_TRILINEAR && !xi)) return fail(AX_ERR_ARG, "D, xi or w is NULL");
+    if (E == 0) return AX_OK;
+    if (!geo || !out) return fail(AX_ERR_ARG, "geo or out is NULL");
+    const int N1 = N + 1;
+    const int64_t n = E * N1 * N1 * N1;
+    if (n / 256 > 0x7fffffff) return fail(AX_ERR_UNSUPPORTED, "too many nodes");
+    DiagTables tb;
+    for (int q = 0; q < kMaxN1 * kMaxN1; ++q) tb.D[q] = q < N1 * N1 ? D[q] : 0.0;
+    fill_nodes(tb.nd, N1, xi, w);
+    hipStream_t st = as_stream(stream);
+    if (geom == AX_TRILINEAR)
+        hipLaunchKernelGGL(local_diag_kernel<true>, dim3(grid_for(n, 256)), dim3(256), 0, st, E, N1, geo, out, tb);
+    else
+        hipLaunchKernelGGL(local_diag_kernel<false>, dim3(grid_for(n, 256)), dim3(256), 0, st, E, N1, geo, out, tb);
+    return hip_check(hipGetLastError(), "ax_local_diag launch");
 }

@@ -29,7 +29,8 @@ constexpr int kReliableCheck = 256;  // longest run of reduced-precision iterati
 
 // Per-column scalar state of one CG (device).
 struct CgScal {
-    double rr;      // r . r
+    double rr;      // r . r (convergence test on the residual norm)
+    double rz;      // r . z, z = M^-1 r (= r . r without a preconditioner)
     double alpha;
     double beta;
     double tol2;    // (rtol * |b|)^2 target on r . r
@@ -38,6 +39,9 @@ struct CgScal {
     int iters;
     int pad;
 };
+
+// Partial sums of the fixed-grid reductions: [2][nrhs][kRedBlocks], the second half for r . z.
+__device__ __forceinline__ double* rz_partials(double* partials, int nrhs) { return partials + (size_t)nrhs * kRedBlocks; }
 
 template <typename TA, typename TB>
 __global__ void __launch_bounds__(kRedThreads)
@@ -79,17 +83,24 @@ __device__ double block_sum_partials(const double* partials)
 // mode 2: rr_new = sum; beta = rr_new / rr; rr = rr_new; converged test.
 // mode 3: rr = sum after a reliable update (alpha, beta and the iteration count are kept).
 // mode 4: sum = d . d of the iterate about to be folded; flags a non-finite one (breakdown 2).
+// With `pre` the partials hold r . r in the first and r . z in the second half (modes 0, 2, 3);
+// without, r . z = r . r.
 __global__ void __launch_bounds__(kRedThreads)
-cg_scalar_kernel(const double* __restrict__ partials, CgScal* __restrict__ sc, int mode)
+cg_scalar_kernel(const double* __restrict__ partials, CgScal* __restrict__ sc, int mode, int pre)
 {
-    const int c = blockIdx.x;
+    const int c = blockIdx.x, nrhs = gridDim.x;
     const double s = block_sum_partials(partials + c * kRedBlocks);
+    __syncthreads();
+    const double s2 = (pre && mode != 1 && mode != 4)
+                          ? block_sum_partials(partials + (size_t)nrhs * kRedBlocks + c * kRedBlocks)
+                          : s;
     if (threadIdx.x != 0) return;
     CgScal& q = sc[c];
     if (mode == 0) {
         q.rr = s;
+        q.rz = s2;
         q.converged = (s <= q.tol2) ? 1 : 0;
-        q.breakdown = isfinite(s) ? 0 : 1;
+        q.breakdown = isfinite(s) && isfinite(s2) ? 0 : 1;
         q.iters = 0;
         q.alpha = q.beta = 0.0;
     } else if (mode == 1) {
@@ -99,7 +110,7 @@ cg_scalar_kernel(const double* __restrict__ partials, CgScal* __restrict__ sc, i
             q.breakdown = 1;
             q.alpha = 0.0;
         } else {
-            q.alpha = q.rr / s;
+            q.alpha = q.rz / s;
         }
     } else if (mode == 4) {
         // s = d . d of the reduced-precision iterate: a non-finite one must not reach x
@@ -107,16 +118,18 @@ cg_scalar_kernel(const double* __restrict__ partials, CgScal* __restrict__ sc, i
     } else if (mode == 3) {
         // the iterated residual was replaced by the true one: new r . r, keep the iteration count
         q.rr = s;
+        q.rz = s2;
         q.converged = (s <= q.tol2) ? 1 : 0;
-        q.breakdown = isfinite(s) ? 0 : 1;
+        q.breakdown = isfinite(s) && isfinite(s2) ? 0 : 1;
     } else {
         if (q.converged || q.breakdown) {
             q.beta = 0.0;
         } else {
-            q.beta = s / q.rr;
+            q.beta = s2 / q.rz;
+            q.rz = s2;
             q.rr = s;
             q.iters += 1;
-            if (!isfinite(s)) q.breakdown = 1;
+            if (!isfinite(s) || !isfinite(s2)) q.breakdown = 1;
             else if (s <= q.tol2) q.converged = 1;
         }
     }
@@ -201,16 +214,31 @@ qt_dot_kernel(int64_t n_global, const CopyPair* __restrict__ cp, const int64_t* 
     if (threadIdx.x == 0) partials[c * kRedBlocks + blockIdx.x] = red[0];
 }
 
-// x += alpha p; r -= alpha Ap; partial sums of r . r (fixed grid)
+// Block sum of `acc` into partials[slot] (fixed combination order).
+__device__ __forceinline__ void block_partial(double acc, double* __restrict__ dst)
+{
+    __shared__ double red[kRedThreads];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = kRedThreads / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *dst = red[0];
+    __syncthreads();
+}
+
+// x += alpha p; r -= alpha Ap; partial sums of r . r and, with the Jacobi preconditioner
+// (dinv != NULL), of r . z with z = dinv o r (fixed grid)
 template <typename TX, typename T>
 __global__ void __launch_bounds__(kRedThreads)
 update_dot_kernel(TX* __restrict__ x, T* __restrict__ r, const T* __restrict__ p, const T* __restrict__ Ap,
-                  const CgScal* __restrict__ sc, int64_t n, double* __restrict__ partials)
+                  const CgScal* __restrict__ sc, int64_t n, const T* __restrict__ dinv, double* __restrict__ partials)
 {
     const int c = blockIdx.y;
     const double al = sc[c].alpha;
     const int64_t o = (int64_t)c * n;
-    double acc = 0.0;
+    double acc = 0.0, acz = 0.0;
     for (int64_t q = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; q < n;
          q += (int64_t)gridDim.x * kRedThreads) {
         T rv = r[o + q];
@@ -220,28 +248,65 @@ update_dot_kernel(TX* __restrict__ x, T* __restrict__ r, const T* __restrict__ p
             r[o + q] = rv;
         }
         acc = fma((double)rv, (double)rv, acc);
+        if (dinv) acz = fma((double)rv * (double)dinv[q], (double)rv, acz);
     }
-    __shared__ double red[kRedThreads];
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int h = kRedThreads / 2; h > 0; h >>= 1) {
-        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) partials[c * kRedBlocks + blockIdx.x] = red[0];
+    block_partial(acc, partials + c * kRedBlocks + blockIdx.x);
+    if (dinv) block_partial(acz, partials + ((size_t)gridDim.y + c) * kRedBlocks + blockIdx.x);
 }
 
-// p = r + beta p
+// Partial sums of r . r and (dinv != NULL) r . (dinv o r), for modes 0 and 3 of the scalar kernel.
+template <typename T>
+__global__ void __launch_bounds__(kRedThreads)
+rr_rz_kernel(const T* __restrict__ r, const T* __restrict__ dinv, int64_t n, double* __restrict__ partials)
+{
+    const int c = blockIdx.y;
+    const T* rc = r + (int64_t)c * n;
+    double acc = 0.0, acz = 0.0;
+    for (int64_t q = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; q < n; q += (int64_t)gridDim.x * kRedThreads) {
+        const double v = (double)rc[q];
+        acc = fma(v, v, acc);
+        if (dinv) acz = fma(v * (double)dinv[q], v, acz);
+    }
+    block_partial(acc, partials + c * kRedBlocks + blockIdx.x);
+    if (dinv) block_partial(acz, partials + ((size_t)gridDim.y + c) * kRedBlocks + blockIdx.x);
+}
+
+// dst = dinv o src (dinv != NULL) or dst = src: the preconditioned residual z
 template <typename T>
 __global__ void __launch_bounds__(256)
-cg_dir_kernel(T* __restrict__ p, const T* __restrict__ r, const CgScal* __restrict__ sc, int64_t n)
+precond_kernel(T* __restrict__ dst, const T* __restrict__ src, const T* __restrict__ dinv, int64_t n)
+{
+    const int64_t o = (int64_t)blockIdx.y * n;
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (int64_t)gridDim.x * 256)
+        dst[o + q] = dinv ? T((double)dinv[q] * (double)src[o + q]) : src[o + q];
+}
+
+// dinv = 1 / diag on the free nodes, 0 on the masked (Dirichlet) ones; also the float copy
+__global__ void __launch_bounds__(256)
+invert_diag_kernel(double* __restrict__ dinv, float* __restrict__ dinv32, const double* __restrict__ diag,
+                   const uint8_t* __restrict__ mask, int64_t n)
+{
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (int64_t)gridDim.x * 256) {
+        const double v = (mask && mask[q]) ? 0.0 : 1.0 / diag[q];
+        dinv[q] = v;
+        if (dinv32) dinv32[q] = (float)v;
+    }
+}
+
+// p = z + beta p, z = dinv o r (dinv != NULL) or r
+template <typename T>
+__global__ void __launch_bounds__(256)
+cg_dir_kernel(T* __restrict__ p, const T* __restrict__ r, const CgScal* __restrict__ sc, int64_t n,
+              const T* __restrict__ dinv)
 {
     const int c = blockIdx.y;
     if (sc[c].converged || sc[c].breakdown) return;
     const double be = sc[c].beta;
     const int64_t o = (int64_t)c * n;
-    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (int64_t)gridDim.x * 256)
-        p[o + q] = (T)((double)r[o + q] + be * (double)p[o + q]);
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (int64_t)gridDim.x * 256) {
+        const double z = dinv ? (double)dinv[q] * (double)r[o + q] : (double)r[o + q];
+        p[o + q] = (T)(z + be * (double)p[o + q]);
+    }
 }
 
 // r = b - Ax (FP64).  Entries under the Dirichlet mask come out 0 because Ax is 0 there and the
@@ -362,13 +427,15 @@ struct CgWork {
     double *pl, *wl;               // FP64 local vectors [nrhs][nl]
     float *b32, *r32, *p32, *Ap32, *d32; // inner global vectors
     float *pl32, *wl32;            // inner local vectors
-    double* partials;              // [nrhs][kRedBlocks]
+    double* partials;              // [2][nrhs][kRedBlocks]
+    double* dinv;                  // Jacobi preconditioner [n_global] (or NULL)
+    float* dinv32;                 // its float copy for the reduced-precision recurrences
     CopyPair* pairs;               // [n_global]
     CgScal *sc, *sc_in;            // outer / inner scalar state [nrhs]
     int* flag;                     // masked right-hand-side check
 };
 
-static void carve(Carver& cv, int64_t nl, int64_t ng, int nrhs, bool mixed, CgWork& w)
+static void carve(Carver& cv, int64_t nl, int64_t ng, int nrhs, bool mixed, bool pre, CgWork& w)
 {
     w.r = cv.take<double>(ng * nrhs);
     w.p = cv.take<double>(ng * nrhs);
@@ -386,7 +453,9 @@ static void carve(Carver& cv, int64_t nl, int64_t ng, int nrhs, bool mixed, CgWo
     } else {
         w.b32 = w.r32 = w.p32 = w.Ap32 = w.d32 = w.pl32 = w.wl32 = nullptr;
     }
-    w.partials = cv.take<double>((size_t)kRedBlocks * nrhs);
+    w.partials = cv.take<double>((size_t)2 * kRedBlocks * nrhs);
+    w.dinv = pre ? cv.take<double>(ng) : nullptr;
+    w.dinv32 = (pre && mixed) ? cv.take<float>(ng) : nullptr;
     w.pairs = cv.take<CopyPair>(ng);
     w.sc = cv.take<CgScal>(nrhs);
     w.sc_in = cv.take<CgScal>(nrhs);
@@ -408,7 +477,16 @@ struct Operator {
     const void* ws64 = nullptr;
     const ax_batch_plan* plan32 = nullptr;
     const void* ws32 = nullptr;
+    const double* dinv64 = nullptr;  // Jacobi preconditioner (NULL: none)
+    const float* dinv32 = nullptr;
 };
+
+template <typename T>
+static const T* op_dinv(const Operator& op)
+{
+    if constexpr (sizeof(T) == 8) return op.dinv64;
+    else return op.dinv32;
+}
 
 // Local result yl = AxLocal(Q x).  With AX_CG_GATHER the gather Q x of one mesh is fused into
 // the AxLocal load (FP64/FP32, GLL D); measured on MI355X the separate, fully occupied gather
@@ -448,10 +526,19 @@ static int dot(const TA* a, const TB* b, int64_t n, int nrhs, double* partials, 
     return hip_check(hipGetLastError(), "dot");
 }
 
-static int scal(const double* partials, CgScal* sc, int mode, int nrhs, hipStream_t st)
+static int scal(const double* partials, CgScal* sc, int mode, int nrhs, hipStream_t st, bool pre = false)
 {
-    hipLaunchKernelGGL(cg_scalar_kernel, dim3(nrhs), dim3(kRedThreads), 0, st, partials, sc, mode);
+    hipLaunchKernelGGL(cg_scalar_kernel, dim3(nrhs), dim3(kRedThreads), 0, st, partials, sc, mode, pre ? 1 : 0);
     return hip_check(hipGetLastError(), "cg scalar");
+}
+
+// r . r and r . z partials (z = dinv o r), then scalar mode 0 or 3
+template <typename T>
+static int rr_rz(const T* r, const T* dinv, int64_t n, int nrhs, double* partials, CgScal* sc, int mode, hipStream_t st)
+{
+    hipLaunchKernelGGL(rr_rz_kernel<T>, dim3(kRedBlocks, nrhs), dim3(kRedThreads), 0, st, r, dinv, n, partials);
+    AX_TRY(hip_check(hipGetLastError(), "r.r / r.z"));
+    return scal(partials, sc, mode, nrhs, st, dinv != nullptr);
 }
 
 // Host view of the scalar state (synchronises the stream).
@@ -470,15 +557,16 @@ static int cg_block(const Operator& op, int nrhs, int prec, TX* x, T* r, T* p, T
 {
     const int64_t ng = op.n_global;
     const dim3 g(vgrid(ng), nrhs);
+    const T* dinv = op_dinv<T>(op);
     for (int q = 0; q < count; ++q) {
         AX_TRY(apply_local<T>(op, nrhs, prec, p, pl, wl, st));
         hipLaunchKernelGGL(qt_dot_kernel<T>, dim3(kRedBlocks, nrhs), dim3(kRedThreads), 0, st, ng, op.pairs,
                            op.gptr, op.gidx, op.n_local, wl, p, Ap, partials);
         AX_TRY(scal(partials, sc, 1, nrhs, st));
         hipLaunchKernelGGL((update_dot_kernel<TX, T>), dim3(kRedBlocks, nrhs), dim3(kRedThreads), 0, st, x, r, p,
-                           Ap, sc, ng, partials);
-        AX_TRY(scal(partials, sc, 2, nrhs, st));
-        hipLaunchKernelGGL(cg_dir_kernel<T>, g, dim3(256), 0, st, p, r, sc, ng);
+                           Ap, sc, ng, dinv, partials);
+        AX_TRY(scal(partials, sc, 2, nrhs, st, dinv != nullptr));
+        hipLaunchKernelGGL(cg_dir_kernel<T>, g, dim3(256), 0, st, p, r, sc, ng, dinv);
     }
     return hip_check(hipGetLastError(), "cg iteration");
 }
@@ -542,9 +630,8 @@ static int cg_core(const Operator& op, int nrhs, int prec, const T* b, TX* x, T*
             return fail(AX_ERR_ARG, "internal: warm start needs FP64 vectors");
         }
     }
-    hipLaunchKernelGGL(copy_kernel<T>, dim3(vgrid(ng * nrhs)), dim3(256), 0, st, p, r, ng * nrhs);
-    AX_TRY(dot(r, r, ng, nrhs, partials, st));
-    AX_TRY(scal(partials, sc, 0, nrhs, st));
+    hipLaunchKernelGGL(precond_kernel<T>, g, dim3(256), 0, st, p, r, op_dinv<T>(op), ng);
+    AX_TRY(rr_rz<T>(r, op_dinv<T>(op), ng, nrhs, partials, sc, 0, st));
     std::vector<CgScal> h;
     int it = 0;
     for (;;) {
@@ -580,6 +667,8 @@ static int validate(const ax_problem* p, int nrhs, const ax_cg_opts* o)
         return fail(AX_ERR_ARG, "refinement needs inner_rtol > 0 and max_outer >= 1");
     if (o->refine != AX_REFINE_RESTART && o->refine != AX_REFINE_RELIABLE)
         return fail(AX_ERR_ARG, "refine must be AX_REFINE_RESTART or AX_REFINE_RELIABLE");
+    if (o->precond != AX_PRECOND_NONE && o->precond != AX_PRECOND_JACOBI)
+        return fail(AX_ERR_ARG, "precond must be AX_PRECOND_NONE or AX_PRECOND_JACOBI");
     if (o->inner_prec != AX_FP64 && o->refine == AX_REFINE_RELIABLE && !(o->inner_rtol < 1.0))
         return fail(AX_ERR_ARG, "reliable updates need inner_rtol < 1");
     if (p->E > 0 && (!p->geo || !p->D || !p->w || !p->l2g || !p->gptr || !p->gidx))
@@ -588,6 +677,20 @@ static int validate(const ax_problem* p, int nrhs, const ax_cg_opts* o)
     const int64_t N1 = p->N + 1;
     if (p->E > 0x7fffffffLL / (N1 * N1 * N1))
         return fail(AX_ERR_UNSUPPORTED, "more than 2^31 - 1 local nodes (local ids are int32)");
+    return AX_OK;
+}
+
+// Jacobi preconditioner of the assembled operator: the element diagonals (recomputed factors)
+// in the local work vector, assembled by Q^T, inverted on the free nodes (0 on the masked ones).
+static int jacobi_setup(Operator& op, const CgWork& w, hipStream_t st)
+{
+    if (!w.dinv) return AX_OK;
+    AX_TRY(gs_apply(op.n_local, op.n_global, op.l2g, op.gptr, op.gidx, op.mask, GS_QT, 1, AX_FP64, w.wl, w.Ap, st));
+    hipLaunchKernelGGL(invert_diag_kernel, dim3(vgrid(op.n_global)), dim3(256), 0, st, w.dinv, w.dinv32, w.Ap,
+                       op.mask, op.n_global);
+    AX_TRY(hip_check(hipGetLastError(), "jacobi inverse"));
+    op.dinv64 = w.dinv;
+    op.dinv32 = w.dinv32;
     return AX_OK;
 }
 
@@ -668,12 +771,11 @@ static int solve(const Operator& op, int64_t nl, int nrhs, const double* b, doub
         AX_TRY(true_residual(worst));
         if (worst > o->rtol) {
             hipLaunchKernelGGL(to_f32_kernel, gv, dim3(256), 0, st, w.r32, w.r, n);
-            hipLaunchKernelGGL(copy_kernel<float>, gv, dim3(256), 0, st, w.p32, w.r32, n);
+            hipLaunchKernelGGL(precond_kernel<float>, g, dim3(256), 0, st, w.p32, w.r32, op.dinv32, ng);
             hipLaunchKernelGGL(zero_kernel<float>, gv, dim3(256), 0, st, w.d32, n);
             AX_TRY(dot(b, b, ng, nrhs, w.partials, st));
             hipLaunchKernelGGL(set_tol_kernel, dim3(nrhs), dim3(kRedThreads), 0, st, w.sc_in, w.partials, o->rtol);
-            AX_TRY(dot(w.r32, w.r32, ng, nrhs, w.partials, st));
-            AX_TRY(scal(w.partials, w.sc_in, 0, nrhs, st));
+            AX_TRY(rr_rz<float>(w.r32, op.dinv32, ng, nrhs, w.partials, w.sc_in, 0, st));
             AX_TRY(poll(w.sc_in, nrhs, hi, st));
             std::vector<double> rref(nrhs);
             for (int c = 0; c < nrhs; ++c) rref[c] = hi[c].rr;
@@ -720,9 +822,8 @@ static int solve(const Operator& op, int64_t nl, int nrhs, const double* b, doub
                 }
                 if (worst <= o->rtol || total >= o->max_it || updates >= o->max_outer) break;
                 hipLaunchKernelGGL(to_f32_kernel, gv, dim3(256), 0, st, w.r32, w.r, n);
-                if (restart_dir) hipLaunchKernelGGL(copy_kernel<float>, gv, dim3(256), 0, st, w.p32, w.r32, n);
-                AX_TRY(dot(w.r32, w.r32, ng, nrhs, w.partials, st));
-                AX_TRY(scal(w.partials, w.sc_in, 3, nrhs, st));
+                if (restart_dir) hipLaunchKernelGGL(precond_kernel<float>, g, dim3(256), 0, st, w.p32, w.r32, op.dinv32, ng);
+                AX_TRY(rr_rz<float>(w.r32, op.dinv32, ng, nrhs, w.partials, w.sc_in, 3, st));
                 AX_TRY(poll(w.sc_in, nrhs, hi, st));
                 for (int c = 0; c < nrhs; ++c) rref[c] = hi[c].rr;
             }
@@ -802,7 +903,7 @@ extern "C" int cg_workspace_bytes(const ax_problem* p, int nrhs, const ax_cg_opt
     const int N1 = p->N + 1;
     Carver cv{nullptr, 0, 0};
     CgWork w;
-    carve(cv, p->E * N1 * N1 * N1, p->n_global, nrhs, o->inner_prec != AX_FP64, w);
+    carve(cv, p->E * N1 * N1 * N1, p->n_global, nrhs, o->inner_prec != AX_FP64, o->precond == AX_PRECOND_JACOBI, w);
     *bytes = cv.used + 256;
     return AX_OK;
 }
@@ -828,7 +929,7 @@ extern "C" int cg_solve(const ax_problem* p, int nrhs, const double* b, double* 
     const int64_t nl = p->E * N1 * N1 * N1;
     Carver cv{(char*)(((uintptr_t)o->workspace + 255) & ~uintptr_t(255)), 0, o->workspace_bytes - 256};
     CgWork w;
-    carve(cv, nl, p->n_global, nrhs, o->inner_prec != AX_FP64, w);
+    carve(cv, nl, p->n_global, nrhs, o->inner_prec != AX_FP64, o->precond == AX_PRECOND_JACOBI, w);
     Operator op;
     op.n_local = nl;
     op.n_global = p->n_global;
@@ -841,6 +942,10 @@ extern "C" int cg_solve(const ax_problem* p, int nrhs, const double* b, double* 
                        p->mask, p->n_global);
     op.pairs = w.pairs;
     AX_TRY(check_masked_rhs(b, op.mask, op.n_global, nrhs, w.flag, st));
+    if (w.dinv) {
+        AX_TRY(ax_local_diag(p->E, p->N, p->geom, p->geo, p->D, p->xi, p->w, w.wl, st));
+        AX_TRY(jacobi_setup(op, w, st));
+    }
     const int status = solve(op, nl, nrhs, b, x, o, rep, w, st);
     if (status != AX_OK && status != AX_ERR_NOT_CONVERGED && status != AX_ERR_BREAKDOWN) {
         (void)hipStreamSynchronize(st);
@@ -892,7 +997,7 @@ extern "C" int cg_batched_workspace_bytes(int n_mesh, const ax_problem* meshes, 
     batched_sizes(n_mesh, meshes, nl, lbase);
     Carver cv{nullptr, 0, 0};
     CgWork w;
-    carve(cv, nl, n_global, nrhs, o->inner_prec != AX_FP64, w);
+    carve(cv, nl, n_global, nrhs, o->inner_prec != AX_FP64, o->precond == AX_PRECOND_JACOBI, w);
     size_t bw = 0;
     AX_TRY(ax_batched_workspace_bytes(n_mesh, meshes, &bw));
     *bytes = cv.used + 2 * ((bw + 255) & ~size_t(255)) + 512;
@@ -922,7 +1027,7 @@ extern "C" int cg_solve_batched(int n_mesh, const ax_problem* meshes, int64_t n_
     Carver cv{(char*)(((uintptr_t)o->workspace + 255) & ~uintptr_t(255)), 0, o->workspace_bytes - 256};
     CgWork w;
     const bool mixed = o->inner_prec != AX_FP64;
-    carve(cv, nl, n_global, nrhs, mixed, w);
+    carve(cv, nl, n_global, nrhs, mixed, o->precond == AX_PRECOND_JACOBI, w);
     size_t bw = 0;
     AX_TRY(ax_batched_workspace_bytes(n_mesh, meshes, &bw));
     char* ws64 = cv.take<char>(bw);
@@ -959,6 +1064,13 @@ extern "C" int cg_solve_batched(int n_mesh, const ax_problem* meshes, int64_t n_
                        n_global);
     op.pairs = w.pairs;
     AX_TRY(check_masked_rhs(b, op.mask, op.n_global, nrhs, w.flag, st));
+    if (w.dinv) {
+        for (int q = 0; q < n_mesh; ++q) {
+            const ax_problem& m = meshes[q];
+            AX_TRY(ax_local_diag(m.E, m.N, m.geom, m.geo, m.D, m.xi, m.w, w.wl + lbase[q], st));
+        }
+        AX_TRY(jacobi_setup(op, w, st));
+    }
     const int status = solve(op, nl, nrhs, b, x, o, rep, w, st);
     if (status != AX_OK && status != AX_ERR_NOT_CONVERGED && status != AX_ERR_BREAKDOWN) {
         (void)hipStreamSynchronize(st);

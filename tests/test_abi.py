@@ -136,6 +136,14 @@ def test_cg_validation(ax):
     p.N = 3
     o.rtol = 0.0
     assert L.cg_workspace_bytes(ctypes.byref(p), 1, ctypes.byref(o), ctypes.byref(n)) == ax.AX_ERR_ARG
+    o.rtol = 1e-10
+    n0 = ctypes.c_size_t(0)
+    assert L.cg_workspace_bytes(ctypes.byref(p), 1, ctypes.byref(o), ctypes.byref(n0)) == ax.AX_OK
+    o.precond = ax.AX_PRECOND_JACOBI
+    assert L.cg_workspace_bytes(ctypes.byref(p), 1, ctypes.byref(o), ctypes.byref(n)) == ax.AX_OK
+    assert n.value >= n0.value + 8 * p.n_global          # room for the inverse diagonal
+    o.precond = 7
+    assert L.cg_workspace_bytes(ctypes.byref(p), 1, ctypes.byref(o), ctypes.byref(n)) == ax.AX_ERR_ARG
 
 
 def test_partial_validation(ax):

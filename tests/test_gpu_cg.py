@@ -182,3 +182,103 @@ def test_batched_cg_union(ax, inner):
         r = rhss[q] - oracle.apply_A(N, D, G, l2gq, ngq, maskq, xq)
         r2 += float(r @ r)
     assert np.sqrt(r2) / np.linalg.norm(b) <= 1e-10
+
+
+@pytest.mark.parametrize("N,geom", [(1, "tri"), (3, "tri"), (7, "tri"), (11, "tri"), (15, "tri"), (4, "para"), (7, "para")])
+def test_local_diag_vs_oracle(ax, N, geom):
+    """Element diagonals of D^T G D with recomputed factors against the oracle's diagonal."""
+    import torch
+    if geom == "tri":
+        m = meshgen.jittered_hex(3, 2, 2, alpha=0.15, seed=60 + N)
+    else:
+        m, _ = meshgen.parallelepiped_hex(2, 2, 3, seed=N)
+    xi, w, D = oracle.gll(N)
+    G, _, _ = oracle.geom_factors(m.verts, N, xi, w)
+    ref = oracle.ax_diag(D, G)
+    b = ax.Basis(N)
+    V = torch.from_numpy(m.verts).cuda()
+    if geom == "tri":
+        dg = ax.local_diag(V, b, ax.AX_TRILINEAR)
+    else:
+        dg = ax.local_diag(ax.parallelepiped_factors(V), b, ax.AX_PARALLELEPIPED)
+    err = np.abs(dg.cpu().numpy() - ref).max() / np.abs(ref).max()
+    print(f"[parity] local diag {geom} N={N} max rel err {err:.3e}", flush=True)
+    assert err <= 1e-13
+
+
+@pytest.mark.parametrize("N,grid", [(3, (3, 3, 3)), (5, (2, 3, 2))])
+def test_jacobi_pcg_fp64_matches_oracle(ax, N, grid):
+    """Jacobi-preconditioned CG (Nekbone's solver, Sec. 5.6) against the oracle's PCG: same
+    iteration count up to rounding drift, same solution, and the oracle recomputes the residual."""
+    import torch
+    m, prob, ref, rhs = _problem(ax, N, grid)
+    D, G, l2g, ng, mask = ref
+    xg, rep = ax.cg_solve(prob, torch.from_numpy(rhs[None]).cuda(), rtol=1e-10, precond=ax.AX_PRECOND_JACOBI)
+    assert rep["status"] == "AX_OK", rep
+    x = xg.cpu().numpy()[0]
+    assert _oracle_rel_res(N, ref, rhs, x) <= 1e-10
+    dinv = oracle.jacobi_dinv(D, G, l2g, ng, mask)
+    xo, it, rel = oracle.pcg(N, D, G, l2g, ng, mask, rhs, dinv, rtol=1e-10)
+    assert np.abs(x - xo).max() <= 1e-8 * np.abs(xo).max()
+    assert abs(rep["iterations"] - it) <= max(2, it // 100), (rep["iterations"], it)
+    _, r_cg = ax.cg_solve(prob, torch.from_numpy(rhs[None]).cuda(), rtol=1e-10)
+    print(f"[pcg] N={N} grid={grid} jacobi {rep['iterations']} its (oracle {it}), plain {r_cg['iterations']}", flush=True)
+    assert rep["iterations"] < r_cg["iterations"]
+
+
+@pytest.mark.parametrize("refine", ["reliable", "restart"])
+def test_jacobi_pcg_mixed_reaches_fp64_residual(ax, refine):
+    import torch
+    N = 4
+    m, prob, ref, rhs = _problem(ax, N, (3, 3, 3))
+    kw = dict(inner_rtol=0.1, refine=ax.AX_REFINE_RELIABLE) if refine == "reliable" else dict(inner_rtol=1e-5)
+    xg, rep = ax.cg_solve(prob, torch.from_numpy(rhs[None]).cuda(), rtol=1e-10, inner_prec=ax.AX_FP32,
+                          precond=ax.AX_PRECOND_JACOBI, **kw)
+    assert rep["status"] == "AX_OK", rep
+    assert rep["outer_it"] >= 2
+    assert _oracle_rel_res(N, ref, rhs, xg.cpu().numpy()[0]) <= 1e-10
+
+
+def test_jacobi_pcg_graph_replay_equals_eager(ax):
+    import torch
+    N = 3
+    m, prob, ref, rhs = _problem(ax, N, (3, 3, 2))
+    bd = torch.from_numpy(rhs[None]).cuda()
+    xg, rg = ax.cg_solve(prob, bd, rtol=1e-10, use_graph=True, precond=ax.AX_PRECOND_JACOBI)
+    xe, re = ax.cg_solve(prob, bd, rtol=1e-10, use_graph=False, precond=ax.AX_PRECOND_JACOBI)
+    assert rg["status"] == re["status"] == "AX_OK"
+    assert rg["iterations"] == re["iterations"]
+    assert torch.equal(xg, xe)
+
+
+@pytest.mark.parametrize("inner", ["fp64", "fp32"])
+def test_jacobi_batched_cg_union(ax, inner):
+    """Jacobi PCG over the block-diagonal union of meshes of different order (diagonals per mesh,
+    one assembly of the union); the oracle recomputes every mesh's residual."""
+    import torch
+    specs = [(2, (3, 2, 2)), (3, (2, 2, 2)), (5, (2, 1, 2)), (4, (2, 2, 3))]
+    meshes, parts, refs, rhss = [], [], [], []
+    for q, (N, grid) in enumerate(specs):
+        m = meshgen.jittered_hex(*grid, alpha=0.1, seed=40 + q)
+        l2g, ng, mask = meshgen.global_numbering(*grid, N)
+        xi, w, D = oracle.gll(N)
+        G, _, _ = oracle.geom_factors(m.verts, N, xi, w)
+        rhs, _ = oracle.poisson_rhs(N, m.verts, xi, w, l2g, ng, mask)
+        meshes.append((torch.from_numpy(m.verts).cuda(), ax.Basis(N)))
+        parts.append((l2g, ng, mask))
+        refs.append((N, D, G, l2g, ng, mask))
+        rhss.append(rhs)
+    l2g, ng, mask, loff, goff = meshgen.concat_numbering(parts)
+    gs = ax.GatherScatter(l2g, ng, mask)
+    b = np.concatenate(rhss)
+    ip = ax.AX_FP64 if inner == "fp64" else ax.AX_FP32
+    x, rep = ax.cg_solve_batched(meshes, gs, torch.from_numpy(b[None]).cuda(), rtol=1e-10, inner_prec=ip,
+                                 inner_rtol=1e-5, precond=ax.AX_PRECOND_JACOBI)
+    assert rep["status"] == "AX_OK", rep
+    x = x.cpu().numpy()[0]
+    r2 = 0.0
+    for q, (N, D, G, l2gq, ngq, maskq) in enumerate(refs):
+        xq = x[goff[q]:goff[q + 1]]
+        r = rhss[q] - oracle.apply_A(N, D, G, l2gq, ngq, maskq, xq)
+        r2 += float(r @ r)
+    assert np.sqrt(r2) / np.linalg.norm(b) <= 1e-10
