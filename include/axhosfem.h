@@ -84,6 +84,18 @@ int ax_local(int64_t E, int N, int geom, const double* geo, const double* D, con
              const double* w, int nrhs, int prec, const void* X, void* Y, void* stream);
 
 /*
+ * ax_local_vector - AxLocal on a vector field (n_col = 3, Sec. 2.1: X and Y hold three columns,
+ * one per component), in the component-interleaved layout X, Y [dev] [E][3][N1^3] (the three
+ * components of an element contiguous).  The geometric factors are recomputed once per element
+ * and serve the three components (the geometry loop outermost, Sec. 4.1), so the traffic per
+ * element is 2 x 3 N1^3 values plus the geometry input.  geom AX_TRILINEAR (geo = vertices) or
+ * AX_PARALLELEPIPED (geo = h), prec AX_FP64 or AX_FP32 (AX_FP16_ACC32 -> AX_ERR_UNSUPPORTED);
+ * other arguments and errors as ax_local.
+ */
+int ax_local_vector(int64_t E, int N, int geom, const double* geo, const double* D, const double* xi,
+                    const double* w, int prec, const void* X, void* Y, void* stream);
+
+/*
  * ax_tune_set / ax_tune_get - [host] launch tuning of the AxLocal kernels for one
  * (order N, geometry kind, precision): geom_kind AX_TRILINEAR, AX_PARALLELEPIPED or
  * AX_STORED_G (ax_local_precomputedG); prec AX_FP64 or AX_FP32.  epb_alt 0 selects the default

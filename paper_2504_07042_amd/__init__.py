@@ -75,6 +75,7 @@ _SIGS = {
     "ax_tune_get": (_int, [_int, _int, _int, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_int)]),
     "ax_local": (_int, [_i64, _int, _int, _vp, _vp, _vp, _vp, _int, _int, _vp, _vp, _vp]),
     "ax_local_precomputedG": (_int, [_i64, _int, _vp, _vp, _int, _int, _vp, _vp, _vp]),
+    "ax_local_vector": (_int, [_i64, _int, _int, _vp, _vp, _vp, _vp, _int, _vp, _vp, _vp]),
     "ax_geom_factors": (_int, [_i64, _int, _vp, _vp, _vp, _int, _vp, _vp, _vp]),
     "ax_local_partial": (_int, [_i64, _int, _vp, _vp, _vp, _vp, _vp, _int, _int, _vp, _vp, _vp]),
     "ax_geom_lambda": (_int, [_i64, _int, _vp, _vp, _vp, _int, _vp, _vp]),
@@ -189,6 +190,19 @@ def ax_local(X, geo, basis: Basis, geom=AX_TRILINEAR, prec=AX_FP64, out=None, st
     Y = torch.empty_like(X) if out is None else out
     _check(lib().ax_local(E, basis.N, geom, _dptr(geo), _np_ptr(basis.D), _np_ptr(basis.xi),
                           _np_ptr(basis.w), nrhs, prec, _dptr(X), _dptr(Y), _stream(stream)))
+    return Y
+
+
+def ax_local_vector(X, geo, basis: Basis, geom=AX_TRILINEAR, prec=AX_FP64, out=None, stream=None):
+    """Y = AxLocal(X) for a vector field: X [E][3][N1^3] device tensor (the three components of an
+    element contiguous), factors recomputed once per element for all three (Sec. 4.1)."""
+    import torch
+    E = geo.shape[0]
+    assert X.dim() == 3 and X.shape[0] == E and X.shape[1] == 3 and X.shape[2] == (basis.N + 1) ** 3
+    assert X.dtype == _prec_dtype(prec) and geo.dtype == torch.float64
+    Y = torch.empty_like(X) if out is None else out
+    _check(lib().ax_local_vector(E, basis.N, geom, _dptr(geo), _np_ptr(basis.D), _np_ptr(basis.xi),
+                                 _np_ptr(basis.w), prec, _dptr(X), _dptr(Y), _stream(stream)))
     return Y
 
 

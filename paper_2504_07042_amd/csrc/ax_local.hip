@@ -24,10 +24,13 @@ namespace ax {
 
 int axl_dispatch_f64(int geo_kind, int N, int64_t E, int nrhs, const double* geo, const double* Gs,
                      const double* X, double* Y, const double* D, const double* xi, const double* w,
-                     hipStream_t st, const int32_t* l2g, int64_t ldg);
+                     hipStream_t st, const int32_t* l2g, int64_t ldg, int64_t es, int64_t ccs);
 int axl_dispatch_f32(int geo_kind, int N, int64_t E, int nrhs, const double* geo, const float* Gs,
                      const float* X, float* Y, const double* D, const double* xi, const double* w,
-                     hipStream_t st, const int32_t* l2g, int64_t ldg);
+                     hipStream_t st, const int32_t* l2g, int64_t ldg, int64_t es, int64_t ccs);
+
+// values per element and column: (N + 1)^3
+static inline int64_t NPL(int N) { return (int64_t)(N + 1) * (N + 1) * (N + 1); }
 
 static int check_common(int64_t E, int N, int nrhs, int prec, const void* X, const void* Y,
                         const double* D)
@@ -51,8 +54,8 @@ int ax_local_gather(const ax_problem& p, int nrhs, int prec, const void* xg, int
     if (p.E == 0) return AX_OK;
     const int gk = p.geom == AX_TRILINEAR ? GEO_TRI : GEO_PARA;
     if (prec == AX_FP64)
-        return axl_dispatch_f64(gk, p.N, p.E, nrhs, p.geo, nullptr, (const double*)xg, (double*)Y, p.D, p.xi, p.w, st, p.l2g, ldg);
-    return axl_dispatch_f32(gk, p.N, p.E, nrhs, p.geo, nullptr, (const float*)xg, (float*)Y, p.D, p.xi, p.w, st, p.l2g, ldg);
+        return axl_dispatch_f64(gk, p.N, p.E, nrhs, p.geo, nullptr, (const double*)xg, (double*)Y, p.D, p.xi, p.w, st, p.l2g, ldg, NPL(p.N), p.E * NPL(p.N));
+    return axl_dispatch_f32(gk, p.N, p.E, nrhs, p.geo, nullptr, (const float*)xg, (float*)Y, p.D, p.xi, p.w, st, p.l2g, ldg, NPL(p.N), p.E * NPL(p.N));
 }
 
 // FP16-input / FP32-accumulate variants live in ax_local_f16.hip.
@@ -79,9 +82,9 @@ extern "C" int ax_local(int64_t E, int N, int geom, const double* geo, const dou
     hipStream_t st = as_stream(stream);
     const int gk = geom == AX_TRILINEAR ? GEO_TRI : GEO_PARA;
     if (prec == AX_FP64)
-        return axl_dispatch_f64(gk, N, E, nrhs, geo, nullptr, (const double*)X, (double*)Y, D, xi, w, st, nullptr, 0);
+        return axl_dispatch_f64(gk, N, E, nrhs, geo, nullptr, (const double*)X, (double*)Y, D, xi, w, st, nullptr, 0, NPL(N), E * NPL(N));
     if (prec == AX_FP32)
-        return axl_dispatch_f32(gk, N, E, nrhs, geo, nullptr, (const float*)X, (float*)Y, D, xi, w, st, nullptr, 0);
+        return axl_dispatch_f32(gk, N, E, nrhs, geo, nullptr, (const float*)X, (float*)Y, D, xi, w, st, nullptr, 0, NPL(N), E * NPL(N));
     return ax_local_f16(E, N, gk, geo, nullptr, D, xi, w, nrhs, (const float*)X, (float*)Y, st);
 }
 
@@ -94,9 +97,9 @@ extern "C" int ax_local_precomputedG(int64_t E, int N, const void* G, const doub
     if (!G) return fail(AX_ERR_ARG, "G is NULL");
     hipStream_t st = as_stream(stream);
     if (prec == AX_FP64)
-        return axl_dispatch_f64(GEO_STORED, N, E, nrhs, nullptr, (const double*)G, (const double*)X, (double*)Y, D, nullptr, nullptr, st, nullptr, 0);
+        return axl_dispatch_f64(GEO_STORED, N, E, nrhs, nullptr, (const double*)G, (const double*)X, (double*)Y, D, nullptr, nullptr, st, nullptr, 0, NPL(N), E * NPL(N));
     if (prec == AX_FP32)
-        return axl_dispatch_f32(GEO_STORED, N, E, nrhs, nullptr, (const float*)G, (const float*)X, (float*)Y, D, nullptr, nullptr, st, nullptr, 0);
+        return axl_dispatch_f32(GEO_STORED, N, E, nrhs, nullptr, (const float*)G, (const float*)X, (float*)Y, D, nullptr, nullptr, st, nullptr, 0, NPL(N), E * NPL(N));
     return ax_local_f16(E, N, GEO_STORED, nullptr, (const float*)G, D, nullptr, nullptr, nrhs, (const float*)X, (float*)Y, st);
 }
 
@@ -113,9 +116,9 @@ extern "C" int ax_local_partial(int64_t E, int N, const double* verts, const voi
     hipStream_t st = as_stream(stream);
     if (prec == AX_FP64)
         return axl_dispatch_f64(GEO_TRIL, N, E, nrhs, verts, (const double*)lam, (const double*)X, (double*)Y, D,
-                                xi, w, st, nullptr, 0);
+                                xi, w, st, nullptr, 0, NPL(N), E * NPL(N));
     return axl_dispatch_f32(GEO_TRIL, N, E, nrhs, verts, (const float*)lam, (const float*)X, (float*)Y, D, xi, w,
-                            st, nullptr, 0);
+                            st, nullptr, 0, NPL(N), E * NPL(N));
 }
 
 extern "C" int ax_local_helmholtz(int64_t E, int N, const double* verts, const void* L23, const double* D,
@@ -131,7 +134,30 @@ extern "C" int ax_local_helmholtz(int64_t E, int N, const double* verts, const v
     hipStream_t st = as_stream(stream);
     if (prec == AX_FP64)
         return axl_dispatch_f64(GEO_HELM, N, E, nrhs, verts, (const double*)L23, (const double*)X, (double*)Y, D,
-                                xi, w, st, nullptr, 0);
+                                xi, w, st, nullptr, 0, NPL(N), E * NPL(N));
     return axl_dispatch_f32(GEO_HELM, N, E, nrhs, verts, (const float*)L23, (const float*)X, (float*)Y, D, xi, w,
-                            st, nullptr, 0);
+                            st, nullptr, 0, NPL(N), E * NPL(N));
+}
+
+extern "C" int ax_local_vector(int64_t E, int N, int geom, const double* geo, const double* D, const double* xi,
+                               const double* w, int prec, const void* X, void* Y, void* stream)
+{
+    clear_error();
+    AX_TRY(check_common(E, N, 3, prec, X, Y, D));
+    if (prec == AX_FP16_ACC32) return fail(AX_ERR_UNSUPPORTED, "the vector-field operator is FP64 or FP32");
+    if (geom != AX_TRILINEAR && geom != AX_PARALLELEPIPED)
+        return fail(AX_ERR_UNSUPPORTED, "unknown geometry %d", geom);
+    if (!w) return fail(AX_ERR_ARG, "w is NULL");
+    if (geom == AX_TRILINEAR && !xi) return fail(AX_ERR_ARG, "xi is NULL (needed for trilinear)");
+    if (E == 0) return AX_OK;
+    if (!geo) return fail(AX_ERR_ARG, "geo is NULL");
+    hipStream_t st = as_stream(stream);
+    const int gk = geom == AX_TRILINEAR ? GEO_TRI : GEO_PARA;
+    const int64_t np = NPL(N);
+    // three components per element, contiguous: element stride 3 N1^3, component stride N1^3
+    if (prec == AX_FP64)
+        return axl_dispatch_f64(gk, N, E, 3, geo, nullptr, (const double*)X, (double*)Y, D, xi, w, st, nullptr, 0,
+                                3 * np, np);
+    return axl_dispatch_f32(gk, N, E, 3, geo, nullptr, (const float*)X, (float*)Y, D, xi, w, st, nullptr, 0, 3 * np,
+                            np);
 }

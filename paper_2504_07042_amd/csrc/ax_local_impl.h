@@ -79,6 +79,7 @@ struct AxArgs {
     T* Y;
     const int32_t* l2g;
     int64_t ldg;
+    int64_t es, ccs;
     Basis<T> bs;
 };
 
@@ -156,12 +157,14 @@ __device__ __forceinline__ void rpencil_write(T* F, int j, int k, const T* o)
 
 // Kernel body.  GATHER: X is a global vector [nrhs][ldg] read through the local-to-global map
 // l2g (the Q of Sec. 2.1 fused into the load), so the solver never materialises Q x.  `cs` is the
-// source of the contraction coefficients (CoefResident or CoefReload).
+// source of the contraction coefficients (CoefResident or CoefReload).  Local vectors: node l of
+// column c of element e at c * ccs + e * es + l (es = N1^3, ccs = E N1^3 for [nrhs][E][N1^3];
+// es = nrhs N1^3, ccs = N1^3 for the component-interleaved [E][nrhs][N1^3] of a vector field).
 template <int N1, int GEO, bool EO, bool GATHER, int EPBX, typename T, typename C>
 __device__ __forceinline__ void
 ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __restrict__ Gs,
               const T* __restrict__ X, T* __restrict__ Y, const Basis<T>& bs,
-              const int32_t* __restrict__ l2g, int64_t ldg, const C& cs)
+              const int32_t* __restrict__ l2g, int64_t ldg, int64_t es, int64_t ccs, const C& cs)
 {
     using S = Shape<N1, sizeof(T)>;
     using TL = Tile<N1, EPBX>;
@@ -214,7 +217,9 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
     auto clamp_group = [&](int64_t ebq) -> int64_t { return ebq < nblk ? ebq : 0; };
     auto slot_active = [&](int64_t g) -> bool { return (slot < EPB) && (g * EPB + slot < E); };
     // byte offset of node (i, j, 0) of this lane's element from the group's first node
-    auto home_off = [&](bool act) -> uint32_t { return (uint32_t)(((act ? slot * NP : 0) + i + j * N1) * sizeof(T)); };
+    auto home_off = [&](bool act) -> uint32_t {
+        return (uint32_t)(((act ? slot * es : 0) + i + j * N1) * (int64_t)sizeof(T));
+    };
     auto load_x = [&](int64_t ebq, int cq, T* dst) {
         const int64_t g = clamp_group(ebq);
         const uint32_t lo = home_off(slot_active(g));
@@ -227,7 +232,7 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
 #pragma unroll
             for (int k = 0; k < N1; ++k) dst[k] = xc[gi[k]];
         } else {
-            const T* src = X + ((int64_t)cq * E + g * EPB) * NP;
+            const T* src = X + (int64_t)cq * ccs + g * EPB * es;
 #pragma unroll
             for (int k = 0; k < N1; ++k) dst[k] = *at_bytes(src, lo + k * NT * (uint32_t)sizeof(T));
         }
@@ -401,7 +406,7 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
 #pragma unroll
             for (int k = 0; k < N1; ++k) y2[k] = fma(l3v[k], xv[k], y2[k]);
         }
-        T* yb = Y + ((int64_t)c * E + eb * EPB) * NP;
+        T* yb = Y + (int64_t)c * ccs + eb * EPB * es;
         const uint32_t lo = home_off(true);
 #if AX_MERGE_RS
         // P5: Y = (D_r^T r + D_s^T s) + D_t^T t
@@ -464,9 +469,9 @@ template <int N1, int GEO, bool EO, bool GATHER, int EPBX, typename T>
 __global__ void __launch_bounds__((Tile<N1, EPBX>::BLOCK), (min_waves<N1, GEO, T>()))
 ax_local_kernel(int64_t E, int nrhs, const double* __restrict__ geo, const T* __restrict__ Gs,
                 const T* __restrict__ X, T* __restrict__ Y, const Basis<T> bs,
-                const int32_t* __restrict__ l2g, int64_t ldg)
+                const int32_t* __restrict__ l2g, int64_t ldg, int64_t es, int64_t ccs)
 {
-    ax_local_body<N1, GEO, EO, GATHER, EPBX, T>(E, nrhs, geo, Gs, X, Y, bs, l2g, ldg, CoefResident<T>{bs});
+    ax_local_body<N1, GEO, EO, GATHER, EPBX, T>(E, nrhs, geo, Gs, X, Y, bs, l2g, ldg, es, ccs, CoefResident<T>{bs});
 }
 
 template <int N1, int GEO, bool EO, bool GATHER, int EPBX, typename T>
@@ -474,12 +479,12 @@ __global__ void __launch_bounds__((Tile<N1, EPBX>::BLOCK), (min_waves<N1, GEO, T
 ax_local_kernel_rl(const AxArgs<T> ka)
 {
     const CoefReload<T> cs = karg_coefs<T, AxArgs<T>>();
-    ax_local_body<N1, GEO, EO, GATHER, EPBX, T>(ka.E, ka.nrhs, ka.geo, ka.Gs, ka.X, ka.Y, ka.bs, ka.l2g, ka.ldg, cs);
+    ax_local_body<N1, GEO, EO, GATHER, EPBX, T>(ka.E, ka.nrhs, ka.geo, ka.Gs, ka.X, ka.Y, ka.bs, ka.l2g, ka.ldg, ka.es, ka.ccs, cs);
 }
 
 template <int N1, int GEO, bool EO, bool GATHER, int EPBX, typename T>
 static int launch_tile(int64_t E, int nrhs, const double* geo, const T* Gs, const T* X, T* Y, const Basis<T>& bs,
-                       int grid_mult, hipStream_t st, const int32_t* l2g, int64_t ldg)
+                       int grid_mult, hipStream_t st, const int32_t* l2g, int64_t ldg, int64_t es, int64_t ccs)
 {
     using TL = Tile<N1, EPBX>;
     static int per = 0;  // resident work-groups per CU for this instantiation
@@ -505,20 +510,22 @@ static int launch_tile(int64_t E, int nrhs, const double* geo, const T* Gs, cons
     const int64_t blocks = nblk < cap ? nblk : cap;
     if (blocks > 0x7fffffff) return fail(AX_ERR_UNSUPPORTED, "too many elements for one launch");
     if constexpr (reload_coefs<N1, GEO, T>()) {
-        const AxArgs<T> ka{E, nrhs, geo, Gs, X, Y, l2g, ldg, bs};
+        const AxArgs<T> ka{E, nrhs, geo, Gs, X, Y, l2g, ldg, es, ccs, bs};
         hipLaunchKernelGGL((ax_local_kernel_rl<N1, GEO, EO, GATHER, EPBX, T>), dim3((unsigned)blocks),
                            dim3(TL::BLOCK), 0, st, ka);
     } else {
         hipLaunchKernelGGL((ax_local_kernel<N1, GEO, EO, GATHER, EPBX, T>), dim3((unsigned)blocks), dim3(TL::BLOCK),
-                           0, st, E, nrhs, geo, Gs, X, Y, bs, l2g, ldg);
+                           0, st, E, nrhs, geo, Gs, X, Y, bs, l2g, ldg, es, ccs);
     }
     return hip_check(hipGetLastError(), "ax_local launch");
 }
 
 int tri_item_dispatch_f64(int N1, int64_t E, int nrhs, const double* verts, const double* X, double* Y,
-                          const Basis<double>& bs, int grid_mult, hipStream_t st, const double* lam);
+                          const Basis<double>& bs, int grid_mult, hipStream_t st, const double* lam, int64_t es,
+                          int64_t ccs);
 int tri_item_dispatch_f32(int N1, int64_t E, int nrhs, const double* verts, const float* X, float* Y,
-                          const Basis<float>& bs, int grid_mult, hipStream_t st, const float* lam);
+                          const Basis<float>& bs, int grid_mult, hipStream_t st, const float* lam, int64_t es,
+                          int64_t ccs);
 // FP32: the per-item kernel from N1 = 9 (measured with it at five waves per SIMD: +7-8 % at
 // N1 = 9 and 10, +13-15 % at N1 = 12, 15, where the prefetching kernel runs at two)
 #ifndef AX_ITEM_LO_F32
@@ -550,7 +557,7 @@ constexpr bool use_item_kernel()
 template <int N1, int GEO, typename T>
 static int launch_n1(int64_t E, int nrhs, const double* geo, const T* Gs, const T* X, T* Y,
                      const double* D, const double* xi, const double* w, hipStream_t st,
-                     const int32_t* l2g, int64_t ldg)
+                     const int32_t* l2g, int64_t ldg, int64_t es, int64_t ccs)
 {
     using S = Shape<N1>;
     Basis<T> bs;
@@ -561,37 +568,37 @@ static int launch_n1(int64_t E, int nrhs, const double* geo, const T* Gs, const 
     if (l2g) {
         if (!eo) return fail(AX_ERR_UNSUPPORTED, "gathering AxLocal needs a GLL differentiation matrix");
         if constexpr (GEO == GEO_TRI || GEO == GEO_PARA)
-            return launch_tile<N1, GEO, true, true, S::EPB, T>(E, nrhs, geo, Gs, X, Y, bs, tu.grid_mult, st, l2g, ldg);
+            return launch_tile<N1, GEO, true, true, S::EPB, T>(E, nrhs, geo, Gs, X, Y, bs, tu.grid_mult, st, l2g, ldg, es, ccs);
         return fail(AX_ERR_UNSUPPORTED, "gathering AxLocal needs on-the-fly factors");
     }
     if constexpr (use_item_kernel<N1, GEO, T>()) {
         if (eo && !l2g) {
             if constexpr (sizeof(T) == 8)
                 return tri_item_dispatch_f64(N1, E, nrhs, geo, (const double*)X, (double*)Y, bs, tu.grid_mult, st,
-                                             GEO == GEO_TRIL ? (const double*)Gs : nullptr);
+                                             GEO == GEO_TRIL ? (const double*)Gs : nullptr, es, ccs);
             else
                 return tri_item_dispatch_f32(N1, E, nrhs, geo, X, Y, bs, tu.grid_mult, st,
-                                             GEO == GEO_TRIL ? (const float*)Gs : nullptr);
+                                             GEO == GEO_TRIL ? (const float*)Gs : nullptr, es, ccs);
         }
     }
     if (!eo)
-        return launch_tile<N1, GEO, false, false, S::EPB, T>(E, nrhs, geo, Gs, X, Y, bs, tu.grid_mult, st, nullptr, 0);
+        return launch_tile<N1, GEO, false, false, S::EPB, T>(E, nrhs, geo, Gs, X, Y, bs, tu.grid_mult, st, nullptr, 0, es, ccs);
     if constexpr (S::EPB_ALT != S::EPB) {
         if (tu.epb_alt)
             return launch_tile<N1, GEO, true, false, S::EPB_ALT, T>(E, nrhs, geo, Gs, X, Y, bs, tu.grid_mult, st,
-                                                                    nullptr, 0);
+                                                                    nullptr, 0, es, ccs);
     }
-    return launch_tile<N1, GEO, true, false, S::EPB, T>(E, nrhs, geo, Gs, X, Y, bs, tu.grid_mult, st, nullptr, 0);
+    return launch_tile<N1, GEO, true, false, S::EPB, T>(E, nrhs, geo, Gs, X, Y, bs, tu.grid_mult, st, nullptr, 0, es, ccs);
 }
 
 template <int GEO, typename T>
 static int dispatch(int N, int64_t E, int nrhs, const double* geo, const T* Gs, const T* X, T* Y,
                     const double* D, const double* xi, const double* w, hipStream_t st,
-                    const int32_t* l2g, int64_t ldg)
+                    const int32_t* l2g, int64_t ldg, int64_t es, int64_t ccs)
 {
     switch (N + 1) {
 #define AX_CASE(n1) \
-    case n1: return launch_n1<n1, GEO, T>(E, nrhs, geo, Gs, X, Y, D, xi, w, st, l2g, ldg);
+    case n1: return launch_n1<n1, GEO, T>(E, nrhs, geo, Gs, X, Y, D, xi, w, st, l2g, ldg, es, ccs);
         AX_CASE(2) AX_CASE(3) AX_CASE(4) AX_CASE(5) AX_CASE(6) AX_CASE(7) AX_CASE(8) AX_CASE(9)
         AX_CASE(10) AX_CASE(11) AX_CASE(12) AX_CASE(13) AX_CASE(14) AX_CASE(15) AX_CASE(16)
 #undef AX_CASE

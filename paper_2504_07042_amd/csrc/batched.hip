@@ -28,12 +28,13 @@ constexpr int kBMaxN1 = 10;
 // One mesh of a batch (device descriptor) and one work item (element group eb of mesh `mesh`).
 struct BMesh {
     int64_t E;
-    int64_t ld;  // stride between columns of X and Y (elements)
+    int64_t ld;  // stride between columns of X and Y (values)
     const double* verts;
     const void* X;
     void* Y;
     int N1;
     int pad;
+    int64_t es;  // stride between elements of X and Y (values): N1^3, or ncol N1^3 interleaved
 };
 
 struct BItem {
@@ -114,7 +115,7 @@ __device__ __forceinline__ void batched_item(const BMesh& m, int64_t eb, int nrh
         tri_narrow(t64, tc);
     }
     for (int c = 0; c < nrhs; ++c) {
-        const int64_t base = (int64_t)c * m.ld + (active ? e : 0) * NP;
+        const int64_t base = (int64_t)c * m.ld + (active ? e : 0) * m.es;
         T xr[N1], x2[N1];
 #pragma unroll
         for (int k = 0; k < N1; ++k) xr[k] = active ? X[base + i + j * N1 + k * NT] : T(0);
@@ -312,7 +313,7 @@ tri_item_kernel(const ItemArgs<T> a)
 
 template <int N1, typename T, bool PL>
 static int tri_item_launch(int64_t E, int nrhs, const double* verts, const T* X, T* Y, const Basis<T>& bs,
-                           const T* lam, int grid_mult, hipStream_t st)
+                           const T* lam, int grid_mult, hipStream_t st, int64_t es, int64_t ccs)
 {
     static int per = 0, cus = 0;
     if (per == 0) {
@@ -329,19 +330,20 @@ static int tri_item_launch(int64_t E, int nrhs, const double* verts, const T* X,
     const int64_t cap = (int64_t)cus * per * (grid_mult > 0 ? grid_mult : 1);
     const int64_t blocks = ng < cap ? ng : cap;
     if (blocks <= 0) return AX_OK;
-    const ItemArgs<T> a{BMesh{E, E * N1 * N1 * N1, verts, X, Y, N1, 0}, nrhs, bs, lam};
+    const ItemArgs<T> a{BMesh{E, ccs, verts, X, Y, N1, 0, es}, nrhs, bs, lam};
     hipLaunchKernelGGL((tri_item_kernel<N1, T, PL>), dim3((unsigned)blocks), dim3(kBBlock), 0, st, a);
     return hip_check(hipGetLastError(), "ax_local (item kernel) launch");
 }
 
 // lam != nullptr: the partial-recomputation form (orders 9..15).
 int tri_item_dispatch_f64(int N1, int64_t E, int nrhs, const double* verts, const double* X, double* Y,
-                          const Basis<double>& bs, int grid_mult, hipStream_t st, const double* lam)
+                          const Basis<double>& bs, int grid_mult, hipStream_t st, const double* lam, int64_t es,
+                          int64_t ccs)
 {
     if (lam) {
         switch (N1) {
 #define AX_ITEM_CASE(n) \
-    case n: return tri_item_launch<n, double, true>(E, nrhs, verts, X, Y, bs, lam, grid_mult, st);
+    case n: return tri_item_launch<n, double, true>(E, nrhs, verts, X, Y, bs, lam, grid_mult, st, es, ccs);
             AX_ITEM_CASE(9) AX_ITEM_CASE(10) AX_ITEM_CASE(11) AX_ITEM_CASE(12) AX_ITEM_CASE(13) AX_ITEM_CASE(14)
             AX_ITEM_CASE(15)
 #undef AX_ITEM_CASE
@@ -350,7 +352,7 @@ int tri_item_dispatch_f64(int N1, int64_t E, int nrhs, const double* verts, cons
     }
     switch (N1) {
 #define AX_ITEM_CASE(n) \
-    case n: return tri_item_launch<n, double, false>(E, nrhs, verts, X, Y, bs, nullptr, grid_mult, st);
+    case n: return tri_item_launch<n, double, false>(E, nrhs, verts, X, Y, bs, nullptr, grid_mult, st, es, ccs);
         AX_ITEM_CASE(2) AX_ITEM_CASE(3) AX_ITEM_CASE(4) AX_ITEM_CASE(5) AX_ITEM_CASE(6) AX_ITEM_CASE(7)
         AX_ITEM_CASE(8) AX_ITEM_CASE(9) AX_ITEM_CASE(10) AX_ITEM_CASE(11) AX_ITEM_CASE(12) AX_ITEM_CASE(13)
         AX_ITEM_CASE(14) AX_ITEM_CASE(15) AX_ITEM_CASE(16)
@@ -362,12 +364,13 @@ int tri_item_dispatch_f64(int N1, int64_t E, int nrhs, const double* verts, cons
 // FP32 orders served by the per-item kernel (see use_item_kernel in ax_local_impl.h);
 // lam != nullptr: the partial-recomputation form.
 int tri_item_dispatch_f32(int N1, int64_t E, int nrhs, const double* verts, const float* X, float* Y,
-                          const Basis<float>& bs, int grid_mult, hipStream_t st, const float* lam)
+                          const Basis<float>& bs, int grid_mult, hipStream_t st, const float* lam, int64_t es,
+                          int64_t ccs)
 {
     if (lam) {
         switch (N1) {
 #define AX_ITEM_CASE(n) \
-    case n: return tri_item_launch<n, float, true>(E, nrhs, verts, X, Y, bs, lam, grid_mult, st);
+    case n: return tri_item_launch<n, float, true>(E, nrhs, verts, X, Y, bs, lam, grid_mult, st, es, ccs);
             AX_ITEM_CASE(13) AX_ITEM_CASE(14) AX_ITEM_CASE(15)
 #undef AX_ITEM_CASE
         default: return fail(AX_ERR_UNSUPPORTED, "FP32 partial item kernel for N1=%d", N1);
@@ -375,7 +378,7 @@ int tri_item_dispatch_f32(int N1, int64_t E, int nrhs, const double* verts, cons
     }
     switch (N1) {
 #define AX_ITEM_CASE(n) \
-    case n: return tri_item_launch<n, float, false>(E, nrhs, verts, X, Y, bs, nullptr, grid_mult, st);
+    case n: return tri_item_launch<n, float, false>(E, nrhs, verts, X, Y, bs, nullptr, grid_mult, st, es, ccs);
         AX_ITEM_CASE(9) AX_ITEM_CASE(10) AX_ITEM_CASE(11) AX_ITEM_CASE(12) AX_ITEM_CASE(13) AX_ITEM_CASE(14)
         AX_ITEM_CASE(15)
 #undef AX_ITEM_CASE
@@ -546,7 +549,8 @@ static int batched_noalloc(int n_mesh, const ax_problem* meshes, int nrhs, int p
                 const ax_problem& p = meshes[idx[c0 + c]];
                 const int64_t np = (int64_t)N1 * N1 * N1;
                 f.id[c] = idx[c0 + c];
-                f.m[c] = BMesh{p.E, col_stride ? col_stride[f.id[c]] : p.E * np, p.geo, X[f.id[c]], Y[f.id[c]], N1, 0};
+                f.m[c] = BMesh{p.E, col_stride ? col_stride[f.id[c]] : p.E * np, p.geo, X[f.id[c]], Y[f.id[c]], N1, 0,
+                               np};
                 f.groups[c] = (p.E + e - 1) / e;
                 f.item_base[c] = next;
                 next += f.groups[c];
@@ -634,7 +638,7 @@ extern "C" int ax_batched_prepare(int n_mesh, const ax_problem* meshes, int nrhs
         const int64_t np = (int64_t)(meshes[q].N + 1) * (meshes[q].N + 1) * (meshes[q].N + 1);
         const int64_t ld = col_stride ? col_stride[q] : meshes[q].E * np;
         if (ld < meshes[q].E * np) return fail(AX_ERR_ARG, "mesh %d: column stride below E*N1^3", q);
-        bm[q] = BMesh{meshes[q].E, ld, meshes[q].geo, X[q], Y[q], meshes[q].N + 1, 0};
+        bm[q] = BMesh{meshes[q].E, ld, meshes[q].geo, X[q], Y[q], meshes[q].N + 1, 0, np};
     }
     // items grouped by order (one persistent kernel each), meshes of an order largest first
     std::vector<BItem> items;
