@@ -56,7 +56,7 @@ def bytes_per_element(N, geom="tri", nrhs=1, fpsize=8):
     return 2 * nrhs * N1**3 * fpsize + geo
 
 
-def measured_traffic(N, E):
+def measured_traffic(N, E, prec="fp64"):
     """HBM bytes per launch of the headline kernel from the calibrated FETCH_SIZE / WRITE_SIZE
     passes recorded in the package (measured_traffic.json), or None when the kernel sources have
     changed since those counters were taken or the workload differs."""
@@ -71,7 +71,8 @@ def measured_traffic(N, E):
                 h.update(f.read())
     except (OSError, KeyError, ValueError):
         return None
-    if h.hexdigest() != rec["sha256"] or rec["workload"]["N"] != N or rec["workload"]["E"] != E:
+    wl = rec["workload"]
+    if h.hexdigest() != rec["sha256"] or wl["N"] != N or wl["E"] != E or wl.get("precision", "fp64") != prec:
         return None
     return int(rec["bytes_per_launch"])
 
@@ -171,7 +172,7 @@ def cpu_baseline(mesh, N, X, budget_s=10.0):
             "os_cpu_count": os.cpu_count(), "affinity_cpus": aff}
 
 
-def cg_solves(ax, meshgen, dev, N=7, grid=(32, 32, 32), rtol=1e-10, check_with_oracle=True):
+def cg_solves(ax, meshgen, dev, N=7, grid=(32, 32, 32), rtol=1e-10, check_with_oracle=True, fp16=False):
     """-Lap u = f on the unit cube (homogeneous Dirichlet), N = 7, 32^3 trilinear hexes with
     +-10 % jitter (seed 4), f from u = sin(pi x) sin(pi y) sin(pi z).  Time to a true relative
     residual of 1e-10: plain FP64 CG against mixed precision with an FP32 inner AxLocal (reliable
@@ -195,11 +196,13 @@ def cg_solves(ax, meshgen, dev, N=7, grid=(32, 32, 32), rtol=1e-10, check_with_o
     runs = [("fp64", dict(inner_prec=ax.AX_FP64)),
             ("mixed_fp32_reliable", dict(inner_prec=ax.AX_FP32, inner_rtol=0.1, refine=ax.AX_REFINE_RELIABLE)),
             ("mixed_fp32_restart", dict(inner_prec=ax.AX_FP32, inner_rtol=1e-5)),
-            ("mixed_fp16_restart", dict(inner_prec=ax.AX_FP16_ACC32, inner_rtol=1e-2)),
             # Jacobi-preconditioned CG (Nekbone's solver, Sec. 5.6), FP64 and mixed
             ("jacobi_fp64", dict(inner_prec=ax.AX_FP64, precond=ax.AX_PRECOND_JACOBI)),
             ("jacobi_mixed_fp32_reliable", dict(inner_prec=ax.AX_FP32, inner_rtol=0.1, refine=ax.AX_REFINE_RELIABLE,
                                                 precond=ax.AX_PRECOND_JACOBI))]
+    if fp16:
+        # half-precision inner operator (N = 7 only); slower than plain FP64 on MI355X
+        runs.append(("mixed_fp16_restart", dict(inner_prec=ax.AX_FP16_ACC32, inner_rtol=1e-2)))
     # per-launch AxLocal time on this mesh in each precision (for the AxLocal share of a solve)
     t_ax = {}
     xl = meshgen.random_nodal_device(m.E, N, 1, seed=9, device=dev)
@@ -448,6 +451,8 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=2000)
     ap.add_argument("--N", type=int, default=7)
+    ap.add_argument("--prec", choices=("fp64", "fp32"), default="fp64",
+                    help="arithmetic of the headline leg (fp32 only with --no-extras; for profiling the FP32 kernel)")
     ap.add_argument("--grid", type=int, nargs=3, default=None)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="only the headline kernel")
@@ -465,8 +470,15 @@ def main(argv=None):
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the order sweep N in {3,5,7,9,11,15} at ~2^24 local nodes")
     ap.add_argument("--no-peaks", action="store_true", help="skip the bandwidth and arithmetic probes")
+    ap.add_argument("--only-cg", action="store_true",
+                    help="headline and the single-mesh CG legs only (for profiling the solver)")
+    ap.add_argument("--fp16-cg", action="store_true",
+                    help="add the CG leg with the half-precision (matrix-core) inner operator")
     args = ap.parse_args(argv)
 
+    if args.prec != "fp64" and not args.no_extras:
+        print("--prec fp32 profiles the FP32 headline kernel only: add --no-extras", file=sys.stderr)
+        return 2
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only; run with --gpus 1 "
               "(the element-parallel operator would shard by element slabs, one per GPU)", file=sys.stderr)
@@ -490,34 +502,37 @@ def main(argv=None):
     b = ax.Basis(N)
     NBUF = 4
     X_host = meshgen.random_nodal(E, N, nrhs=1, seed=N)
-    Xs = [torch.from_numpy(X_host).to(dev) for _ in range(NBUF)]
+    f64 = args.prec == "fp64"
+    hprec = ax.AX_FP64 if f64 else ax.AX_FP32
+    Xs = [torch.from_numpy(X_host).to(dev).to(torch.float64 if f64 else torch.float32) for _ in range(NBUF)]
     Ys = [torch.empty_like(Xs[0]) for _ in range(NBUF)]
     V = torch.from_numpy(mesh.verts).to(dev)
     torch.cuda.synchronize()
+    PEAK = PEAK_FP64_TFS if f64 else PEAK_FP32_TFS
 
     def step(q):
-        ax.ax_local(Xs[q], V, b, ax.AX_TRILINEAR, ax.AX_FP64, out=Ys[q])
+        ax.ax_local(Xs[q], V, b, ax.AX_TRILINEAR, hprec, out=Ys[q])
 
     wall, per = time_steps(step, args.steps, args.warmup, NBUF)
     t_kernel = float(per.mean())
     dofs = E * NP
     gdofs = dofs * args.steps / wall / 1e9
     f_ax, f_geo = flops_per_element(N, "tri")
-    by = bytes_per_element(N, "tri")
+    by = bytes_per_element(N, "tri", fpsize=8 if f64 else 4)
     achieved_tf = (f_ax + f_geo) * E / t_kernel / 1e12
     achieved_gbs = by * E / t_kernel / 1e9
     # time-based roofline (Sec. 3.4): T_cmp = (F_ax + F_geo) / P, T_mem = M / B
-    t_cmp = (f_ax + f_geo) * E / (PEAK_FP64_TFS * 1e12)
+    t_cmp = (f_ax + f_geo) * E / (PEAK * 1e12)
     t_mem = by * E / (PEAK_HBM_GBS * 1e9)
     compute_bound = t_cmp >= t_mem
     roofline = {
         "bound": "alu" if compute_bound else "hbm",
         "achieved": round(achieved_tf if compute_bound else achieved_gbs, 3),
-        "peak": PEAK_FP64_TFS if compute_bound else PEAK_HBM_GBS,
+        "peak": PEAK if compute_bound else PEAK_HBM_GBS,
         "unit": "TFLOP/s" if compute_bound else "GB/s",
-        "frac": round((achieved_tf / PEAK_FP64_TFS) if compute_bound else (achieved_gbs / PEAK_HBM_GBS), 4),
-        "traffic": measured_traffic(N, E),
-        "kernel": "ax_local_kernel<N1=8, trilinear, double>",
+        "frac": round((achieved_tf / PEAK) if compute_bound else (achieved_gbs / PEAK_HBM_GBS), 4),
+        "traffic": measured_traffic(N, E, args.prec),
+        "kernel": f"ax_local_kernel<N1={N1}, trilinear, {'double' if f64 else 'float'}>",
         "per_launch": {"elements": E, "flops_per_element": f_ax + f_geo, "bytes_per_element": by,
                        "avg_launch_ms": round(t_kernel * 1e3, 4)},
         "hbm_GBs_achieved": round(achieved_gbs, 1),
@@ -525,16 +540,17 @@ def main(argv=None):
         "pct_of_R_eff": round(max(t_cmp, t_mem) / t_kernel, 4),
         "time_base": "mean HIP-event time per launch on the launch stream (value uses the wall time of "
                      "the timed steps)",
-        "frac_wall_clock": round((f_ax + f_geo) * E / (wall / args.steps) / 1e12 / PEAK_FP64_TFS, 4)
+        "frac_wall_clock": round((f_ax + f_geo) * E / (wall / args.steps) / 1e12 / PEAK, 4)
         if compute_bound else round(by * E / (wall / args.steps) / 1e9 / PEAK_HBM_GBS, 4),
     }
 
     peaks = None
     if not args.no_peaks:
         peaks = measure_peaks(ax, dev)
-        roofline["peak_measured"] = peaks["fp64_valu_fma_TFs"] if compute_bound else peaks["hbm_copy_GBs"]
+        pm = peaks["fp64_valu_fma_TFs"] if f64 else peaks["fp32_valu_fma_unpacked_TFs"]
+        roofline["peak_measured"] = pm if compute_bound else peaks["hbm_copy_GBs"]
         roofline["frac_of_measured_peak"] = round(roofline["achieved"] / roofline["peak_measured"], 4)
-        t_cmp_m = (f_ax + f_geo) * E / (peaks["fp64_valu_fma_TFs"] * 1e12)
+        t_cmp_m = (f_ax + f_geo) * E / (pm * 1e12)
         t_mem_m = by * E / (peaks["hbm_copy_GBs"] * 1e9)
         roofline["R_eff_measured_GDOFs"] = round(dofs / max(t_cmp_m, t_mem_m) / 1e9, 1)
         roofline["pct_of_R_eff_measured"] = round(max(t_cmp_m, t_mem_m) / t_kernel, 4)
@@ -550,14 +566,16 @@ def main(argv=None):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if f64 else "f32",
         "data": "synthetic",
         "config": {"workload": f"AxLocal trilinear N={N} E={grid[0]}x{grid[1]}x{grid[2]}={E} jitter 15% seed {N}",
                    "N": N, "E": E, "local_dofs": dofs, "nrhs": 1, "geometry": "trilinear",
-                   "precision": "fp64"},
+                   "precision": args.prec},
         "roofline": roofline,
     }
 
+    if args.only_cg:
+        args.no_extras = True
     if not args.no_extras:
         extras = {}
         # stored-factor baseline on the same mesh: the roofline the paper raises
@@ -657,8 +675,8 @@ def main(argv=None):
     if not args.no_extras and not args.no_sweep:
         out["order_sweep"] = order_sweep(ax, meshgen, dev, steps=20, warmup=10, peaks=peaks)
 
-    if not args.no_extras and not args.no_cg:
-        out["cg"] = cg_solves(ax, meshgen, dev, check_with_oracle=not args.no_cpu)
+    if (args.only_cg or not args.no_extras) and not args.no_cg:
+        out["cg"] = cg_solves(ax, meshgen, dev, check_with_oracle=not args.no_cpu, fp16=args.fp16_cg)
 
     if not args.no_extras and not args.no_batched:
         out["batched"] = batched_run(ax, meshgen, dev, steps=10, warmup=3, check_with_oracle=not args.no_cpu)
