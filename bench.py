@@ -196,7 +196,8 @@ def cg_solves(ax, meshgen, dev, N=7, grid=(32, 32, 32), rtol=1e-10, check_with_o
     runs = [("fp64", dict(inner_prec=ax.AX_FP64)),
             ("mixed_fp32_reliable", dict(inner_prec=ax.AX_FP32, inner_rtol=0.1, refine=ax.AX_REFINE_RELIABLE)),
             ("mixed_fp32_restart", dict(inner_prec=ax.AX_FP32, inner_rtol=1e-5)),
-            # Jacobi-preconditioned CG (Nekbone's solver, Sec. 5.6), FP64 and mixed
+            # Jacobi-preconditioned CG (a Table 5-style solve; the paper does not name the
+            # preconditioner), FP64 and mixed
             ("jacobi_fp64", dict(inner_prec=ax.AX_FP64, precond=ax.AX_PRECOND_JACOBI)),
             ("jacobi_mixed_fp32_reliable", dict(inner_prec=ax.AX_FP32, inner_rtol=0.1, refine=ax.AX_REFINE_RELIABLE,
                                                 precond=ax.AX_PRECOND_JACOBI))]

@@ -264,7 +264,8 @@ typedef struct {
  * AX_PRECOND_NONE   - plain CG;
  * AX_PRECOND_JACOBI - z = diag(A)^-1 r with the diagonal of the assembled operator (the element
  *                     diagonals of ax_local_diag, factors recomputed, assembled by Q^T; zero on
- *                     the Dirichlet nodes), the preconditioner of the Nekbone CG of Sec. 5.6.
+ *                     the Dirichlet nodes); the paper does not name the preconditioner of the
+ *                     solves of Sec. 5.6, the diagonal one is this library's reading.
  *                     The same diagonal (in float) serves the reduced-precision iterations of
  *                     the mixed-precision solves.  The convergence test stays on ||r||_2. */
 enum { AX_PRECOND_NONE = 0, AX_PRECOND_JACOBI = 1 };

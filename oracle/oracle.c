@@ -464,8 +464,8 @@ int orc_cg(int64_t E, int N, const double* D, const double* G, int64_t n_global,
 }
 
 /* Preconditioned conjugate gradients with the diagonal preconditioner M^-1 = diag(dinv) (the
- * textbook algorithm; the paper's Nekbone benchmark of Sec. 5.6 runs a Jacobi-preconditioned
- * CG).  Same stopping rule, return values and residual report as orc_cg. */
+ * textbook algorithm; the paper does not name the solver's preconditioner, the diagonal one is
+ * the reading used for the Table 5-style runs).  Same stopping rule, return values and residual report as orc_cg. */
 int orc_pcg(int64_t E, int N, const double* D, const double* G, int64_t n_global,
             const int32_t* l2g, const uint8_t* mask, const double* b, const double* dinv, double* x,
             double rtol, int max_it, double* rel_res)

@@ -208,7 +208,7 @@ def test_local_diag_vs_oracle(ax, N, geom):
 
 @pytest.mark.parametrize("N,grid", [(3, (3, 3, 3)), (5, (2, 3, 2))])
 def test_jacobi_pcg_fp64_matches_oracle(ax, N, grid):
-    """Jacobi-preconditioned CG (Nekbone's solver, Sec. 5.6) against the oracle's PCG: same
+    """Jacobi-preconditioned CG (the Table 5-style solve) against the oracle's PCG: same
     iteration count up to rounding drift, same solution, and the oracle recomputes the residual."""
     import torch
     m, prob, ref, rhs = _problem(ax, N, grid)
