@@ -194,6 +194,22 @@ int ax_geom_factors(int64_t E, int N, const double* verts, const double* xi, con
 int ax_parallelepiped_factors(int64_t E, const double* verts, double* h, void* stream);
 
 /*
+ * ax_check_mesh - set-up: reject inverted or degenerate elements.  Evaluates det J of the
+ * trilinear map (Eq. 8-9) at every GLL node of every element; the geometric factors of Eq. (7)
+ * divide by det J, so the operator is defined only where det J > 0.  verts [dev] double
+ * [E][8][3]; xi [host] double[N1] (the nodes of the order the mesh will be used with).  On
+ * return *bad_element [host] is the lowest index of an element with det J <= 0 or not finite at
+ * some node (-1 if none) and *min_det [host] the smallest finite det J over all nodes (+inf if
+ * E == 0); either pointer may be NULL.  Returns AX_ERR_ARG naming the element if one fails.
+ * Unlike the other entry points this call synchronises `stream` (it reads the result back) and
+ * allocates 16 bytes of device memory for the reduction, so it cannot be captured in a graph.
+ * Parallelepipeds are covered too (their det J is constant).  Errors: E < 0, xi or verts NULL
+ * -> AX_ERR_ARG; N outside [1,15] -> AX_ERR_UNSUPPORTED.
+ */
+int ax_check_mesh(int64_t E, int N, const double* verts, const double* xi, int64_t* bad_element,
+                  double* min_det, void* stream);
+
+/*
  * ax_node_coords - physical coordinates of every GLL node, x = sum_v sigma_v(xi_i,xi_j,xi_k) v
  * (Eq. 8).  XYZ [dev] double [E][3][N1^3].  verts [dev]; xi [host] double[N1].
  */

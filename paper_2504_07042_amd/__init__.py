@@ -15,7 +15,8 @@ import numpy as np
 from . import meshgen  # noqa: F401  (seeded synthetic inputs)
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIBPATH = os.path.join(PKG, "libaxhosfem.so")
+# AXHOSFEM_LIB selects another build of the same library (e.g. the LDS-poisoned debug twin)
+LIBPATH = os.environ.get("AXHOSFEM_LIB") or os.path.join(PKG, "libaxhosfem.so")
 
 AX_OK, AX_ERR_ARG, AX_ERR_UNSUPPORTED, AX_ERR_HIP, AX_ERR_NOMEM, AX_ERR_NOT_CONVERGED, AX_ERR_BREAKDOWN = (
     0, -1, -2, -3, -4, -5, -6)
@@ -84,6 +85,7 @@ _SIGS = {
     "ax_parallelepiped_factors": (_int, [_i64, _vp, _vp, _vp]),
     "ax_local_diag": (_int, [_i64, _int, _int, _vp, _vp, _vp, _vp, _vp, _vp]),
     "ax_node_coords": (_int, [_i64, _int, _vp, _vp, _vp, _vp]),
+    "ax_check_mesh": (_int, [_i64, _int, _vp, _vp, ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double), _vp]),
     "gs_build_csr": (_int, [_i64, _i64, _vp, _vp, _vp]),
     "gs_assemble": (_int, [_i64, _i64, _vp, _vp, _vp, _vp, _int, _int, _int, _vp, _vp, _vp]),
     "cg_workspace_bytes": (_int, [ctypes.POINTER(AxProblem), _int, ctypes.POINTER(AxCgOpts),
@@ -289,6 +291,19 @@ def local_diag(geo, basis: Basis, geom=AX_TRILINEAR, stream=None):
     _check(lib().ax_local_diag(E, basis.N, geom, _dptr(geo), _np_ptr(basis.D), _np_ptr(basis.xi),
                                _np_ptr(basis.w), _dptr(out), _stream(stream)))
     return out
+
+
+def check_mesh(verts, basis: Basis, stream=None):
+    """det J > 0 at every GLL node of every element (Eq. 8-9)?  Returns (bad_element, min_det):
+    bad_element is -1 for a valid mesh, else the lowest element with det J <= 0 (or not finite)
+    at a node; min_det is the smallest finite det J.  Other errors raise AxError."""
+    bad = _i64(-1)
+    dmin = ctypes.c_double(0.0)
+    code = lib().ax_check_mesh(verts.shape[0], basis.N, _dptr(verts), _np_ptr(basis.xi), ctypes.byref(bad),
+                               ctypes.byref(dmin), _stream(stream))
+    if code not in (AX_OK, AX_ERR_ARG) or (code == AX_ERR_ARG and bad.value < 0):
+        _check(code)
+    return bad.value, dmin.value
 
 
 def parallelepiped_factors(verts, stream=None):

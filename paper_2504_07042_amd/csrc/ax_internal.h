@@ -37,6 +37,25 @@ inline int hip_check(hipError_t e, const char* what)
     return AX_OK;
 }
 
+// Debug builds compiled with -DAX_LDS_POISON=1 fill a kernel's LDS with all-ones bytes before
+// its first use.  All-ones is a NaN in FP64, FP32 and FP16, so a read of an LDS word that no
+// thread wrote in this launch reaches the output as NaN and fails any parity check.  Every thread
+// of the block calls it, before anything else touches that LDS array.
+#ifndef AX_LDS_POISON
+#define AX_LDS_POISON 0
+#endif
+__device__ __forceinline__ void lds_poison(void* p, int bytes)
+{
+#if AX_LDS_POISON
+    unsigned* w = (unsigned*)p;
+    for (int q = (int)threadIdx.x; q < bytes / 4; q += (int)blockDim.x) w[q] = 0xffffffffu;
+    __syncthreads();
+#else
+    (void)p;
+    (void)bytes;
+#endif
+}
+
 #define AX_TRY(expr)              \
     do {                          \
         int _s = (expr);          \

@@ -89,6 +89,9 @@ ax_local_f16_kernel(int64_t E, int nrhs, const double* __restrict__ geo, const f
     __shared__ _Float16 hx[3][NP];  // X, then r, s, t (half)
     __shared__ float fb[3][NP];     // x0, x1, x2, then the accumulated output
     __shared__ double sv[24];
+    lds_poison(hx, sizeof(hx));
+    lds_poison(fb, sizeof(fb));
+    lds_poison(sv, sizeof(sv));
     const int l = threadIdx.x;
     const int i = l & 7, j = l >> 3;
 
@@ -196,8 +199,8 @@ int ax_local_f16(int64_t E, int N, int geo_kind, const double* geo, const float*
         bs.w[q] = w ? w[q] : 0.0;
     }
     int dev = 0, cus = 256;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     const int64_t cap = (int64_t)cus * 16;
     const unsigned grid = (unsigned)(E < cap ? E : cap);
     switch (geo_kind) {

@@ -177,6 +177,9 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
     // (xi_k, w_k) pairs: the per-lane (xi_i, w_i), (xi_j, w_j) of the home columns, and xi_k, w_k
     // of the node loop for the kernels that do not keep them in scalar registers
     __shared__ double sxw[2 * N1];
+    lds_poison(smem, sizeof(smem));
+    lds_poison(svert, sizeof(svert));
+    lds_poison(sxw, sizeof(sxw));
 
     const int tid = threadIdx.x;
     const int slot = (TL::SLOTS == 1) ? 0 : tid / NT;

@@ -1,5 +1,8 @@
 // Set-up kernels: stored geometric factors (Eq. 7) of trilinear elements, the constant factors h
-// of parallelepipeds (input of Algorithm 3), and physical node coordinates (Eq. 8).
+// of parallelepipeds (input of Algorithm 3), physical node coordinates (Eq. 8), element diagonals
+// and the mesh validity check (det J > 0 at every GLL node).
+#include <cstring>
+
 #include "ax_internal.h"
 #include "geom.h"
 
@@ -181,6 +184,49 @@ local_diag_kernel(int64_t E, int N1, const double* __restrict__ geo, double* __r
     out[idx] = acc;
 }
 
+// Mesh validity (Eq. 8-9): det J of the trilinear map at every GLL node of every element.  The
+// factors of Eq. (7) divide by det J, so an element with det J <= 0 at a node is inverted or
+// collapsed there and the operator is undefined.  One thread per node; each wave reduces the
+// smallest det and the lowest failing element index, and one lane per wave merges them into
+// res[0] (min element index whose det is <= 0 or not finite, ~0 if none) and res[1] (the
+// order-preserving key of the smallest finite det(8J)).
+__device__ __forceinline__ unsigned long long det_key(double d)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(d);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+__global__ void __launch_bounds__(256)
+check_mesh_kernel(int64_t E, int N1, const double* __restrict__ verts, unsigned long long* __restrict__ res,
+                  const Nodes nd)
+{
+    const int NP = N1 * N1 * N1;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double dmin = __builtin_inf();
+    unsigned long long bad = ~0ull;
+    if (idx < E * NP) {
+        const int64_t e = idx / NP;
+        const int l = (int)(idx - e * NP);
+        const int i = l % N1, j = (l / N1) % N1, k = l / (N1 * N1);
+        const double* Ve = verts + e * 24;
+        TriCoef tc;
+        tri_prelude([&](int v, int q) { return Ve[v * 3 + q]; }, nd.xi[i], nd.xi[j], 1.0, 1.0, tc);
+        const double det = tri_det(tc, nd.xi[k]);
+        if (!(det > 0.0) || !(det < __builtin_inf())) bad = (unsigned long long)e;
+        if (det == det) dmin = det;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        dmin = fmin(dmin, __shfl_xor(dmin, off));
+        const unsigned long long o = __shfl_xor(bad, off);
+        bad = o < bad ? o : bad;
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (bad != ~0ull) atomicMin(&res[0], bad);
+        atomicMin(&res[1], det_key(dmin));
+    }
+}
+
 static void fill_nodes(Nodes& nd, int N1, const double* xi, const double* w)
 {
     for (int q = 0; q < kMaxN1; ++q) {
@@ -322,4 +368,51 @@ extern "C" int ax_local_diag(int64_t E, int N, int geom, const double* geo, cons
     else
         hipLaunchKernelGGL(local_diag_kernel<false>, dim3(grid_for(n, 256)), dim3(256), 0, st, E, N1, geo, out, tb);
     return hip_check(hipGetLastError(), "ax_local_diag launch");
+}
+
+extern "C" int ax_check_mesh(int64_t E, int N, const double* verts, const double* xi, int64_t* bad_element,
+                             double* min_det, void* stream)
+{
+    clear_error();
+    if (bad_element) *bad_element = -1;
+    if (min_det) *min_det = __builtin_inf();
+    if (E < 0) return fail(AX_ERR_ARG, "E < 0");
+    if (N < 1 || N > 15) return fail(AX_ERR_UNSUPPORTED, "order N=%d outside [1,15]", N);
+    if (!xi) return fail(AX_ERR_ARG, "xi is NULL");
+    if (E == 0) return AX_OK;
+    if (!verts) return fail(AX_ERR_ARG, "verts is NULL");
+    const int N1 = N + 1;
+    const int64_t n = E * N1 * N1 * N1;
+    if (n / 256 > 0x7fffffff) return fail(AX_ERR_UNSUPPORTED, "too many nodes");
+    Nodes nd;
+    fill_nodes(nd, N1, xi, nullptr);
+    hipStream_t st = as_stream(stream);
+    unsigned long long* res = nullptr;
+    if (hipMalloc((void**)&res, 2 * sizeof(unsigned long long)) != hipSuccess)
+        return fail(AX_ERR_HIP, "ax_check_mesh: hipMalloc of 16 bytes failed");
+    unsigned long long h[2] = {~0ull, ~0ull};
+    hipError_t err = hipMemcpyAsync(res, h, sizeof(h), hipMemcpyHostToDevice, st);
+    if (err == hipSuccess) {
+        hipLaunchKernelGGL(check_mesh_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, E, N1, verts, res, nd);
+        err = hipGetLastError();
+    }
+    if (err == hipSuccess) err = hipMemcpyAsync(h, res, sizeof(h), hipMemcpyDeviceToHost, st);
+    if (err == hipSuccess) err = hipStreamSynchronize(st);
+    (void)hipFree(res);
+    if (err != hipSuccess) return hip_check(err, "ax_check_mesh");
+    // decode the smallest finite det(8J) and scale to det J (exact: a power of two)
+    double dm = __builtin_inf();
+    if (h[1] != ~0ull) {
+        const unsigned long long b = (h[1] >> 63) ? (h[1] & 0x7fffffffffffffffull) : ~h[1];
+        std::memcpy(&dm, &b, sizeof(dm));
+        dm *= 1.0 / 512.0;
+    }
+    if (min_det) *min_det = dm;
+    if (h[0] != ~0ull) {
+        if (bad_element) *bad_element = (int64_t)h[0];
+        return fail(AX_ERR_ARG, "element %lld is inverted or degenerate: det J <= 0 or not finite at a GLL node "
+                                "(smallest finite det J over the mesh %.6g)",
+                    (long long)h[0], dm);
+    }
+    return AX_OK;
 }

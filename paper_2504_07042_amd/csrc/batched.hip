@@ -218,6 +218,7 @@ order_item_kernel(const BItem* __restrict__ items, const BMesh* __restrict__ mes
                   const Basis<T>* __restrict__ bsp)
 {
     __shared__ __attribute__((aligned(16))) char lds[BShape<N1>::template lds_bytes<T>()];
+    lds_poison(lds, sizeof(lds));
     const CoefReload<T> cs{as_constant(bsp)};
     for (int64_t it = blockIdx.x; it < n; it += gridDim.x) {
         const BItem q = items[it];
@@ -305,6 +306,7 @@ __global__ void __launch_bounds__(kBBlock, (item_minw<N1, T, PL>()))
 tri_item_kernel(const ItemArgs<T> a)
 {
     __shared__ __attribute__((aligned(16))) char lds[BShape<N1>::template lds_bytes<T>()];
+    lds_poison(lds, sizeof(lds));
     const int64_t ng = (a.m.E + BShape<N1>::EPB - 1) / BShape<N1>::EPB;
     const CoefReload<T> cs = karg_coefs<T, ItemArgs<T>>();
     for (int64_t eb = blockIdx.x; eb < ng; eb += gridDim.x)

@@ -208,3 +208,21 @@ def test_probe_validation(ax):
     assert L.ax_probe_compute(0, 0, ctypes.c_void_p(16), ctypes.byref(fl), None) == ax.AX_ERR_ARG
     assert L.ax_probe_compute(0, 10, None, ctypes.byref(fl), None) == ax.AX_ERR_ARG
     assert L.ax_probe_compute(0, 10, ctypes.c_void_p(16), None, None) == ax.AX_ERR_ARG
+
+
+def test_check_mesh_validation(ax):
+    L = ax.lib()
+    b = ax.Basis(3)
+    bad = ctypes.c_int64(5)
+    dmin = ctypes.c_double(0.0)
+    xi = ax._np_ptr(b.xi)
+    assert L.ax_check_mesh(-1, 3, ctypes.c_void_p(8), xi, None, None, None) == ax.AX_ERR_ARG
+    assert L.ax_check_mesh(4, 0, ctypes.c_void_p(8), xi, None, None, None) == ax.AX_ERR_UNSUPPORTED
+    assert L.ax_check_mesh(4, 16, ctypes.c_void_p(8), xi, None, None, None) == ax.AX_ERR_UNSUPPORTED
+    assert L.ax_check_mesh(4, 3, ctypes.c_void_p(8), None, None, None, None) == ax.AX_ERR_ARG
+    assert L.ax_check_mesh(4, 3, None, xi, ctypes.byref(bad), ctypes.byref(dmin), None) == ax.AX_ERR_ARG
+    assert bad.value == -1 and dmin.value == float("inf")
+    # an empty mesh is valid and touches no device
+    bad.value = 5
+    assert L.ax_check_mesh(0, 3, None, xi, ctypes.byref(bad), ctypes.byref(dmin), None) == ax.AX_OK
+    assert bad.value == -1 and dmin.value == float("inf")
