@@ -388,9 +388,13 @@ def batched_run(ax, meshgen, dev, nrhs=8, steps=5, warmup=2, check_with_oracle=T
                 ax.ax_local(x, v, b, ax.AX_TRILINEAR, prec, out=y)
 
         wall_l, per_l = time_steps(per_mesh, steps, warmup, 1)
+        from paper_2504_07042_amd import item_shape_of
+        shapes = {f"N={N1 - 1}": item_shape_of(N1, bat.plan.order_variant[N1])
+                  for N1 in range(2, 11) if bat.plan.order_count[N1] > 0}
         res[pname] = {"batched_graph_GDOFs": round(dofs / per_b.mean() / 1e9, 1),
                       "per_mesh_launches_GDOFs": round(dofs / per_l.mean() / 1e9, 1),
-                      "batched_ms": round(per_b.mean() * 1e3, 3), "per_mesh_ms": round(per_l.mean() * 1e3, 3)}
+                      "batched_ms": round(per_b.mean() * 1e3, 3), "per_mesh_ms": round(per_l.mean() * 1e3, 3),
+                      "work_group_shapes": shapes}
         if Yb is not None:
             import oracle
             worst = 0.0
@@ -487,6 +491,7 @@ def main(argv=None):
 
     import torch
     import paper_2504_07042_amd as ax
+    from paper_2504_07042_amd import autotune
     from paper_2504_07042_amd import meshgen
 
     if not torch.cuda.is_available():
@@ -571,7 +576,9 @@ def main(argv=None):
         "data": "synthetic",
         "config": {"workload": f"AxLocal trilinear N={N} E={grid[0]}x{grid[1]}x{grid[2]}={E} jitter 15% seed {N}",
                    "N": N, "E": E, "local_dofs": dofs, "nrhs": 1, "geometry": "trilinear",
-                   "precision": args.prec},
+                   "precision": args.prec, "tuning_cache": autotune.cache_status(),
+                   "launch": {k: v for k, v in autotune.tune_get(N, ax.AX_TUNE_TRILINEAR, hprec).items()
+                              if k in ("kernel_used", "elems_per_group", "block", "waves", "grid_mult")}},
         "roofline": roofline,
     }
 

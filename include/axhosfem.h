@@ -96,17 +96,51 @@ int ax_local_vector(int64_t E, int N, int geom, const double* geo, const double*
                     const double* w, int prec, const void* X, void* Y, void* stream);
 
 /*
- * ax_tune_set / ax_tune_get - [host] launch tuning of the AxLocal kernels for one
- * (order N, geometry kind, precision): geom_kind AX_TRILINEAR, AX_PARALLELEPIPED or
- * AX_STORED_G (ax_local_precomputedG); prec AX_FP64 or AX_FP32.  epb_alt 0 selects the default
- * elements per work-group, 1 the alternative shape (see elems_per_group); grid_mult sets the
- * persistent grid to grid_mult times the resident work-group capacity (1..64).  The setting is
- * process-wide and applies to launches enqueued after the call; results do not depend on it.
- * Written by the autotuner from its cache (paper_2504_07042_amd/autotune.py).
+ * ax_tune_set / ax_tune_get - [host] the launch variants of the AxLocal kernels, one entry per
+ * (order N, tuning kind, precision AX_FP64 or AX_FP32).  Kinds: AX_TUNE_TRILINEAR (ax_local on
+ * trilinear elements, also ax_local_vector and the CG operators), AX_TUNE_PARALLELEPIPED,
+ * AX_TUNE_STORED (ax_local_precomputedG), AX_TUNE_PARTIAL (ax_local_partial),
+ * AX_TUNE_HELMHOLTZ (ax_local_helmholtz) and AX_TUNE_BATCHED (the per-order kernels of the
+ * batched launches; N <= 9).  Every variant computes the same result; only the speed differs.
+ * Fields of ax_tune:
+ *   kernel     AX_KERNEL_AUTO (the measured default), AX_KERNEL_TILE (the prefetching kernel:
+ *              several elements per work-group, next element's input loaded during the current
+ *              one) or AX_KERNEL_ITEM (the per-item kernel: element groups handed out one at a
+ *              time, tables reloaded per output row); ITEM exists for the trilinear full form
+ *              (every order) and the partial form (N >= 8) on GLL bases: elsewhere the tile
+ *              kernel runs.  Ignored for AX_TUNE_BATCHED (always per-item).
+ *   tile_alt   tile kernel: 0 default elements per work-group, 1 the alternative shape;
+ *   item_alt   per-item kernels (single-mesh and batched): 0 a 256-lane work-group, 1 the
+ *              order's alternative shape (N <= 12; see elems_per_group and block);
+ *   waves_alt  single-mesh per-item kernel: 0 the default register budget, 1 the alternative
+ *              (one wave per SIMD more where the default is two, one fewer where it is five);
+ *   grid_mult  persistent grid = grid_mult x the resident work-group capacity, 1..64.
+ * ax_tune_get also fills the read-only fields: kernel_used (what AUTO resolves to for this
+ * entry: AX_KERNEL_TILE or AX_KERNEL_ITEM), elems_per_group and block (the work-group shape that
+ * will run) and waves (the waves per SIMD its register budget targets).  The table is
+ * process-wide and applies to launches enqueued after the call; a batched work list keeps the
+ * shape it was prepared with.  Written by the autotuner from its cache
+ * (paper_2504_07042_amd/autotune.py).  Errors: N outside [1,15] -> AX_ERR_UNSUPPORTED; unknown
+ * kind, precision or field value, or AX_TUNE_BATCHED with N > 9 -> AX_ERR_ARG.
  */
 enum { AX_STORED_G = 2 };
-int ax_tune_set(int N, int geom_kind, int prec, int epb_alt, int grid_mult);
-int ax_tune_get(int N, int geom_kind, int prec, int* epb_alt, int* grid_mult, int* elems_per_group);
+enum { AX_TUNE_TRILINEAR = 0, AX_TUNE_PARALLELEPIPED = 1, AX_TUNE_STORED = 2, AX_TUNE_PARTIAL = 3,
+       AX_TUNE_HELMHOLTZ = 4, AX_TUNE_BATCHED = 5 };
+enum { AX_KERNEL_AUTO = 0, AX_KERNEL_TILE = 1, AX_KERNEL_ITEM = 2 };
+typedef struct {
+    int kernel;
+    int tile_alt;
+    int item_alt;
+    int waves_alt;
+    int grid_mult;
+    /* filled by ax_tune_get, ignored by ax_tune_set */
+    int kernel_used;
+    int elems_per_group;
+    int block;
+    int waves;
+} ax_tune;
+int ax_tune_set(int N, int kind, int prec, const ax_tune* t);
+int ax_tune_get(int N, int kind, int prec, ax_tune* t);
 
 /*
  * ax_local_precomputedG - the same operator with the six factors streamed from memory, the
@@ -354,6 +388,7 @@ typedef struct {
     int pad;
     int64_t order_first[11];  /* items of order N1 = N + 1 (2..10): [order_first[N1], +order_count[N1]) */
     int64_t order_count[11];
+    int order_variant[11];    /* work-group shape of order N1 (ax_tune.item_alt at prepare time) */
 } ax_batch_plan;
 
 int ax_batched_workspace_bytes(int n_mesh, const ax_problem* meshes, size_t* bytes);

@@ -25,6 +25,9 @@ AX_FP64, AX_FP32, AX_FP16_ACC32 = 0, 1, 2
 AX_REFINE_RESTART, AX_REFINE_RELIABLE = 0, 1
 AX_PRECOND_NONE, AX_PRECOND_JACOBI = 0, 1
 AX_PROBE_FMA_F64, AX_PROBE_FMA_F32, AX_PROBE_MFMA_F64, AX_PROBE_MFMA_F32, AX_PROBE_MIX_F64 = 0, 1, 2, 3, 4
+(AX_TUNE_TRILINEAR, AX_TUNE_PARALLELEPIPED, AX_TUNE_STORED, AX_TUNE_PARTIAL, AX_TUNE_HELMHOLTZ,
+ AX_TUNE_BATCHED) = 0, 1, 2, 3, 4, 5
+AX_KERNEL_AUTO, AX_KERNEL_TILE, AX_KERNEL_ITEM = 0, 1, 2
 GS_QT, GS_Q, GS_QQT = 0, 1, 2
 
 _STATUS = {0: "AX_OK", -1: "AX_ERR_ARG", -2: "AX_ERR_UNSUPPORTED", -3: "AX_ERR_HIP",
@@ -57,7 +60,14 @@ class AxCgOpts(ctypes.Structure):
 
 class AxBatchPlan(ctypes.Structure):
     _fields_ = [("n_items", _i64), ("nrhs", _int), ("prec", _int), ("bytes", ctypes.c_size_t),
-                ("n_mesh", _int), ("pad", _int), ("order_first", _i64 * 11), ("order_count", _i64 * 11)]
+                ("n_mesh", _int), ("pad", _int), ("order_first", _i64 * 11), ("order_count", _i64 * 11),
+                ("order_variant", _int * 11)]
+
+
+class AxTune(ctypes.Structure):
+    _fields_ = [("kernel", _int), ("tile_alt", _int), ("item_alt", _int), ("waves_alt", _int),
+                ("grid_mult", _int), ("kernel_used", _int), ("elems_per_group", _int), ("block", _int),
+                ("waves", _int)]
 
 
 class AxCgReport(ctypes.Structure):
@@ -72,8 +82,8 @@ _SIGS = {
     "ax_last_error": (ctypes.c_char_p, []),
     "ax_version": (ctypes.c_char_p, []),
     "ax_gll": (_int, [_int, _vp, _vp, _vp]),
-    "ax_tune_set": (_int, [_int, _int, _int, _int, _int]),
-    "ax_tune_get": (_int, [_int, _int, _int, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_int)]),
+    "ax_tune_set": (_int, [_int, _int, _int, ctypes.POINTER(AxTune)]),
+    "ax_tune_get": (_int, [_int, _int, _int, ctypes.POINTER(AxTune)]),
     "ax_local": (_int, [_i64, _int, _int, _vp, _vp, _vp, _vp, _int, _int, _vp, _vp, _vp]),
     "ax_local_precomputedG": (_int, [_i64, _int, _vp, _vp, _int, _int, _vp, _vp, _vp]),
     "ax_local_vector": (_int, [_i64, _int, _int, _vp, _vp, _vp, _vp, _int, _vp, _vp, _vp]),
@@ -443,6 +453,21 @@ class BatchedAxLocal:
 
     def launch(self, stream=None):
         _check(lib().ax_local_batched(ctypes.byref(self.plan), _dptr(self.ws), _stream(stream)))
+
+
+def item_shape_of(N1: int, variant: int) -> dict:
+    """Work-group shape of the per-item kernels of order N1 - 1 in a shape variant (0 or 1)."""
+    t = AxTune(kernel=AX_KERNEL_ITEM, item_alt=int(variant), grid_mult=2)
+    saved = AxTune()
+    L = lib()
+    kind = AX_TUNE_BATCHED if N1 <= 10 else AX_TUNE_TRILINEAR
+    _check(L.ax_tune_get(N1 - 1, kind, AX_FP64, ctypes.byref(saved)))
+    try:
+        _check(L.ax_tune_set(N1 - 1, kind, AX_FP64, ctypes.byref(t)))
+        _check(L.ax_tune_get(N1 - 1, kind, AX_FP64, ctypes.byref(t)))
+    finally:
+        _check(L.ax_tune_set(N1 - 1, kind, AX_FP64, ctypes.byref(saved)))
+    return {"elems_per_group": t.elems_per_group, "block": t.block}
 
 
 def probe_copy(src, dst, stream=None):

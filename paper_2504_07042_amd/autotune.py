@@ -1,135 +1,259 @@
-"""Autotuner for the AxLocal launch shape on gfx950.
+"""Autotuner for the AxLocal launch variants on gfx950.
 
-For each (order N, geometry kind, precision) it times the kernel with the default and the
-alternative elements-per-work-group shape and several persistent grid sizes on a synthetic mesh
-of about 2^22 local nodes, keeps the fastest, and writes a JSON cache.  ``load()`` pushes a
-cache into the library (``ax_tune_set``); the package calls it on import when the cache for this
-architecture exists.  Tuning never changes results, only the launch shape.
+For each (order N, tuning kind, precision) it times every launch variant the library can select
+at run time (``ax_tune_set``):
+
+* the kernel: the prefetching tile kernel or the per-item kernel (where the form has one);
+* the tile kernel's elements per work-group (default or alternative shape);
+* the per-item kernels' work-group shape (256 lanes or the order's alternative) and, for the
+  single-mesh per-item kernel, its register budget (default or alternative waves per SIMD);
+* the persistent grid (1, 2, 4 or 8 times the resident work-group capacity);
+
+on a synthetic mesh of about 2^24 local nodes (two rotating X/Y pairs, so that the vectors do not
+stay in the 256 MB Infinity Cache), keeps the fastest when it beats the default by more than the
+noise margin, and writes a JSON cache stamped with the SHA-256 of the kernel sources it was
+measured on.  ``load()`` pushes a cache into the library; the package calls it on import.  Every
+variant gives the same result up to rounding (bitwise the same for one kernel).
 
     python -m paper_2504_07042_amd.autotune            # tune everything, write the cache
-    python -m paper_2504_07042_amd.autotune --N 7      # one order
+    python -m paper_2504_07042_amd.autotune --N 7      # some orders only (merged into the cache)
 """
 from __future__ import annotations
 
 import argparse
 import ctypes
+import hashlib
+import itertools
 import json
 import os
 import time
 
-import numpy as np
+from . import (AX_FP32, AX_FP64, AX_KERNEL_AUTO, AX_KERNEL_ITEM, AX_KERNEL_TILE, AX_PARALLELEPIPED,
+               AX_TRILINEAR, AX_TUNE_BATCHED, AX_TUNE_HELMHOLTZ, AX_TUNE_PARALLELEPIPED, AX_TUNE_PARTIAL,
+               AX_TUNE_STORED, AX_TUNE_TRILINEAR, AxTune, Basis, _check, lib)
 
-from . import AX_FP32, AX_FP64, AX_PARALLELEPIPED, AX_STORED_G, AX_TRILINEAR, Basis, _check, lib
-
-CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_gfx950.json")
-GEOMS = {"trilinear": AX_TRILINEAR, "parallelepiped": AX_PARALLELEPIPED, "stored": AX_STORED_G}
+PKG = os.path.dirname(os.path.abspath(__file__))
+CACHE = os.path.join(PKG, "tuning_gfx950.json")
+KINDS = {"trilinear": AX_TUNE_TRILINEAR, "parallelepiped": AX_TUNE_PARALLELEPIPED, "stored": AX_TUNE_STORED,
+         "partial": AX_TUNE_PARTIAL, "helmholtz": AX_TUNE_HELMHOLTZ, "batched": AX_TUNE_BATCHED}
 PRECS = {"fp64": AX_FP64, "fp32": AX_FP32}
+KNOBS = ("kernel", "tile_alt", "item_alt", "waves_alt", "grid_mult")
+DEFAULT = {"kernel": AX_KERNEL_AUTO, "tile_alt": 0, "item_alt": 0, "waves_alt": 0, "grid_mult": 2}
 GRID_MULTS = (1, 2, 4, 8)
+MARGIN = 0.01      # a variant replaces the default only if it is this much faster
 
 
-def tune_get(N: int, geom: int, prec: int):
-    a, g, e = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-    _check(lib().ax_tune_get(N, geom, prec, ctypes.byref(a), ctypes.byref(g), ctypes.byref(e)))
-    return {"epb_alt": a.value, "grid_mult": g.value, "elems_per_group": e.value}
+def source_hash() -> str:
+    """SHA-256 over the library's kernel sources and public header (what the timings depend on)."""
+    h = hashlib.sha256()
+    csrc = os.path.join(PKG, "csrc")
+    files = sorted(f for f in os.listdir(csrc) if f.endswith((".hip", ".h", ".cpp")))
+    for f in files:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    with open(os.path.join(os.path.dirname(PKG), "include", "axhosfem.h"), "rb") as fh:
+        h.update(b"axhosfem.h\0" + fh.read())
+    return h.hexdigest()
 
 
-def tune_set(N: int, geom: int, prec: int, epb_alt: int, grid_mult: int):
-    _check(lib().ax_tune_set(N, geom, prec, int(epb_alt), int(grid_mult)))
+def tune_get(N: int, kind: int, prec: int) -> dict:
+    t = AxTune()
+    _check(lib().ax_tune_get(N, kind, prec, ctypes.byref(t)))
+    return {f: getattr(t, f) for f, _ in AxTune._fields_}
+
+
+def tune_set(N: int, kind: int, prec: int, **knobs):
+    """Set some knobs of one entry (the others keep their current values)."""
+    cur = tune_get(N, kind, prec)
+    cur.update(knobs)
+    t = AxTune(**{k: int(cur[k]) for k in KNOBS})
+    _check(lib().ax_tune_set(N, kind, prec, ctypes.byref(t)))
+
+
+def cache_status(path: str = CACHE) -> str:
+    """'current' (stamped with the present sources), 'stale' or 'absent'."""
+    if not os.path.exists(path):
+        return "absent"
+    with open(path) as f:
+        data = json.load(f)
+    return "current" if data.get("sources_sha256") == source_hash() else "stale"
 
 
 def load(path: str = CACHE) -> int:
-    """Apply a tuning cache; returns the number of entries applied (0 if there is none)."""
+    """Apply a tuning cache; returns the number of entries applied (0 if there is none).  A stale
+    cache is applied too: every variant it names is valid, only possibly no longer the fastest."""
     if not os.path.exists(path):
         return 0
     with open(path) as f:
         data = json.load(f)
     n = 0
     for ent in data.get("entries", []):
-        tune_set(ent["N"], GEOMS[ent["geom"]], PRECS[ent["prec"]], ent["epb_alt"], ent["grid_mult"])
-        n += 1
+        if ent.get("kind") not in KINDS or ent.get("prec") not in PRECS:
+            continue
+        try:
+            tune_set(ent["N"], KINDS[ent["kind"]], PRECS[ent["prec"]], **{k: ent[k] for k in KNOBS if k in ent})
+            n += 1
+        except Exception:   # an entry of an older format: keep the default
+            pass
     return n
 
 
-def _time(fn, reps=20, warmup=3):
-    import torch
-    for _ in range(warmup):
-        fn()
-    torch.cuda.synchronize()
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record()
-    for _ in range(reps):
-        fn()
-    b.record()
-    torch.cuda.synchronize()
-    return a.elapsed_time(b) * 1e-3 / reps
+def _variants(N: int, kind: int, prec: int):
+    """Every distinct launch variant of one entry (as knob dicts, without the grid)."""
+    saved = tune_get(N, kind, prec)
+    out, seen = [], set()
+    try:
+        kernels = (AX_KERNEL_ITEM,) if kind == AX_TUNE_BATCHED else (AX_KERNEL_TILE, AX_KERNEL_ITEM)
+        for kern, ta, ia, wa in itertools.product(kernels, (0, 1), (0, 1), (0, 1)):
+            tune_set(N, kind, prec, kernel=kern, tile_alt=ta, item_alt=ia, waves_alt=wa)
+            r = tune_get(N, kind, prec)
+            if r["kernel_used"] != kern:
+                continue
+            key = (r["kernel_used"], r["elems_per_group"], r["block"], r["waves"])
+            if key in seen:
+                continue
+            seen.add(key)
+            out.append({"kernel": kern, "tile_alt": ta, "item_alt": ia, "waves_alt": wa})
+    finally:
+        tune_set(N, kind, prec, **{k: saved[k] for k in KNOBS})
+    return out
 
 
-def tune(orders=range(1, 16), geoms=tuple(GEOMS), precs=tuple(PRECS), target_nodes=1 << 22, verbose=True):
+def _time_configs(fns, configs, apply, rounds=3, reps=8, warmup=2):
+    """Interleaved timing: each round times every config; the best round per config counts."""
     import torch
-    from . import ax_local, ax_local_precomputedG, geom_factors, meshgen, parallelepiped_factors
+    best = [float("inf")] * len(configs)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    for _ in range(rounds):
+        for q, cfg in enumerate(configs):
+            apply(cfg)
+            for w in range(warmup):
+                fns[w % len(fns)]()
+            ev[0].record()
+            for r in range(reps):
+                fns[r % len(fns)]()
+            ev[1].record()
+            ev[1].synchronize()
+            best[q] = min(best[q], ev[0].elapsed_time(ev[1]) * 1e-3 / reps)
+    return best
+
+
+def _workloads(N, prec, target_nodes, kinds):
+    """Launch closures per tuning kind on two rotating X/Y pairs of about target_nodes nodes."""
+    import torch
+
+    from . import (BatchedAxLocal, ax_local, ax_local_helmholtz, ax_local_partial, ax_local_precomputedG,
+                   geom_factors, geom_lambda, helmholtz_factors, meshgen, parallelepiped_factors)
+    b = Basis(N)
+    NP = (N + 1) ** 3
+    grid = meshgen.grid_for_nodes(N, target_nodes)
+    m = meshgen.jittered_hex(*grid, alpha=0.15, seed=N)
+    V = torch.from_numpy(m.verts).cuda()
+    dt = torch.float64 if prec == AX_FP64 else torch.float32
+    Xs = [meshgen.random_nodal_device(m.E, N, seed=N + q, dtype=dt) for q in range(2)]
+    Ys = [torch.empty_like(x) for x in Xs]
+    work = {}
+    if "trilinear" in kinds:
+        work["trilinear"] = [lambda q=q: ax_local(Xs[q], V, b, AX_TRILINEAR, prec, out=Ys[q]) for q in range(2)]
+    if "parallelepiped" in kinds:
+        pm, _ = meshgen.parallelepiped_hex(*grid, seed=2)
+        h = parallelepiped_factors(torch.from_numpy(pm.verts).cuda())
+        work["parallelepiped"] = [lambda q=q: ax_local(Xs[q], h, b, AX_PARALLELEPIPED, prec, out=Ys[q])
+                                  for q in range(2)]
+    if "stored" in kinds:
+        G, _ = geom_factors(V, b, prec)
+        work["stored"] = [lambda q=q: ax_local_precomputedG(Xs[q], G, b, prec, out=Ys[q]) for q in range(2)]
+    if "partial" in kinds:
+        lam = geom_lambda(V, b, prec)
+        work["partial"] = [lambda q=q: ax_local_partial(Xs[q], V, lam, b, prec, out=Ys[q]) for q in range(2)]
+    if "helmholtz" in kinds:
+        l0 = torch.ones((m.E, NP), dtype=torch.float64, device="cuda")
+        l1 = torch.full((m.E, NP), 0.5, dtype=torch.float64, device="cuda")
+        L23 = helmholtz_factors(V, l0, l1, b, prec)
+        del l0, l1
+        work["helmholtz"] = [lambda q=q: ax_local_helmholtz(Xs[q], V, L23, b, prec, out=Ys[q]) for q in range(2)]
+    if "batched" in kinds and N <= 9:
+        # eight meshes of this order of uneven size (the batched kernels' work lists)
+        sizes = [max(1, m.E * f // 36) for f in (8, 7, 6, 5, 4, 3, 2, 1)]
+        meshes, off = [], 0
+        for s in sizes:
+            meshes.append((V[off:off + s], b))
+            off += s
+        views = [[x[:, a:a + s] for a, s in zip(itertools.accumulate([0] + sizes[:-1]), sizes)] for x in Xs]
+        outs = [[y[:, a:a + s] for a, s in zip(itertools.accumulate([0] + sizes[:-1]), sizes)] for y in Ys]
+        work["batched"] = (meshes, views, outs)
+    return m.E * NP, work
+
+
+def tune(orders=range(1, 16), kinds=tuple(KINDS), precs=tuple(PRECS), target_nodes=1 << 24, verbose=True):
+    import torch
+
+    from . import BatchedAxLocal
     entries = []
     for N in orders:
-        b = Basis(N)
-        grid = meshgen.grid_for_nodes(N, target_nodes)
-        m = meshgen.jittered_hex(*grid, alpha=0.15, seed=N)
-        pm, _ = meshgen.parallelepiped_hex(*grid, seed=2)
-        V = torch.from_numpy(m.verts).cuda()
-        h = parallelepiped_factors(torch.from_numpy(pm.verts).cuda())
-        X64 = torch.from_numpy(meshgen.random_nodal(m.E, N, seed=N)).cuda()
         for pname in precs:
             prec = PRECS[pname]
-            X = X64 if prec == AX_FP64 else X64.float()
-            Y = torch.empty_like(X)
-            G = None
-            for gname in geoms:
-                geom = GEOMS[gname]
-                if geom == AX_STORED_G:
-                    G, _ = geom_factors(V, b, prec)
-                    fn = lambda: ax_local_precomputedG(X, G, b, prec, out=Y)
-                elif geom == AX_TRILINEAR:
-                    fn = lambda: ax_local(X, V, b, AX_TRILINEAR, prec, out=Y)
+            ndof, work = _workloads(N, prec, target_nodes, kinds)
+            for kname in kinds:
+                if kname not in work:
+                    continue
+                kind = KINDS[kname]
+                variants = _variants(N, kind, prec)
+                configs = [dict(v, grid_mult=g) for v in variants for g in GRID_MULTS]
+                configs.insert(0, dict(DEFAULT))
+                if kname == "batched":
+                    meshes, views, outs = work["batched"]
+                    plans = {}
+
+                    def fn_for(cfg):
+                        key = cfg["item_alt"]
+                        if key not in plans:
+                            tune_set(N, kind, prec, item_alt=key)
+                            plans[key] = [BatchedAxLocal(meshes, list(views[q]), list(outs[q]), prec)
+                                          for q in range(2)]
+                        return [p.launch for p in plans[key]]
+                    times = []
+                    for cfg in configs:
+                        fns = fn_for(cfg)
+                        times.append(_time_configs(fns, [cfg], lambda c: tune_set(N, kind, prec, **c))[0])
+                    del plans
                 else:
-                    fn = lambda: ax_local(X, h, b, AX_PARALLELEPIPED, prec, out=Y)
-                best = None
-                alts = (0, 1) if tune_get(N, geom, prec)["elems_per_group"] != _elems(N, geom, prec, 1) else (0,)
-                for alt in alts:
-                    for gm in GRID_MULTS:
-                        tune_set(N, geom, prec, alt, gm)
-                        t = _time(fn)
-                        if best is None or t < best[0]:
-                            best = (t, alt, gm)
-                tune_set(N, geom, prec, best[1], best[2])
-                ent = {"N": N, "geom": gname, "prec": pname, "epb_alt": best[1], "grid_mult": best[2],
-                       "elems_per_group": tune_get(N, geom, prec)["elems_per_group"],
-                       "GDOFs": round(m.E * (N + 1) ** 3 / best[0] / 1e9, 2)}
+                    times = _time_configs(work[kname], configs, lambda c: tune_set(N, kind, prec, **c))
+                t_def = times[0]
+                q = min(range(len(configs)), key=lambda i: times[i])
+                chosen = configs[q] if times[q] < (1.0 - MARGIN) * t_def else configs[0]
+                t_best = times[q] if chosen is configs[q] else t_def
+                tune_set(N, kind, prec, **chosen)
+                info = tune_get(N, kind, prec)
+                ent = {"N": N, "kind": kname, "prec": pname, **{k: info[k] for k in KNOBS},
+                       "kernel_used": info["kernel_used"], "elems_per_group": info["elems_per_group"],
+                       "block": info["block"], "waves": info["waves"], "variants_timed": len(configs),
+                       "GDOFs": round(ndof / t_best / 1e9, 2), "GDOFs_default": round(ndof / t_def / 1e9, 2)}
                 entries.append(ent)
                 if verbose:
                     print(json.dumps(ent), flush=True)
-                del fn
-            del G
-    return {"arch": "gfx950", "target_nodes": target_nodes, "created": time.strftime("%Y-%m-%d"),
-            "entries": entries}
-
-
-def _elems(N, geom, prec, alt):
-    cur = tune_get(N, geom, prec)
-    tune_set(N, geom, prec, alt, cur["grid_mult"])
-    e = tune_get(N, geom, prec)["elems_per_group"]
-    tune_set(N, geom, prec, cur["epb_alt"], cur["grid_mult"])
-    return e
+            del work
+            torch.cuda.empty_cache()
+    return {"arch": "gfx950", "sources_sha256": source_hash(), "target_nodes": target_nodes,
+            "created": time.strftime("%Y-%m-%d"), "margin": MARGIN, "entries": entries}
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--N", type=int, nargs="*", default=None)
+    ap.add_argument("--kinds", nargs="*", default=list(KINDS), choices=list(KINDS))
+    ap.add_argument("--prec", nargs="*", default=list(PRECS), choices=list(PRECS))
     ap.add_argument("--out", default=CACHE)
     args = ap.parse_args(argv)
-    res = tune(orders=args.N or range(1, 16))
-    if os.path.exists(args.out) and args.N:
+    res = tune(orders=args.N or range(1, 16), kinds=tuple(args.kinds), precs=tuple(args.prec))
+    if os.path.exists(args.out) and (args.N or len(args.kinds) < len(KINDS) or len(args.prec) < len(PRECS)):
         with open(args.out) as f:
             old = json.load(f)
-        keep = [e for e in old.get("entries", []) if e["N"] not in set(args.N)]
-        res["entries"] = sorted(keep + res["entries"], key=lambda e: (e["N"], e["geom"], e["prec"]))
+        new_keys = {(e["N"], e["kind"], e["prec"]) for e in res["entries"]}
+        keep = [e for e in old.get("entries", []) if "kind" in e and (e["N"], e["kind"], e["prec"]) not in new_keys]
+        res["entries"] = sorted(keep + res["entries"], key=lambda e: (e["N"], e["kind"], e["prec"]))
+        if old.get("sources_sha256") != res["sources_sha256"] and keep:
+            res["sources_sha256_note"] = "entries not re-timed in this run were measured on other sources"
     with open(args.out, "w") as f:
         json.dump(res, f, indent=1)
     print(f"wrote {args.out} ({len(res['entries'])} entries)")

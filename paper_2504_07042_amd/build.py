@@ -30,9 +30,10 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall",
          "-I", os.path.join(ROOT, "include")]
 
 SOURCES = ["ax_common.cpp", "ax_local.hip", "ax_local_f64.hip", "ax_local_f32.hip", "ax_local_f16.hip",
-           "ax_setup.hip", "gs.hip", "cg.hip", "batched.hip", "probe.hip"]
+           "item_f64.hip", "item_f32.hip", "ax_setup.hip", "gs.hip", "cg.hip", "batched.hip", "probe.hip"]
 # sources whose kernels hold LDS arrays: recompiled for the poisoned debug twin
-LDS_SOURCES = ["ax_local_f64.hip", "ax_local_f32.hip", "ax_local_f16.hip", "batched.hip"]
+LDS_SOURCES = ["ax_local_f64.hip", "ax_local_f32.hip", "ax_local_f16.hip", "item_f64.hip", "item_f32.hip",
+               "batched.hip"]
 
 
 def _compile(job) -> str:

@@ -1,6 +1,7 @@
 // Error reporting, version and the GLL tables of the library (host code).
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "ax_internal.h"
 #include "ax_kernels.h"
@@ -41,26 +42,27 @@ static void legendre(int n, double x, double& L, double& dL)
 }
 
 // Process-wide launch tuning table (filled by ax_tune_set, e.g. from the autotuner's cache).
-static TuneEntry g_tune[kMaxN1 + 1][3][2];
-static bool g_tune_init = false;
+constexpr TuneEntry kTuneDefault{AX_KERNEL_AUTO, 0, 0, 0, 2};
+static TuneEntry g_tune[kMaxN1 + 1][TUNE_KINDS][2];
+static std::once_flag g_tune_once;
 
 static void tune_init()
 {
-    if (g_tune_init) return;
-    for (auto& a : g_tune)
-        for (auto& b : a)
-            for (auto& c : b) c = TuneEntry{0, 2};
-    g_tune_init = true;
+    std::call_once(g_tune_once, [] {
+        for (auto& a : g_tune)
+            for (auto& b : a)
+                for (auto& c : b) c = kTuneDefault;
+    });
 }
 
-TuneEntry tune_get(int N1, int geo_kind, int prec)
+TuneEntry tune_get(int N1, int kind, int prec)
 {
     tune_init();
-    if (N1 < 2 || N1 > kMaxN1 || geo_kind < 0 || geo_kind > 2 || prec < 0 || prec > 1) return TuneEntry{0, 2};
-    return g_tune[N1][geo_kind][prec];
+    if (N1 < 2 || N1 > kMaxN1 || kind < 0 || kind >= TUNE_KINDS || prec < 0 || prec > 1) return kTuneDefault;
+    return g_tune[N1][kind][prec];
 }
 
-static int epb_of(int N1, bool alt)
+static int tile_epb(int N1, bool alt)
 {
     switch (N1) {
 #define AX_E(n) \
@@ -72,33 +74,58 @@ static int epb_of(int N1, bool alt)
     }
 }
 
+static int tune_check(int N, int kind, int prec)
+{
+    if (N < 1 || N > 15) return fail(AX_ERR_UNSUPPORTED, "order N=%d outside [1,15]", N);
+    if (kind < 0 || kind >= TUNE_KINDS) return fail(AX_ERR_ARG, "tuning kind %d", kind);
+    if (kind == TUNE_BATCHED && N > 9) return fail(AX_ERR_ARG, "batched launches take N <= 9");
+    if (prec != AX_FP64 && prec != AX_FP32) return fail(AX_ERR_ARG, "precision %d (FP64 or FP32)", prec);
+    return AX_OK;
+}
+
 }  // namespace ax
 
 using namespace ax;
 
-extern "C" int ax_tune_set(int N, int geom_kind, int prec, int epb_alt, int grid_mult)
+extern "C" int ax_tune_set(int N, int kind, int prec, const ax_tune* t)
 {
     clear_error();
-    if (N < 1 || N > 15) return fail(AX_ERR_UNSUPPORTED, "order N=%d outside [1,15]", N);
-    if (geom_kind < 0 || geom_kind > 2) return fail(AX_ERR_ARG, "geometry kind %d", geom_kind);
-    if (prec != AX_FP64 && prec != AX_FP32) return fail(AX_ERR_ARG, "precision %d (FP64 or FP32)", prec);
-    if ((epb_alt != 0 && epb_alt != 1) || grid_mult < 1 || grid_mult > 64)
-        return fail(AX_ERR_ARG, "epb_alt must be 0/1 and grid_mult in [1,64]");
+    AX_TRY(tune_check(N, kind, prec));
+    if (!t) return fail(AX_ERR_ARG, "t is NULL");
+    if (t->kernel < AX_KERNEL_AUTO || t->kernel > AX_KERNEL_ITEM) return fail(AX_ERR_ARG, "kernel %d", t->kernel);
+    if ((t->tile_alt | t->item_alt | t->waves_alt) & ~1)
+        return fail(AX_ERR_ARG, "tile_alt, item_alt and waves_alt must be 0 or 1");
+    if (t->grid_mult < 1 || t->grid_mult > 64) return fail(AX_ERR_ARG, "grid_mult %d outside [1,64]", t->grid_mult);
     tune_init();
-    g_tune[N + 1][geom_kind][prec] = TuneEntry{epb_alt, grid_mult};
+    g_tune[N + 1][kind][prec] = TuneEntry{t->kernel, t->tile_alt, t->item_alt, t->waves_alt, t->grid_mult};
     return AX_OK;
 }
 
-extern "C" int ax_tune_get(int N, int geom_kind, int prec, int* epb_alt, int* grid_mult, int* elems_per_group)
+extern "C" int ax_tune_get(int N, int kind, int prec, ax_tune* t)
 {
     clear_error();
-    if (N < 1 || N > 15) return fail(AX_ERR_UNSUPPORTED, "order N=%d outside [1,15]", N);
-    if (geom_kind < 0 || geom_kind > 2) return fail(AX_ERR_ARG, "geometry kind %d", geom_kind);
-    if (prec != AX_FP64 && prec != AX_FP32) return fail(AX_ERR_ARG, "precision %d (FP64 or FP32)", prec);
-    const TuneEntry t = tune_get(N + 1, geom_kind, prec);
-    if (epb_alt) *epb_alt = t.epb_alt;
-    if (grid_mult) *grid_mult = t.grid_mult;
-    if (elems_per_group) *elems_per_group = epb_of(N + 1, t.epb_alt != 0);
+    AX_TRY(tune_check(N, kind, prec));
+    if (!t) return fail(AX_ERR_ARG, "t is NULL");
+    const int N1 = N + 1;
+    const bool fp32 = prec == AX_FP32;
+    const TuneEntry e = tune_get(N1, kind, prec);
+    const int geo = kind == TUNE_TRI ? GEO_TRI : kind == TUNE_PARTIAL ? GEO_TRIL : kind == TUNE_PARA ? GEO_PARA
+                  : kind == TUNE_STORED ? GEO_STORED : GEO_HELM;
+    const bool item = kind == TUNE_BATCHED ||
+                      (item_available(N1, geo) &&
+                       (e.kernel == AX_KERNEL_ITEM || (e.kernel == AX_KERNEL_AUTO && item_default(N1, geo, fp32))));
+    *t = ax_tune{e.kernel, e.tile_alt, e.item_alt, e.waves_alt, e.grid_mult, 0, 0, 0, 0};
+    t->kernel_used = item ? AX_KERNEL_ITEM : AX_KERNEL_TILE;
+    if (item) {
+        const ItemShape sh = item_shape(N1, item_has_alt(N1) ? e.item_alt : 0);
+        t->elems_per_group = sh.epb;
+        t->block = sh.block;
+        t->waves = kind == TUNE_BATCHED ? batch_waves(fp32) : item_waves(N1, fp32, geo == GEO_TRIL, e.waves_alt);
+    } else {
+        t->elems_per_group = tile_epb(N1, e.tile_alt != 0);
+        t->block = ((t->elems_per_group * N1 * N1 + 63) / 64) * 64;
+        t->waves = tile_waves(N1, geo, fp32);
+    }
     return AX_OK;
 }
 

@@ -133,11 +133,15 @@ inline bool symmetric_nodes(int N1, const double* xi, const double* w)
 
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
-// Launch tuning of the AxLocal kernels per (N1, geometry kind 0/1/2, precision FP64/FP32).
+// Launch variants of the AxLocal kernels per (N1, tuning kind TUNE_*, precision FP64/FP32); the
+// fields are those of the public ax_tune.
 struct TuneEntry {
-    int epb_alt;    // 0: default elements per work-group, 1: the alternative shape
+    int kernel;     // AX_KERNEL_AUTO, AX_KERNEL_TILE or AX_KERNEL_ITEM
+    int tile_alt;   // tile kernel: 0 default elements per work-group, 1 the alternative
+    int item_alt;   // per-item kernels: 0 the 256-lane shape, 1 the order's alternative
+    int waves_alt;  // single-mesh per-item kernel: 0 default register budget, 1 the alternative
     int grid_mult;  // persistent grid = grid_mult x resident capacity
 };
-TuneEntry tune_get(int N1, int geo_kind, int prec);
+TuneEntry tune_get(int N1, int kind, int prec);
 
 }  // namespace ax

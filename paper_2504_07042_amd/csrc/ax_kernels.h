@@ -14,6 +14,97 @@ enum { GEO_TRI = 0, GEO_PARA = 1, GEO_STORED = 2, GEO_TRIL = 3, GEO_HELM = 4 };
 
 constexpr bool is_trilinear(int geo) { return geo == GEO_TRI || geo == GEO_TRIL || geo == GEO_HELM; }
 
+// ---- Launch variants chosen at run time (the tuning table, ax_tune_set) ----
+//
+// Tuning kinds: one table entry per (order, kind, precision).
+enum { TUNE_TRI = 0, TUNE_PARA = 1, TUNE_STORED = 2, TUNE_PARTIAL = 3, TUNE_HELM = 4, TUNE_BATCHED = 5,
+       TUNE_KINDS = 6 };
+constexpr int tune_kind_of(int geo)
+{
+    return geo == GEO_TRI ? TUNE_TRI : geo == GEO_PARA ? TUNE_PARA : geo == GEO_STORED ? TUNE_STORED
+         : geo == GEO_TRIL ? TUNE_PARTIAL : TUNE_HELM;
+}
+
+// Shape of the per-item kernels (one element per N1^2 lanes, several elements per work-group):
+// variant 0 is a 256-lane work-group holding floor(256 / N1^2) elements (at most 64); variant 1
+// is the alternative the tuner may pick: half the work-group for N1 <= 8 (smaller groups, cheaper
+// barriers), a larger group for N1 = 9, 10 and a tighter one for N1 = 11..13 (fewer idle lanes:
+// at N1 = 12 the 256-lane group leaves 112 lanes idle, a 192-lane group 48).  N1 >= 14 has no
+// alternative.
+struct ItemShape {
+    int epb, block;
+};
+constexpr ItemShape item_shape(int N1, int v)
+{
+    if (v == 1) {
+        switch (N1) {
+        case 2: return {32, 128};
+        case 3: return {14, 128};
+        case 4: return {8, 128};
+        case 5: return {5, 128};
+        case 6: return {5, 192};
+        case 7: return {2, 128};
+        case 8: return {2, 128};
+        case 9: return {4, 384};
+        case 10: return {3, 320};
+        case 11: return {1, 128};
+        case 12: return {1, 192};
+        case 13: return {1, 192};
+        default: break;
+        }
+    }
+    return {256 / (N1 * N1) > 64 ? 64 : (256 / (N1 * N1) < 1 ? 1 : 256 / (N1 * N1)), 256};
+}
+constexpr bool item_has_alt(int N1) { return N1 >= 2 && N1 <= 13; }
+
+// Register budget of the single-mesh per-item kernel, as waves per SIMD: the default (FP32 full
+// form five waves except at N1 = 13, otherwise no limit beyond two) and the alternative (one wave
+// more where the default is two, one fewer where it is five).
+constexpr int item_waves(int N1, bool fp32, bool partial, int alt)
+{
+    const int d = (fp32 && !partial && N1 != 13) ? 5 : 2;
+    return alt ? (d == 2 ? 3 : 4) : d;
+}
+
+// Which kernel runs when the tuning table says "auto" (measured on gfx950, interleaved runs).
+// FP64 full form: the per-item kernel for N1 = 6, 7 and 9..15 (faster than the prefetching
+// kernel there, about even at N1 = 5, slower at N1 <= 4, 8 and 16).  FP64 partial form: the
+// per-item kernel from N1 = 9 (the prefetching kernel, with fewer live registers in this form,
+// was faster at N1 = 6).  FP32 full form: the per-item kernel from N1 = 9 (at five waves per SIMD:
+// +7-8 % at N1 = 9 and 10, +13-15 % at N1 = 12, 15, where the prefetching kernel runs at two).
+// FP32 partial form: from N1 = 13 (+18 % at 13, +7 % at 14, +2 % at 15; even at 10 and 8-10 %
+// behind at 11, 12).
+#ifndef AX_ITEM_LO
+#define AX_ITEM_LO 6
+#endif
+#ifndef AX_ITEM_LO_F32
+#define AX_ITEM_LO_F32 9
+#endif
+#ifndef AX_ITEM_PL_LO_F32
+#define AX_ITEM_PL_LO_F32 13
+#endif
+constexpr bool item_default(int N1, int geo, bool fp32)
+{
+    if (N1 > 15) return false;
+    if (fp32)
+        return (geo == GEO_TRI && N1 >= AX_ITEM_LO_F32 && N1 >= 9) ||
+               (geo == GEO_TRIL && N1 >= AX_ITEM_PL_LO_F32 && N1 >= 13);
+    return (geo == GEO_TRI && N1 >= AX_ITEM_LO && N1 != 8) || (geo == GEO_TRIL && N1 >= 9);
+}
+
+// Register budget of the batched per-order kernels: FP32 fits five waves per SIMD.
+#ifndef AX_BATCH_MINW_F32
+#define AX_BATCH_MINW_F32 5
+#endif
+constexpr int batch_waves(bool fp32) { return fp32 ? AX_BATCH_MINW_F32 : 2; }
+
+// Orders with a per-item kernel: the full trilinear form for every order, the partial form from
+// N1 = 9.
+constexpr bool item_available(int N1, int geo)
+{
+    return (geo == GEO_TRI && N1 >= 2 && N1 <= 16) || (geo == GEO_TRIL && N1 >= 9 && N1 <= 16);
+}
+
 // Tuning knobs (compile-time): waves per SIMD the register allocation targets for N1 <= 8, and
 // how many times the resident capacity the persistent grid is.
 #ifndef AX_MINW_SMALL
@@ -90,6 +181,30 @@ struct Shape {
     // waves per SIMD the register allocation must allow (latency hiding for the X/Y streams)
     static constexpr int MINW = N1 == 8 ? AX_MINW_SMALL : AX_MINW_OTHER;
 };
+
+// Waves per SIMD the register allocation of the prefetching (tile) kernel targets: four at
+// N1 = 8 and two elsewhere (AX_MINW_SMALL / AX_MINW_OTHER), except that the FP64 Helmholtz kernel
+// at N1 = 8 also carries the mass-term operands through the last phases, which does not fit the
+// four-wave budget without spills, and FP32 at N1 = 8, measured interleaved at N = 7, 32^3 with
+// LDS layout 2: the trilinear kernel is fastest at four (49.3 us; five spill 6 registers,
+// 52.0 us; six 58.2 us), partial recomputation at five (47.0 vs 48.6 us at four),
+// parallelepipeds and stored factors within 1 % of each other from four to six.
+#ifndef AX_HELM_MINW
+#define AX_HELM_MINW 3
+#endif
+#ifndef AX_MINW_F32
+#define AX_MINW_F32 5
+#endif
+#ifndef AX_MINW_F32_TRI
+#define AX_MINW_F32_TRI 4
+#endif
+constexpr int tile_waves(int N1, int geo, bool fp32)
+{
+    return (geo == GEO_HELM && N1 == 8 && !fp32) ? AX_HELM_MINW
+           : (N1 == 8 && fp32)                  ? (geo == GEO_TRI ? AX_MINW_F32_TRI : AX_MINW_F32)
+           : N1 == 8                            ? AX_MINW_SMALL
+                                                : AX_MINW_OTHER;
+}
 
 // Coefficient sources of the contractions.  CoefResident reads the basis tables as they are
 // (kernel arguments: the compiler keeps every coefficient it needs in scalar registers).

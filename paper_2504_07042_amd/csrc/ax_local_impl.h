@@ -442,28 +442,10 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
     }
 }
 
-// Waves per SIMD the register allocation targets: the FP64 Helmholtz kernel at N1 = 8 also
-// carries the mass-term operands through the last phases, which does not fit the four-wave
-// budget without spills.
-#ifndef AX_HELM_MINW
-#define AX_HELM_MINW 3
-#endif
-// FP32 at N1 = 8: waves per SIMD the register allocation targets.  Measured interleaved at
-// N = 7, 32^3 with LDS layout 2: the trilinear kernel is fastest at four (49.3 us; five spill 6
-// registers, 52.0 us; six 58.2 us), partial recomputation at five (47.0 vs 48.6 us at four),
-// parallelepipeds and stored factors within 1 % of each other from four to six.
-#ifndef AX_MINW_F32
-#define AX_MINW_F32 5
-#endif
-#ifndef AX_MINW_F32_TRI
-#define AX_MINW_F32_TRI 4
-#endif
 template <int N1, int GEO, typename T>
 constexpr int min_waves()
 {
-    return (GEO == GEO_HELM && N1 == 8 && sizeof(T) == 8) ? AX_HELM_MINW
-           : (N1 == 8 && sizeof(T) == 4)                 ? (GEO == GEO_TRI ? AX_MINW_F32_TRI : AX_MINW_F32)
-                                                         : Shape<N1>::MINW;
+    return tile_waves(N1, GEO, sizeof(T) == 4);
 }
 
 // Entry points: the tables of orders that fit the scalar register file stay resident; the
@@ -524,38 +506,11 @@ static int launch_tile(int64_t E, int nrhs, const double* geo, const T* Gs, cons
 }
 
 int tri_item_dispatch_f64(int N1, int64_t E, int nrhs, const double* verts, const double* X, double* Y,
-                          const Basis<double>& bs, int grid_mult, hipStream_t st, const double* lam, int64_t es,
-                          int64_t ccs);
+                          const Basis<double>& bs, int grid_mult, int variant, int waves, hipStream_t st,
+                          const double* lam, int64_t es, int64_t ccs);
 int tri_item_dispatch_f32(int N1, int64_t E, int nrhs, const double* verts, const float* X, float* Y,
-                          const Basis<float>& bs, int grid_mult, hipStream_t st, const float* lam, int64_t es,
-                          int64_t ccs);
-// FP32: the per-item kernel from N1 = 9 (measured with it at five waves per SIMD: +7-8 % at
-// N1 = 9 and 10, +13-15 % at N1 = 12, 15, where the prefetching kernel runs at two)
-#ifndef AX_ITEM_LO_F32
-#define AX_ITEM_LO_F32 9
-#endif
-// FP32 partial recomputation: the per-item kernel from N1 = 13 (measured interleaved: +18 % at
-// N1 = 13, +7 % at 14, +2 % at 15; even at 10 and 8-10 % behind at 11, 12)
-#ifndef AX_ITEM_PL_LO_F32
-#define AX_ITEM_PL_LO_F32 13
-#endif
-
-// Trilinear FP64 orders served by the per-item kernel (see batched.hip); measured on gfx950
-// it is faster than the prefetching kernel for N1 = 6, 7 and 9..15, about even at N1 = 5 and
-// slower at N1 <= 4, 8 and 16.
-#ifndef AX_ITEM_LO
-#define AX_ITEM_LO 6
-#endif
-template <int N1, int GEO, typename T>
-constexpr bool use_item_kernel()
-{
-    // the partial-recomputation form (fewer live registers) stays on the prefetching kernel
-    // below N1 = 9 (measured faster there at N1 = 6)
-    if constexpr (sizeof(T) == 4)
-        return ((GEO == GEO_TRI && N1 >= AX_ITEM_LO_F32 && N1 >= 9) ||
-                (GEO == GEO_TRIL && N1 >= AX_ITEM_PL_LO_F32 && N1 >= 13)) && N1 <= 15;
-    return (GEO == GEO_TRI || GEO == GEO_TRIL) && N1 >= (GEO == GEO_TRIL ? 9 : AX_ITEM_LO) && N1 <= 15 && N1 != 8;
-}
+                          const Basis<float>& bs, int grid_mult, int variant, int waves, hipStream_t st,
+                          const float* lam, int64_t es, int64_t ccs);
 
 template <int N1, int GEO, typename T>
 static int launch_n1(int64_t E, int nrhs, const double* geo, const T* Gs, const T* X, T* Y,
@@ -567,27 +522,31 @@ static int launch_n1(int64_t E, int nrhs, const double* geo, const T* Gs, const 
     fill_basis(bs, N1, D, xi, w);
     // the even-odd kernels also take the nodes as mirror-symmetric (the factors need none)
     const bool eo = centro_antisymmetric(N1, D) && (GEO == GEO_STORED || symmetric_nodes(N1, xi, w));
-    const TuneEntry tu = tune_get(N1, is_trilinear(GEO) ? GEO_TRI : GEO, sizeof(T) == 8 ? AX_FP64 : AX_FP32);
+    const TuneEntry tu = tune_get(N1, tune_kind_of(GEO), sizeof(T) == 8 ? AX_FP64 : AX_FP32);
     if (l2g) {
         if (!eo) return fail(AX_ERR_UNSUPPORTED, "gathering AxLocal needs a GLL differentiation matrix");
         if constexpr (GEO == GEO_TRI || GEO == GEO_PARA)
             return launch_tile<N1, GEO, true, true, S::EPB, T>(E, nrhs, geo, Gs, X, Y, bs, tu.grid_mult, st, l2g, ldg, es, ccs);
         return fail(AX_ERR_UNSUPPORTED, "gathering AxLocal needs on-the-fly factors");
     }
-    if constexpr (use_item_kernel<N1, GEO, T>()) {
-        if (eo && !l2g) {
+    // the per-item kernel where the tuning table (or the measured default) picks it
+    if constexpr (item_available(N1, GEO)) {
+        const bool item = tu.kernel == AX_KERNEL_ITEM ||
+                          (tu.kernel == AX_KERNEL_AUTO && item_default(N1, GEO, sizeof(T) == 4));
+        if (eo && item) {
             if constexpr (sizeof(T) == 8)
-                return tri_item_dispatch_f64(N1, E, nrhs, geo, (const double*)X, (double*)Y, bs, tu.grid_mult, st,
+                return tri_item_dispatch_f64(N1, E, nrhs, geo, (const double*)X, (double*)Y, bs, tu.grid_mult,
+                                             tu.item_alt, tu.waves_alt, st,
                                              GEO == GEO_TRIL ? (const double*)Gs : nullptr, es, ccs);
             else
-                return tri_item_dispatch_f32(N1, E, nrhs, geo, X, Y, bs, tu.grid_mult, st,
+                return tri_item_dispatch_f32(N1, E, nrhs, geo, X, Y, bs, tu.grid_mult, tu.item_alt, tu.waves_alt, st,
                                              GEO == GEO_TRIL ? (const float*)Gs : nullptr, es, ccs);
         }
     }
     if (!eo)
         return launch_tile<N1, GEO, false, false, S::EPB, T>(E, nrhs, geo, Gs, X, Y, bs, tu.grid_mult, st, nullptr, 0, es, ccs);
     if constexpr (S::EPB_ALT != S::EPB) {
-        if (tu.epb_alt)
+        if (tu.tile_alt)
             return launch_tile<N1, GEO, true, false, S::EPB_ALT, T>(E, nrhs, geo, Gs, X, Y, bs, tu.grid_mult, st,
                                                                     nullptr, 0, es, ccs);
     }

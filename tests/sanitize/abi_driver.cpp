@@ -69,19 +69,29 @@ int main()
     CHECK(std::strlen(ax_last_error()) > 0);
 
     // tuning table
-    int a = -1, g = -1, epg = -1;
-    EXPECT(ax_tune_get(7, AX_TRILINEAR, AX_FP64, &a, &g, &epg), AX_OK);
-    EXPECT(ax_tune_set(7, AX_TRILINEAR, AX_FP64, 1, 4), AX_OK);
-    int a2, g2, e2;
-    EXPECT(ax_tune_get(7, AX_TRILINEAR, AX_FP64, &a2, &g2, &e2), AX_OK);
-    CHECK(a2 == 1 && g2 == 4);
-    EXPECT(ax_tune_set(7, AX_TRILINEAR, AX_FP64, a, g), AX_OK);
-    EXPECT(ax_tune_set(7, 0, 0, 2, 1), AX_ERR_ARG);
-    EXPECT(ax_tune_set(16, 0, 0, 0, 1), AX_ERR_UNSUPPORTED);
-    EXPECT(ax_tune_set(7, 3, 0, 0, 1), AX_ERR_ARG);
+    ax_tune t0{}, t1{};
+    EXPECT(ax_tune_get(7, AX_TUNE_TRILINEAR, AX_FP64, &t0), AX_OK);
+    t1 = t0;
+    t1.kernel = AX_KERNEL_ITEM;
+    t1.item_alt = 1;
+    t1.grid_mult = 4;
+    EXPECT(ax_tune_set(7, AX_TUNE_TRILINEAR, AX_FP64, &t1), AX_OK);
+    ax_tune t2{};
+    EXPECT(ax_tune_get(7, AX_TUNE_TRILINEAR, AX_FP64, &t2), AX_OK);
+    CHECK(t2.kernel_used == AX_KERNEL_ITEM && t2.grid_mult == 4 && t2.block == 128);
+    EXPECT(ax_tune_set(7, AX_TUNE_TRILINEAR, AX_FP64, &t0), AX_OK);
+    t1.tile_alt = 2;
+    EXPECT(ax_tune_set(7, AX_TUNE_TRILINEAR, AX_FP64, &t1), AX_ERR_ARG);
+    EXPECT(ax_tune_set(16, AX_TUNE_TRILINEAR, AX_FP64, &t0), AX_ERR_UNSUPPORTED);
+    EXPECT(ax_tune_set(7, 6, AX_FP64, &t0), AX_ERR_ARG);
+    EXPECT(ax_tune_set(10, AX_TUNE_BATCHED, AX_FP64, &t0), AX_ERR_ARG);
+    EXPECT(ax_tune_get(7, AX_TUNE_TRILINEAR, AX_FP64, nullptr), AX_ERR_ARG);
     for (int N = 1; N <= 15; ++N)
-        for (int k = 0; k < 3; ++k)
-            for (int p = 0; p < 2; ++p) EXPECT(ax_tune_get(N, k, p, &a, &g, &epg), AX_OK);
+        for (int k = 0; k < 6; ++k)
+            for (int p = 0; p < 2; ++p) {
+                ax_tune t{};
+                EXPECT(ax_tune_get(N, k, p, &t), (k == AX_TUNE_BATCHED && N > 9) ? AX_ERR_ARG : AX_OK);
+            }
 
     // element-local operators: validation only
     Gll b3(3);

@@ -103,18 +103,54 @@ def test_gs_validation_and_csr(ax):
 
 def test_tuning_roundtrip(ax):
     from paper_2504_07042_amd import autotune
-    before = autotune.tune_get(7, ax.AX_TRILINEAR, ax.AX_FP64)
-    autotune.tune_set(7, ax.AX_TRILINEAR, ax.AX_FP64, 1, 4)
-    t = autotune.tune_get(7, ax.AX_TRILINEAR, ax.AX_FP64)
-    assert t["epb_alt"] == 1 and t["grid_mult"] == 4 and t["elems_per_group"] == 2
-    autotune.tune_set(7, ax.AX_TRILINEAR, ax.AX_FP64, before["epb_alt"], before["grid_mult"])
-    assert autotune.tune_get(7, ax.AX_TRILINEAR, ax.AX_FP64) == before
+    K, P = ax.AX_TUNE_TRILINEAR, ax.AX_FP64
+    before = autotune.tune_get(7, K, P)
+    try:
+        autotune.tune_set(7, K, P, kernel=ax.AX_KERNEL_TILE, tile_alt=1, grid_mult=4)
+        t = autotune.tune_get(7, K, P)
+        assert (t["kernel_used"], t["elems_per_group"], t["block"], t["grid_mult"]) == (ax.AX_KERNEL_TILE, 2, 128, 4)
+        autotune.tune_set(7, K, P, kernel=ax.AX_KERNEL_ITEM, item_alt=1, waves_alt=1)
+        t = autotune.tune_get(7, K, P)
+        assert (t["kernel_used"], t["elems_per_group"], t["block"], t["waves"]) == (ax.AX_KERNEL_ITEM, 2, 128, 3)
+        autotune.tune_set(7, K, P, kernel=ax.AX_KERNEL_AUTO, item_alt=0, waves_alt=0)
+        assert autotune.tune_get(7, K, P)["kernel_used"] == ax.AX_KERNEL_TILE      # N1 = 8: measured default
+        assert autotune.tune_get(6, K, P)["kernel_used"] == ax.AX_KERNEL_ITEM
+        # the partial form has a per-item kernel from N1 = 9 only
+        autotune.tune_set(7, ax.AX_TUNE_PARTIAL, P, kernel=ax.AX_KERNEL_ITEM)
+        assert autotune.tune_get(7, ax.AX_TUNE_PARTIAL, P)["kernel_used"] == ax.AX_KERNEL_TILE
+        autotune.tune_set(7, ax.AX_TUNE_PARTIAL, P, kernel=ax.AX_KERNEL_AUTO)
+        # batched: per-item, shape per order
+        autotune.tune_set(3, ax.AX_TUNE_BATCHED, ax.AX_FP32, item_alt=1)
+        t = autotune.tune_get(3, ax.AX_TUNE_BATCHED, ax.AX_FP32)
+        assert (t["kernel_used"], t["elems_per_group"], t["block"], t["waves"]) == (ax.AX_KERNEL_ITEM, 8, 128, 5)
+        autotune.tune_set(3, ax.AX_TUNE_BATCHED, ax.AX_FP32, item_alt=0)
+        # the variants the tuner enumerates at N1 = 12: one tile shape (no alternative there) and
+        # the per-item kernel in two shapes times two register budgets
+        v = autotune._variants(11, K, ax.AX_FP32)
+        assert len(v) == 5 and len({tuple(sorted(d.items())) for d in v}) == 5
+        assert sum(d["kernel"] == ax.AX_KERNEL_ITEM for d in v) == 4
+        assert len(autotune._variants(11, ax.AX_TUNE_STORED, ax.AX_FP32)) == 1
+        assert len(autotune._variants(3, ax.AX_TUNE_BATCHED, ax.AX_FP64)) == 2
+    finally:
+        autotune.tune_set(7, K, P, **{k: before[k] for k in autotune.KNOBS})
+    assert autotune.tune_get(7, K, P) == before
     L = ax.lib()
-    assert L.ax_tune_set(7, 0, 0, 2, 1) == ax.AX_ERR_ARG
-    assert L.ax_tune_set(7, 0, 0, 0, 0) == ax.AX_ERR_ARG
-    assert L.ax_tune_set(16, 0, 0, 0, 1) == ax.AX_ERR_UNSUPPORTED
-    assert L.ax_tune_set(7, 3, 0, 0, 1) == ax.AX_ERR_ARG
-    assert L.ax_tune_set(7, 0, ax.AX_FP16_ACC32, 0, 1) == ax.AX_ERR_ARG
+
+    def raw(N, kind, prec, **kw):
+        t = ax.AxTune(**dict(autotune.DEFAULT, **kw))
+        return L.ax_tune_set(N, kind, prec, ctypes.byref(t))
+    assert raw(7, K, P) == ax.AX_OK
+    assert raw(7, K, P, kernel=3) == ax.AX_ERR_ARG
+    assert raw(7, K, P, tile_alt=2) == ax.AX_ERR_ARG
+    assert raw(7, K, P, waves_alt=-1) == ax.AX_ERR_ARG
+    assert raw(7, K, P, grid_mult=0) == ax.AX_ERR_ARG
+    assert raw(7, K, P, grid_mult=65) == ax.AX_ERR_ARG
+    assert raw(16, K, P) == ax.AX_ERR_UNSUPPORTED
+    assert raw(7, 6, P) == ax.AX_ERR_ARG
+    assert raw(7, K, ax.AX_FP16_ACC32) == ax.AX_ERR_ARG
+    assert raw(10, ax.AX_TUNE_BATCHED, P) == ax.AX_ERR_ARG
+    assert L.ax_tune_set(7, K, P, None) == ax.AX_ERR_ARG
+    assert L.ax_tune_get(7, K, P, None) == ax.AX_ERR_ARG
 
 
 def test_cg_validation(ax):

@@ -229,22 +229,3 @@ def test_fp16_other_orders_unsupported(ax):
     assert ei.value.code == ax.AX_ERR_UNSUPPORTED
 
 
-@pytest.mark.parametrize("N", [3, 7])
-def test_tuning_does_not_change_results(ax, N):
-    """Every launch shape the autotuner may pick gives bitwise the same result."""
-    from paper_2504_07042_amd import autotune
-    m = _mesh_for(N)
-    X = _dev(meshgen.random_nodal(m.E, N, seed=5))
-    b = ax.Basis(N)
-    v = _dev(m.verts)
-    saved = autotune.tune_get(N, ax.AX_TRILINEAR, ax.AX_FP64)
-    outs = []
-    try:
-        for alt in (0, 1):
-            for gm in (1, 3):
-                autotune.tune_set(N, ax.AX_TRILINEAR, ax.AX_FP64, alt, gm)
-                outs.append(ax.ax_local(X, v, b).cpu().numpy())
-    finally:
-        autotune.tune_set(N, ax.AX_TRILINEAR, ax.AX_FP64, saved["epb_alt"], saved["grid_mult"])
-    for o in outs[1:]:
-        assert np.array_equal(o, outs[0])
