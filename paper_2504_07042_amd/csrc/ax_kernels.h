@@ -198,11 +198,19 @@ struct Shape {
 #ifndef AX_MINW_F32_TRI
 #define AX_MINW_F32_TRI 4
 #endif
+#ifndef AX_MINW_TINY
+#define AX_MINW_TINY AX_MINW_OTHER
+#endif
+#ifndef AX_MINW_MID
+#define AX_MINW_MID AX_MINW_OTHER
+#endif
 constexpr int tile_waves(int N1, int geo, bool fp32)
 {
     return (geo == GEO_HELM && N1 == 8 && !fp32) ? AX_HELM_MINW
            : (N1 == 8 && fp32)                  ? (geo == GEO_TRI ? AX_MINW_F32_TRI : AX_MINW_F32)
            : N1 == 8                            ? AX_MINW_SMALL
+           : N1 <= 4                            ? AX_MINW_TINY
+           : N1 <= 7                            ? AX_MINW_MID
                                                 : AX_MINW_OTHER;
 }
 

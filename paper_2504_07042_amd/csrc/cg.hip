@@ -174,7 +174,7 @@ qt_dot_kernel(int64_t n_global, const CopyPair* __restrict__ cp, const int64_t* 
     const T* pd = pdir + (int64_t)c * n_global;
     T* o = out + (int64_t)c * n_global;
     double acc = 0.0;
-    for (int64_t g0 = (int64_t)blockIdx.x * kRedThreads * kUnroll + threadIdx.x; g0 < n_global;
+    for (int64_t g0 = xcd_tile(blockIdx.x, gridDim.x) * kRedThreads * kUnroll + threadIdx.x; g0 < n_global;
          g0 += (int64_t)gridDim.x * kRedThreads * kUnroll) {
         CopyPair q[kUnroll];
 #pragma unroll
@@ -183,10 +183,14 @@ qt_dot_kernel(int64_t n_global, const CopyPair* __restrict__ cp, const int64_t* 
             q[u] = g < n_global ? cp[g] : CopyPair{-1, -1};
         }
         T v0[kUnroll], v1[kUnroll];
+        int64_t b[kUnroll], e[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             v0[u] = q[u].first >= 0 ? x[q[u].first] : T(0);
             v1[u] = q[u].second >= 0 ? x[q[u].second] : T(0);
+            const bool many = q[u].second == -2;
+            b[u] = many ? gptr[g0 + u * kRedThreads] + 1 : 0;
+            e[u] = many ? gptr[g0 + u * kRedThreads + 1] : 0;
         }
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
@@ -196,8 +200,19 @@ qt_dot_kernel(int64_t n_global, const CopyPair* __restrict__ cp, const int64_t* 
                 if (q[u].second >= 0) {
                     s += v1[u];
                 } else if (q[u].second == -2) {
-                    const int64_t e = gptr[g + 1];
-                    for (int64_t k = gptr[g] + 1; k < e; ++k) s += x[gidx[k]];
+                    // the further copies (at most 7 more on a hexahedral mesh) fetched with
+                    // independent loads, summed in ascending local id
+                    constexpr int kMore = 7;
+                    int32_t id[kMore];
+#pragma unroll
+                    for (int m = 0; m < kMore; ++m) id[m] = b[u] + m < e[u] ? gidx[b[u] + m] : -1;
+                    T v[kMore];
+#pragma unroll
+                    for (int m = 0; m < kMore; ++m) v[m] = id[m] >= 0 ? x[id[m]] : T(0);
+#pragma unroll
+                    for (int m = 0; m < kMore; ++m)
+                        if (id[m] >= 0) s += v[m];
+                    for (int64_t k = b[u] + kMore; k < e[u]; ++k) s += x[gidx[k]];
                 }
                 o[g] = s;
                 acc = fma((double)pd[g], (double)s, acc);

@@ -7,8 +7,9 @@ namespace ax {
 
 // Sums of the local copies of U global nodes g[u] (ascending local id each, the order of the plain
 // loop).  The first copies of all U nodes are fetched with independent loads (offsets, then
-// indices, then values), so the common single-copy node costs three overlapped round trips;
-// further copies of shared nodes follow in a loop.  valid[u] false yields 0 without loads.
+// indices, then values), so the common single-copy node costs three overlapped round trips; the
+// further copies of a shared node (up to 7 more: a vertex of a hexahedral mesh has 8) are fetched
+// together too, any beyond those in a loop.  valid[u] false yields 0 without loads.
 template <int U, typename T, typename IP>
 __device__ __forceinline__ void gather_sums(const IP* __restrict__ gptr, const int32_t* __restrict__ gidx,
                                             const T* __restrict__ x, const int64_t* g, const bool* valid, T* s)
@@ -25,8 +26,20 @@ __device__ __forceinline__ void gather_sums(const IP* __restrict__ gptr, const i
 #pragma unroll
     for (int u = 0; u < U; ++u) s[u] = q1[u] > q0[u] ? T(0) + x[id[u]] : T(0);
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-        for (int64_t q = q0[u] + 1; q < q1[u]; ++q) s[u] += x[gidx[q]];
+    for (int u = 0; u < U; ++u) {
+        if (q1[u] - q0[u] < 2) continue;
+        constexpr int kMore = 7;
+        int32_t idm[kMore];
+#pragma unroll
+        for (int m = 0; m < kMore; ++m) idm[m] = q0[u] + 1 + m < q1[u] ? gidx[q0[u] + 1 + m] : -1;
+        T v[kMore];
+#pragma unroll
+        for (int m = 0; m < kMore; ++m) v[m] = idm[m] >= 0 ? x[idm[m]] : T(0);
+#pragma unroll
+        for (int m = 0; m < kMore; ++m)
+            if (idm[m] >= 0) s[u] += v[m];
+        for (int64_t q = q0[u] + 1 + kMore; q < q1[u]; ++q) s[u] += x[gidx[q]];
+    }
 }
 
 // nodes (or local entries) per thread and tile in the gather-scatter kernels
