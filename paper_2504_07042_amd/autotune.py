@@ -9,10 +9,10 @@ at run time (``ax_tune_set``):
   single-mesh per-item kernel, its register budget (default or alternative waves per SIMD);
 * the persistent grid (1, 2, 4 or 8 times the resident work-group capacity);
 
-on a synthetic mesh of about 2^24 local nodes (two rotating X/Y pairs, so that the vectors do not
-stay in the 256 MB Infinity Cache), keeps the fastest when it beats the default by more than the
-noise margin, and writes a JSON cache stamped with the SHA-256 of the kernel sources it was
-measured on.  ``load()`` pushes a cache into the library; the package calls it on import.  Every
+on a synthetic mesh of about 2^24 local nodes (four rotating X/Y pairs, as the benchmark times
+them, so that the vectors do not stay in the 256 MB Infinity Cache), keeps the fastest when it
+beats the default by more than the noise margin, and writes a JSON cache stamped with the
+SHA-256 of the kernel sources it was measured on.  ``load()`` pushes a cache into the library; the package calls it on import.  Every
 variant gives the same result up to rounding (bitwise the same for one kernel).
 
     python -m paper_2504_07042_amd.autotune            # tune everything, write the cache
@@ -119,7 +119,7 @@ def _variants(N: int, kind: int, prec: int):
     return out
 
 
-def _time_configs(fns, configs, apply, rounds=3, reps=8, warmup=2):
+def _time_configs(fns, configs, apply, rounds=3, reps=12, warmup=4):
     """Interleaved timing: each round times every config; the best round per config counts."""
     import torch
     best = [float("inf")] * len(configs)
@@ -138,8 +138,11 @@ def _time_configs(fns, configs, apply, rounds=3, reps=8, warmup=2):
     return best
 
 
+NBUF = 4          # rotating X/Y pairs
+
+
 def _workloads(N, prec, target_nodes, kinds):
-    """Launch closures per tuning kind on two rotating X/Y pairs of about target_nodes nodes."""
+    """Launch closures per tuning kind on NBUF rotating X/Y pairs of about target_nodes nodes."""
     import torch
 
     from . import (BatchedAxLocal, ax_local, ax_local_helmholtz, ax_local_partial, ax_local_precomputedG,
@@ -150,28 +153,28 @@ def _workloads(N, prec, target_nodes, kinds):
     m = meshgen.jittered_hex(*grid, alpha=0.15, seed=N)
     V = torch.from_numpy(m.verts).cuda()
     dt = torch.float64 if prec == AX_FP64 else torch.float32
-    Xs = [meshgen.random_nodal_device(m.E, N, seed=N + q, dtype=dt) for q in range(2)]
+    Xs = [meshgen.random_nodal_device(m.E, N, seed=N + q, dtype=dt) for q in range(NBUF)]
     Ys = [torch.empty_like(x) for x in Xs]
     work = {}
     if "trilinear" in kinds:
-        work["trilinear"] = [lambda q=q: ax_local(Xs[q], V, b, AX_TRILINEAR, prec, out=Ys[q]) for q in range(2)]
+        work["trilinear"] = [lambda q=q: ax_local(Xs[q], V, b, AX_TRILINEAR, prec, out=Ys[q]) for q in range(NBUF)]
     if "parallelepiped" in kinds:
         pm, _ = meshgen.parallelepiped_hex(*grid, seed=2)
         h = parallelepiped_factors(torch.from_numpy(pm.verts).cuda())
         work["parallelepiped"] = [lambda q=q: ax_local(Xs[q], h, b, AX_PARALLELEPIPED, prec, out=Ys[q])
-                                  for q in range(2)]
+                                  for q in range(NBUF)]
     if "stored" in kinds:
         G, _ = geom_factors(V, b, prec)
-        work["stored"] = [lambda q=q: ax_local_precomputedG(Xs[q], G, b, prec, out=Ys[q]) for q in range(2)]
+        work["stored"] = [lambda q=q: ax_local_precomputedG(Xs[q], G, b, prec, out=Ys[q]) for q in range(NBUF)]
     if "partial" in kinds:
         lam = geom_lambda(V, b, prec)
-        work["partial"] = [lambda q=q: ax_local_partial(Xs[q], V, lam, b, prec, out=Ys[q]) for q in range(2)]
+        work["partial"] = [lambda q=q: ax_local_partial(Xs[q], V, lam, b, prec, out=Ys[q]) for q in range(NBUF)]
     if "helmholtz" in kinds:
         l0 = torch.ones((m.E, NP), dtype=torch.float64, device="cuda")
         l1 = torch.full((m.E, NP), 0.5, dtype=torch.float64, device="cuda")
         L23 = helmholtz_factors(V, l0, l1, b, prec)
         del l0, l1
-        work["helmholtz"] = [lambda q=q: ax_local_helmholtz(Xs[q], V, L23, b, prec, out=Ys[q]) for q in range(2)]
+        work["helmholtz"] = [lambda q=q: ax_local_helmholtz(Xs[q], V, L23, b, prec, out=Ys[q]) for q in range(NBUF)]
     if "batched" in kinds and N <= 9:
         # eight meshes of this order of uneven size (the batched kernels' work lists)
         sizes = [max(1, m.E * f // 36) for f in (8, 7, 6, 5, 4, 3, 2, 1)]
@@ -210,7 +213,7 @@ def tune(orders=range(1, 16), kinds=tuple(KINDS), precs=tuple(PRECS), target_nod
                         if key not in plans:
                             tune_set(N, kind, prec, item_alt=key)
                             plans[key] = [BatchedAxLocal(meshes, list(views[q]), list(outs[q]), prec)
-                                          for q in range(2)]
+                                          for q in range(NBUF)]
                         return [p.launch for p in plans[key]]
                     times = []
                     for cfg in configs:
