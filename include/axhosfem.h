@@ -84,6 +84,22 @@ int ax_local(int64_t E, int N, int geom, const double* geo, const double* D, con
              const double* w, int nrhs, int prec, const void* X, void* Y, void* stream);
 
 /*
+ * ax_local_gathered - Y = AxLocal(Q Xg): the element-local operator applied to a global vector,
+ * the gather Q of Eq. (1) fused into the operator's load (node l of element e reads
+ * Xg[l2g[e N1^3 + l]]), so the local copy Q Xg is never stored.  This is the operator
+ * application of the CG solver (cg_solve).  l2g [dev] int32 [E*N1^3], every entry in
+ * [0, n_global) (not range-checked here: gs_build_csr checks a map); Xg [dev] [nrhs][n_global];
+ * Y [dev] [nrhs][E][N1^3]; both of the storage type of prec, AX_FP64 or AX_FP32 (AX_FP16_ACC32
+ * -> AX_ERR_UNSUPPORTED).  geom, geo, D, xi, w as ax_local; D must be a GLL differentiation
+ * matrix (centro-antisymmetric, AX_ERR_UNSUPPORTED otherwise).  The result equals gs_assemble
+ * (GS_Q) followed by ax_local bit for bit.  Errors: as ax_local, plus l2g NULL, n_global < 1 or
+ * Xg == Y -> AX_ERR_ARG.
+ */
+int ax_local_gathered(int64_t E, int N, int geom, const double* geo, const double* D, const double* xi,
+                      const double* w, int nrhs, int prec, const int32_t* l2g, int64_t n_global,
+                      const void* Xg, void* Y, void* stream);
+
+/*
  * ax_local_vector - AxLocal on a vector field (n_col = 3, Sec. 2.1: X and Y hold three columns,
  * one per component), in the component-interleaved layout X, Y [dev] [E][3][N1^3] (the three
  * components of an element contiguous).  The geometric factors are recomputed once per element

@@ -87,6 +87,7 @@ _SIGS = {
     "ax_local": (_int, [_i64, _int, _int, _vp, _vp, _vp, _vp, _int, _int, _vp, _vp, _vp]),
     "ax_local_precomputedG": (_int, [_i64, _int, _vp, _vp, _int, _int, _vp, _vp, _vp]),
     "ax_local_vector": (_int, [_i64, _int, _int, _vp, _vp, _vp, _vp, _int, _vp, _vp, _vp]),
+    "ax_local_gathered": (_int, [_i64, _int, _int, _vp, _vp, _vp, _vp, _int, _int, _vp, _i64, _vp, _vp, _vp]),
     "ax_geom_factors": (_int, [_i64, _int, _vp, _vp, _vp, _int, _vp, _vp, _vp]),
     "ax_local_partial": (_int, [_i64, _int, _vp, _vp, _vp, _vp, _vp, _int, _int, _vp, _vp, _vp]),
     "ax_geom_lambda": (_int, [_i64, _int, _vp, _vp, _vp, _int, _vp, _vp]),
@@ -215,6 +216,22 @@ def ax_local_vector(X, geo, basis: Basis, geom=AX_TRILINEAR, prec=AX_FP64, out=N
     Y = torch.empty_like(X) if out is None else out
     _check(lib().ax_local_vector(E, basis.N, geom, _dptr(geo), _np_ptr(basis.D), _np_ptr(basis.xi),
                                  _np_ptr(basis.w), prec, _dptr(X), _dptr(Y), _stream(stream)))
+    return Y
+
+
+def ax_local_gathered(Xg, l2g, geo, basis: Basis, geom=AX_TRILINEAR, prec=AX_FP64, out=None, stream=None):
+    """Y = AxLocal(Q Xg) with the gather fused into the load: Xg [nrhs][n_global] (or [n_global])
+    global device tensor, l2g int32 device tensor [E*N1^3]; returns Y [nrhs][E][N1^3]."""
+    import torch
+    E = geo.shape[0]
+    NP = (basis.N + 1) ** 3
+    ng = Xg.shape[-1]
+    nrhs = Xg.shape[0] if Xg.dim() == 2 else 1
+    assert Xg.dtype == _prec_dtype(prec) and l2g.dtype == torch.int32 and l2g.numel() == E * NP
+    Y = torch.empty((nrhs, E, NP), dtype=Xg.dtype, device=Xg.device) if out is None else out
+    _check(lib().ax_local_gathered(E, basis.N, geom, _dptr(geo), _np_ptr(basis.D), _np_ptr(basis.xi),
+                                   _np_ptr(basis.w), nrhs, prec, _dptr(l2g), ng, _dptr(Xg), _dptr(Y),
+                                   _stream(stream)))
     return Y
 
 

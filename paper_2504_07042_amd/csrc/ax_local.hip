@@ -88,6 +88,34 @@ extern "C" int ax_local(int64_t E, int N, int geom, const double* geo, const dou
     return ax_local_f16(E, N, gk, geo, nullptr, D, xi, w, nrhs, (const float*)X, (float*)Y, st);
 }
 
+extern "C" int ax_local_gathered(int64_t E, int N, int geom, const double* geo, const double* D,
+                                 const double* xi, const double* w, int nrhs, int prec, const int32_t* l2g,
+                                 int64_t n_global, const void* Xg, void* Y, void* stream)
+{
+    clear_error();
+    AX_TRY(check_common(E, N, nrhs, prec, Xg, Y, D));
+    if (prec == AX_FP16_ACC32) return fail(AX_ERR_UNSUPPORTED, "the gathering operator is FP64/FP32");
+    if (geom != AX_TRILINEAR && geom != AX_PARALLELEPIPED)
+        return fail(AX_ERR_UNSUPPORTED, "unknown geometry %d", geom);
+    if (!w) return fail(AX_ERR_ARG, "w is NULL");
+    if (geom == AX_TRILINEAR && !xi) return fail(AX_ERR_ARG, "xi is NULL (needed for trilinear)");
+    if (E == 0) return AX_OK;
+    if (!geo || !l2g) return fail(AX_ERR_ARG, "geo or l2g is NULL");
+    if (n_global < 1) return fail(AX_ERR_ARG, "n_global < 1");
+    if (!centro_antisymmetric(N + 1, D)) return fail(AX_ERR_UNSUPPORTED, "the gathering operator needs a GLL D");
+    ax_problem p{};
+    p.E = E;
+    p.N = N;
+    p.geom = geom;
+    p.geo = geo;
+    p.D = D;
+    p.xi = xi;
+    p.w = w;
+    p.n_global = n_global;
+    p.l2g = l2g;
+    return ax_local_gather(p, nrhs, prec, Xg, n_global, Y, as_stream(stream));
+}
+
 extern "C" int ax_local_precomputedG(int64_t E, int N, const void* G, const double* D, int nrhs,
                                      int prec, const void* X, void* Y, void* stream)
 {
