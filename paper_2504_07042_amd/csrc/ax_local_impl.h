@@ -155,6 +155,26 @@ __device__ __forceinline__ void rpencil_write(T* F, int j, int k, const T* o)
     }
 }
 
+// Synchronisation of the work-group between LDS phases.  A work-group of one wave (N1 = 8 with one
+// element per group) needs no hardware barrier and no wait for its LDS writes: the LDS performs the
+// accesses of one wave in issue order, so a later read by any lane sees an earlier write by any
+// lane.  Only the compiler must keep the order, which the wavefront-scope fences and the wave
+// barrier enforce; no instruction is emitted, so the wave waits on LDS only where it uses a value.
+#ifndef AX_WAVE_SYNC
+#define AX_WAVE_SYNC 1
+#endif
+template <int BLOCK>
+__device__ __forceinline__ void group_sync()
+{
+    if constexpr (AX_WAVE_SYNC && BLOCK <= 64) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 // Kernel body.  GATHER: X is a global vector [nrhs][ldg] read through the local-to-global map
 // l2g (the Q of Sec. 2.1 fused into the load), so the solver never materialises Q x.  `cs` is the
 // source of the contraction coefficients (CoefResident or CoefReload).  Local vectors: node l of
@@ -191,6 +211,7 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
     const int ra = S::rpa(lane), rb = S::rpb(lane);  // r-pencil lane (j, k)
     const int64_t nblk = (E + EPB - 1) / EPB;
     if (tid < 2 * N1) sxw[tid] = (tid & 1) ? bs.w[tid >> 1] : bs.xi[tid >> 1];
+    group_sync<BLOCK>();   // sxw is read by every wave from the first element on
     // the D-contractions: forward (D) and transposed (D^T), on the matrix cores or the vector ALU
     constexpr bool MF = use_mfma<N1, EO, T>();
     MfmaCoef<MF ? N1 : 2> kD, kT;
@@ -297,7 +318,7 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
         // the point of the item where the fewest registers are live,) t-contraction in
         // registers, then the next item's loads
         if constexpr (EARLY) {
-            __syncthreads();
+            group_sync<BLOCK>();
             if constexpr (is_trilinear(GEO)) {
                 if (c == 0) {
                     const double* sv = svert + (slot < EPB ? slot : 0) * 24;
@@ -313,7 +334,7 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
         T xn[N1];
         load_x(eb_n, c_n, xn);
         if (last_col) load_v(eb_n, vr);
-        if constexpr (!EARLY) __syncthreads();
+        if constexpr (!EARLY) group_sync<BLOCK>();
         // P1: r-pencils (j,k) -> x0 in B; s-pencils (i,k) -> x1 held in registers
         T o1[N1];
         {
@@ -325,7 +346,7 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
             for (int n = 0; n < N1; ++n) p[n] = A[S::pos(pa, n, pb)];
             fwd(p, o1);
         }
-        __syncthreads();
+        group_sync<BLOCK>();
         // P2: x1 -> A; (per-element geometry invariants of the home column from the staged vertices)
 #pragma unroll
         for (int a = 0; a < N1; ++a) A[S::pos(pa, a, pb)] = o1[a];
@@ -338,7 +359,7 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
                 tri_narrow(t64, tc);
             }
         }
-        __syncthreads();
+        group_sync<BLOCK>();
         // P3: pointwise factors at the home column; r -> B, s -> A, t stays in registers
         T tt[N1];
 #pragma unroll
@@ -388,7 +409,7 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
             for (int k = 0; k < N1; ++k) l3v[k] = l3[k * NT];
             load_x(eb, c, xv);
         }
-        __syncthreads();
+        group_sync<BLOCK>();
         // P4: D_r^T r in place on the r-pencils; D_s^T s into registers
         {
             T p[N1], o[N1];
@@ -404,7 +425,7 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
             for (int a = 0; a < N1; ++a) A[S::pos(pa, a, pb)] = o1[a];
 #endif
         }
-        __syncthreads();
+        group_sync<BLOCK>();
         if constexpr (GEO == GEO_HELM) {
 #pragma unroll
             for (int k = 0; k < N1; ++k) y2[k] = fma(l3v[k], xv[k], y2[k]);
@@ -424,7 +445,7 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
         // P5: add D_s^T s on the s-pencils
 #pragma unroll
         for (int a = 0; a < N1; ++a) B[S::pos(pa, a, pb)] += o1[a];
-        __syncthreads();
+        group_sync<BLOCK>();
         // P6: Y = (D_r^T r + D_s^T s) + D_t^T t
         if (active) {
 #pragma unroll
