@@ -76,8 +76,11 @@ int ax_gll(int N, double* xi, double* w, double* D);
  *                              ax_parallelepiped_factors).
  * D [host] double[N1*N1] (see ax_gll), xi and w [host] double[N1] (xi may be NULL for
  * AX_PARALLELEPIPED).  X [dev] read, Y [dev] fully overwritten; both [nrhs][E][N1^3] of the
- * storage type of `prec`; X and Y must not overlap.  The factors are reused across the nrhs
- * columns (Sec. 4.1).  No NaN checks are made.  Errors: E < 0, nrhs < 1, null pointers,
+ * storage type of `prec`; X and Y must not overlap.  Columns share the per-element geometric
+ * set-up (Sec. 4.1): the vertices are read and the per-column polynomial coefficients of the
+ * factors formed once per element for all nrhs columns; the per-node evaluation of the factors
+ * from those coefficients is repeated for each column (cheaper than holding seven words per node
+ * between columns).  No NaN checks are made.  Errors: E < 0, nrhs < 1, null pointers,
  * X == Y -> AX_ERR_ARG; N outside [1,15] or an unknown geom/prec -> AX_ERR_UNSUPPORTED.
  */
 int ax_local(int64_t E, int N, int geom, const double* geo, const double* D, const double* xi,
@@ -102,9 +105,10 @@ int ax_local_gathered(int64_t E, int N, int geom, const double* geo, const doubl
 /*
  * ax_local_vector - AxLocal on a vector field (n_col = 3, Sec. 2.1: X and Y hold three columns,
  * one per component), in the component-interleaved layout X, Y [dev] [E][3][N1^3] (the three
- * components of an element contiguous).  The geometric factors are recomputed once per element
- * and serve the three components (the geometry loop outermost, Sec. 4.1), so the traffic per
- * element is 2 x 3 N1^3 values plus the geometry input.  geom AX_TRILINEAR (geo = vertices) or
+ * components of an element contiguous).  The three components share the element's geometric
+ * set-up (the geometry loop outermost, Sec. 4.1: vertices read and the per-column coefficients of
+ * the factors formed once per element; the per-node evaluation repeated per component), so the
+ * traffic per element is 2 x 3 N1^3 values plus the geometry input once.  geom AX_TRILINEAR (geo = vertices) or
  * AX_PARALLELEPIPED (geo = h), prec AX_FP64 or AX_FP32 (AX_FP16_ACC32 -> AX_ERR_UNSUPPORTED);
  * other arguments and errors as ax_local.
  */

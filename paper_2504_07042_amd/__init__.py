@@ -208,7 +208,7 @@ def ax_local(X, geo, basis: Basis, geom=AX_TRILINEAR, prec=AX_FP64, out=None, st
 
 def ax_local_vector(X, geo, basis: Basis, geom=AX_TRILINEAR, prec=AX_FP64, out=None, stream=None):
     """Y = AxLocal(X) for a vector field: X [E][3][N1^3] device tensor (the three components of an
-    element contiguous), factors recomputed once per element for all three (Sec. 4.1)."""
+    element contiguous); the element's geometric set-up serves all three (Sec. 4.1)."""
     import torch
     E = geo.shape[0]
     assert X.dim() == 3 and X.shape[0] == E and X.shape[1] == 3 and X.shape[2] == (basis.N + 1) ** 3
