@@ -1,5 +1,5 @@
 """GPU parity of the vector-field operator (n_col = 3, component-interleaved [E][3][N1^3], one
-factor recomputation per element for the three components) against the oracle, which applies
+geometric set-up per element shared by the three components) against the oracle, which applies
 Eq. 3 to the three components as three columns."""
 import numpy as np
 import pytest
