@@ -131,7 +131,7 @@ extern "C" int ax_tune_get(int N, int kind, int prec, ax_tune* t)
 
 extern "C" const char* ax_last_error(void) { return g_err; }
 
-extern "C" const char* ax_version(void) { return "axhosfem 0.1 (gfx950)"; }
+extern "C" const char* ax_version(void) { return "axhosfem 0.2 (gfx950)"; }
 
 // GLL tables (Sec. 2.1, Table 1).  The interior points are the zeros of q(x) = (1-x^2) L_N'(x);
 // Newton's method uses q'(x) = -N(N+1) L_N(x) (Legendre's equation), started from the

@@ -409,6 +409,9 @@ extern "C" int ax_local_batched(const ax_batch_plan* plan, const void* workspace
     clear_error();
     if (!plan || !workspace) return fail(AX_ERR_ARG, "plan or workspace is NULL");
     if (plan->prec != AX_FP64 && plan->prec != AX_FP32) return fail(AX_ERR_ARG, "plan was not filled by ax_batched_prepare");
+    for (int N1 = 2; N1 <= kBMaxN1; ++N1)
+        if (plan->order_variant[N1] != 0 && plan->order_variant[N1] != 1)
+            return fail(AX_ERR_ARG, "plan was not filled by ax_batched_prepare (shape variant %d)", plan->order_variant[N1]);
     if (plan->n_items == 0) return AX_OK;
     BHeader h{};
     h.off_mesh = h.off_items = h.off_basis = 0;

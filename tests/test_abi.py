@@ -246,6 +246,17 @@ def test_probe_validation(ax):
     assert L.ax_probe_compute(0, 10, ctypes.c_void_p(16), None, None) == ax.AX_ERR_ARG
 
 
+def test_batched_launch_rejects_foreign_plan(ax):
+    """A plan whose shape variants were not written by ax_batched_prepare is refused on the host."""
+    L = ax.lib()
+    plan = ax.AxBatchPlan()
+    plan.prec = ax.AX_FP64
+    plan.n_items = 5
+    plan.order_variant[4] = 7
+    assert L.ax_local_batched(ctypes.byref(plan), ctypes.c_void_p(256), None) == ax.AX_ERR_ARG
+    assert b"shape variant" in L.ax_last_error()
+
+
 def test_check_mesh_validation(ax):
     L = ax.lib()
     b = ax.Basis(3)
