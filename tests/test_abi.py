@@ -273,3 +273,31 @@ def test_check_mesh_validation(ax):
     bad.value = 5
     assert L.ax_check_mesh(0, 3, None, xi, ctypes.byref(bad), ctypes.byref(dmin), None) == ax.AX_OK
     assert bad.value == -1 and dmin.value == float("inf")
+
+
+def test_tuning_cache_load_is_tolerant(ax, tmp_path):
+    """The cache loader applies valid entries, skips entries of another format or an unknown kind,
+    and reports whether the cache was measured on the present kernel sources."""
+    import json
+    from paper_2504_07042_amd import autotune
+    K, P = ax.AX_TUNE_TRILINEAR, ax.AX_FP64
+    before = autotune.tune_get(5, K, P)
+    path = tmp_path / "cache.json"
+    entries = [
+        {"N": 5, "kind": "trilinear", "prec": "fp64", "kernel": ax.AX_KERNEL_TILE, "tile_alt": 1, "item_alt": 0,
+         "waves_alt": 0, "grid_mult": 4},
+        {"N": 5, "geom": "trilinear", "prec": "fp64", "epb_alt": 1, "grid_mult": 4},       # older format
+        {"N": 5, "kind": "nonsense", "prec": "fp64", "kernel": 0, "grid_mult": 1},
+        {"N": 5, "kind": "stored", "prec": "fp64", "kernel": 0, "tile_alt": 0, "item_alt": 0,
+         "waves_alt": 0, "grid_mult": 99},                                                   # invalid value
+    ]
+    path.write_text(json.dumps({"arch": "gfx950", "sources_sha256": "0" * 64, "entries": entries}))
+    try:
+        assert autotune.load(str(path)) == 1
+        t = autotune.tune_get(5, K, P)
+        assert (t["kernel_used"], t["tile_alt"], t["grid_mult"]) == (ax.AX_KERNEL_TILE, 1, 4)
+        assert autotune.cache_status(str(path)) == "stale"
+        assert autotune.cache_status(str(tmp_path / "absent.json")) == "absent"
+    finally:
+        autotune.tune_set(5, K, P, **{k: before[k] for k in autotune.KNOBS})
+    assert autotune.tune_get(5, K, P) == before
