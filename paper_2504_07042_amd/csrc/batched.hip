@@ -332,18 +332,38 @@ extern "C" int ax_batched_workspace_bytes(int n_mesh, const ax_problem* meshes, 
     return AX_OK;
 }
 
-extern "C" int ax_batched_prepare(int n_mesh, const ax_problem* meshes, int nrhs, int prec,
-                                  const void* const* X, void* const* Y, const int64_t* col_stride,
-                                  void* workspace, size_t workspace_bytes, ax_batch_plan* plan)
+// Workspace offsets of a prepared plan (a pure function of it, as batched_prepare laid them out).
+static BHeader plan_header(const ax_batch_plan* plan)
 {
-    clear_error();
+    BHeader h{};
+    auto up = [](int64_t v) { return (v + 255) & ~int64_t(255); };
+    h.off_mesh = up(sizeof(BHeader));
+    h.off_items = up(h.off_mesh + (int64_t)plan->n_mesh * sizeof(BMesh));
+    h.off_basis = up(h.off_items + plan->n_items * (int64_t)sizeof(BItem));
+    h.nrhs = plan->nrhs;
+    return h;
+}
+
+__global__ void __launch_bounds__(256) set_source_kernel(BMesh* __restrict__ meshes, int n_mesh, const void* xg)
+{
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    if (q < n_mesh) meshes[q].X = xg;
+}
+
+// l2g == nullptr: X[q] local vectors as Y.  Otherwise the gathering form: mesh q reads a global
+// vector (its address set by batched_set_source, X unused) through l2g + lbase[q], columns ldg
+// values apart.
+static int batched_prepare(int n_mesh, const ax_problem* meshes, int nrhs, int prec, const void* const* X,
+                           void* const* Y, const int64_t* col_stride, const int32_t* l2g, const int64_t* lbase,
+                           int64_t ldg, void* workspace, size_t workspace_bytes, ax_batch_plan* plan)
+{
     if (!plan) return fail(AX_ERR_ARG, "plan is NULL");
     std::memset(plan, 0, sizeof(*plan));
     AX_TRY(check_meshes(n_mesh, meshes));
     if (nrhs < 1) return fail(AX_ERR_ARG, "nrhs < 1");
     if (prec != AX_FP64 && prec != AX_FP32) return fail(AX_ERR_UNSUPPORTED, "batched precision must be FP64 or FP32");
     if (!workspace) return fail(AX_ERR_ARG, "workspace is NULL");
-    AX_TRY(check_io(n_mesh, meshes, X, Y, col_stride));
+    if (!l2g) AX_TRY(check_io(n_mesh, meshes, X, Y, col_stride));
     for (int N1 = 2; N1 <= kBMaxN1; ++N1) plan->order_variant[N1] = order_variant(N1, prec);
     const int64_t n_items = n_items_of(n_mesh, meshes, prec);
     BHeader h{};
@@ -360,7 +380,8 @@ extern "C" int ax_batched_prepare(int n_mesh, const ax_problem* meshes, int nrhs
         const int64_t np = (int64_t)(meshes[q].N + 1) * (meshes[q].N + 1) * (meshes[q].N + 1);
         const int64_t ld = col_stride ? col_stride[q] : meshes[q].E * np;
         if (ld < meshes[q].E * np) return fail(AX_ERR_ARG, "mesh %d: column stride below E*N1^3", q);
-        bm[q] = BMesh{meshes[q].E, ld, meshes[q].geo, X[q], Y[q], meshes[q].N + 1, 0, np};
+        bm[q] = BMesh{meshes[q].E, ld, meshes[q].geo, l2g ? nullptr : X[q], Y[q], meshes[q].N + 1, 0, np,
+                      l2g ? l2g + lbase[q] : nullptr, ldg};
     }
     // items grouped by order (one persistent kernel each), meshes of an order largest first
     std::vector<BItem> items;
@@ -402,6 +423,41 @@ extern "C" int ax_batched_prepare(int n_mesh, const ax_problem* meshes, int nrhs
     plan->prec = prec;
     plan->bytes = (size_t)h.bytes;
     return AX_OK;
+}
+
+namespace ax {
+
+// Internal (the batched CG): a plan in the gathering form, every mesh reading the global vector
+// set by batched_set_source through l2g + lbase[q] (columns n_global apart) and writing its local
+// result to Y[q] (columns ldy[q] apart).
+int batched_prepare_gather(int n_mesh, const ax_problem* meshes, int nrhs, int prec, const int32_t* l2g,
+                           const int64_t* lbase, int64_t n_global, void* const* Y, const int64_t* ldy, void* ws,
+                           size_t bytes, ax_batch_plan* plan)
+{
+    if (!l2g || !lbase || !Y || !ldy) return fail(AX_ERR_ARG, "internal: NULL gather arguments");
+    return batched_prepare(n_mesh, meshes, nrhs, prec, nullptr, Y, ldy, l2g, lbase, n_global, ws, bytes, plan);
+}
+
+// Point every mesh of a gathering plan at the global vector xg (one small kernel: capturable).
+int batched_set_source(const ax_batch_plan* plan, void* ws, const void* xg, hipStream_t st)
+{
+    if (plan->n_mesh == 0) return AX_OK;
+    const BHeader h = plan_header(plan);
+    BMesh* m = reinterpret_cast<BMesh*>(static_cast<char*>(ws) + h.off_mesh);
+    hipLaunchKernelGGL(set_source_kernel, dim3((unsigned)((plan->n_mesh + 255) / 256)), dim3(256), 0, st, m,
+                       plan->n_mesh, xg);
+    return hip_check(hipGetLastError(), "batched source");
+}
+
+}  // namespace ax
+
+extern "C" int ax_batched_prepare(int n_mesh, const ax_problem* meshes, int nrhs, int prec,
+                                  const void* const* X, void* const* Y, const int64_t* col_stride,
+                                  void* workspace, size_t workspace_bytes, ax_batch_plan* plan)
+{
+    clear_error();
+    return batched_prepare(n_mesh, meshes, nrhs, prec, X, Y, col_stride, nullptr, nullptr, 0, workspace,
+                           workspace_bytes, plan);
 }
 
 extern "C" int ax_local_batched(const ax_batch_plan* plan, const void* workspace, void* stream)

@@ -21,6 +21,10 @@ int gs_apply(int64_t n_local, int64_t n_global, const int32_t* l2g, const int64_
              const int32_t* gidx, const uint8_t* mask, int mode, int nrhs, int dtype, const void* in,
              void* out, hipStream_t st);
 int ax_local_gather(const ax_problem& p, int nrhs, int prec, const void* xg, int64_t ldg, void* Y, hipStream_t st);
+int batched_prepare_gather(int n_mesh, const ax_problem* meshes, int nrhs, int prec, const int32_t* l2g,
+                           const int64_t* lbase, int64_t n_global, void* const* Y, const int64_t* ldy, void* ws,
+                           size_t bytes, ax_batch_plan* plan);
+int batched_set_source(const ax_batch_plan* plan, void* ws, const void* xg, hipStream_t st);
 
 constexpr int kRedBlocks = 4096;  // partial sums per dot product and column (fixed grid)
 constexpr int kRedThreads = 256;
@@ -498,6 +502,7 @@ struct Operator {
     const void* ws64 = nullptr;
     const ax_batch_plan* plan32 = nullptr;
     const void* ws32 = nullptr;
+    bool batched_gather = false;    // the batched plans read the global vector through l2g
     const double* dinv64 = nullptr;  // Jacobi preconditioner (NULL: none)
     const float* dinv32 = nullptr;
 };
@@ -519,19 +524,30 @@ static const T* op_dinv(const Operator& op)
 #ifndef AX_CG_GATHER
 #define AX_CG_GATHER 1
 #endif
+// The same for the batched operator of cg_solve_batched: every mesh's per-item kernel reads the
+// global vector through its part of the union's local-to-global map.
+#ifndef AX_CG_GATHER_BATCHED
+#define AX_CG_GATHER_BATCHED 1
+#endif
 template <typename T>
 static int apply_local(const Operator& op, int nrhs, int prec, const T* x, T* xl, T* yl, hipStream_t st)
 {
     const int dt = sizeof(T) == 8 ? AX_FP64 : AX_FP32;
     if (AX_CG_GATHER && op.p && prec != AX_FP16_ACC32 && centro_antisymmetric(op.p->N + 1, op.p->D))
         return ax_local_gather(*op.p, nrhs, prec, x, op.n_global, yl, st);
-    AX_TRY(gs_apply(op.n_local, op.n_global, op.l2g, op.gptr, op.gidx, nullptr, GS_Q, nrhs, dt, x, xl, st));
+    if (!op.batched_gather)
+        AX_TRY(gs_apply(op.n_local, op.n_global, op.l2g, op.gptr, op.gidx, nullptr, GS_Q, nrhs, dt, x, xl, st));
     if (op.p) {
         const ax_problem& pb = *op.p;
         return ax_local(pb.E, pb.N, pb.geom, pb.geo, pb.D, pb.xi, pb.w, nrhs, prec, xl, yl, st);
     }
-    if (sizeof(T) == 8) return ax_local_batched(op.plan64, op.ws64, st);
-    return ax_local_batched(op.plan32, op.ws32, st);
+    const ax_batch_plan* plan = sizeof(T) == 8 ? op.plan64 : op.plan32;
+    void* ws = const_cast<void*>(sizeof(T) == 8 ? op.ws64 : op.ws32);
+    if (op.batched_gather) {
+        AX_TRY(batched_set_source(plan, ws, x, st));
+        return ax_local_batched(plan, ws, st);
+    }
+    return ax_local_batched(plan, ws, st);
 }
 
 template <typename T>
@@ -1066,13 +1082,22 @@ extern "C" int cg_solve_batched(int n_mesh, const ax_problem* meshes, int64_t n_
         xs[q] = w.pl + lbase[q];
         ys[q] = w.wl + lbase[q];
     }
-    AX_TRY(ax_batched_prepare(n_mesh, meshes, nrhs, AX_FP64, xs.data(), ys.data(), ld.data(), ws64, bw, &plan64));
+    if (AX_CG_GATHER_BATCHED)
+        AX_TRY(batched_prepare_gather(n_mesh, meshes, nrhs, AX_FP64, l2g, lbase.data(), n_global, ys.data(),
+                                      ld.data(), ws64, bw, &plan64));
+    else
+        AX_TRY(ax_batched_prepare(n_mesh, meshes, nrhs, AX_FP64, xs.data(), ys.data(), ld.data(), ws64, bw, &plan64));
     if (mixed) {
         for (int q = 0; q < n_mesh; ++q) {
             xs[q] = w.pl32 + lbase[q];
             ys[q] = w.wl32 + lbase[q];
         }
-        AX_TRY(ax_batched_prepare(n_mesh, meshes, nrhs, AX_FP32, xs.data(), ys.data(), ld.data(), ws32, bw, &plan32));
+        if (AX_CG_GATHER_BATCHED)
+            AX_TRY(batched_prepare_gather(n_mesh, meshes, nrhs, AX_FP32, l2g, lbase.data(), n_global, ys.data(),
+                                          ld.data(), ws32, bw, &plan32));
+        else
+            AX_TRY(ax_batched_prepare(n_mesh, meshes, nrhs, AX_FP32, xs.data(), ys.data(), ld.data(), ws32, bw,
+                                      &plan32));
     }
     Operator op;
     op.n_local = nl;
@@ -1085,6 +1110,7 @@ extern "C" int cg_solve_batched(int n_mesh, const ax_problem* meshes, int64_t n_
     op.ws64 = ws64;
     op.plan32 = &plan32;
     op.ws32 = ws32;
+    op.batched_gather = AX_CG_GATHER_BATCHED != 0;
     hipLaunchKernelGGL(copy_pairs_kernel, dim3(vgrid(n_global)), dim3(256), 0, st, w.pairs, gptr, gidx, mask,
                        n_global);
     op.pairs = w.pairs;

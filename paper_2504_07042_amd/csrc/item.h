@@ -26,6 +26,10 @@ struct BMesh {
     int N1;
     int pad;
     int64_t es;  // stride between elements of X and Y (values): N1^3, or ncol N1^3 interleaved
+    // gathering form: X is a global vector read through l2g (this mesh's part of the map, local
+    // element-major numbering), columns ldg values apart; nullptr: X is local like Y
+    const int32_t* l2g;
+    int64_t ldg;
 };
 
 struct BItem {
@@ -87,8 +91,18 @@ __device__ __forceinline__ void batched_item(const BMesh& m, int64_t eb, int nrh
     for (int c = 0; c < nrhs; ++c) {
         const int64_t base = (int64_t)c * m.ld + (active ? e : 0) * m.es;
         T xr[N1], x2[N1];
+        if (m.l2g) {
+            const int32_t* lm = m.l2g + (active ? e : 0) * NP + i + j * N1;
+            int32_t gi[N1];
 #pragma unroll
-        for (int k = 0; k < N1; ++k) xr[k] = active ? X[base + i + j * N1 + k * NT] : T(0);
+            for (int k = 0; k < N1; ++k) gi[k] = active ? lm[k * NT] : 0;
+            const T* xc = X + (int64_t)c * m.ldg;
+#pragma unroll
+            for (int k = 0; k < N1; ++k) xr[k] = active ? xc[gi[k]] : T(0);
+        } else {
+#pragma unroll
+            for (int k = 0; k < N1; ++k) xr[k] = active ? X[base + i + j * N1 + k * NT] : T(0);
+        }
         if (inslot) {
 #pragma unroll
             for (int k = 0; k < N1; ++k) A[Shape<N1, sizeof(T)>::pos(i, j, k)] = xr[k];
