@@ -405,7 +405,7 @@ typedef struct {
     int prec;         /* AX_FP64 or AX_FP32 */
     size_t bytes;     /* workspace bytes in use */
     int n_mesh;
-    int pad;
+    int gather;       /* 0 (internal use: 1 for the solver's plans reading a global vector) */
     int64_t order_first[11];  /* items of order N1 = N + 1 (2..10): [order_first[N1], +order_count[N1]) */
     int64_t order_count[11];
     int order_variant[11];    /* work-group shape of order N1 (ax_tune.item_alt at prepare time) */

@@ -60,7 +60,7 @@ class AxCgOpts(ctypes.Structure):
 
 class AxBatchPlan(ctypes.Structure):
     _fields_ = [("n_items", _i64), ("nrhs", _int), ("prec", _int), ("bytes", ctypes.c_size_t),
-                ("n_mesh", _int), ("pad", _int), ("order_first", _i64 * 11), ("order_count", _i64 * 11),
+                ("n_mesh", _int), ("gather", _int), ("order_first", _i64 * 11), ("order_count", _i64 * 11),
                 ("order_variant", _int * 11)]
 
 

@@ -29,7 +29,7 @@ struct BHeader {
 };
 
 // Per-order persistent kernel over the items [0, n) of one order, in shape variant V.
-template <int N1, typename T, int V>
+template <int N1, typename T, int V, bool G>
 __global__ void __launch_bounds__((BShape<N1, V>::BLOCK), (batch_waves(sizeof(T) == 4)))
 order_item_kernel(const BItem* __restrict__ items, const BMesh* __restrict__ meshes, int64_t n, int nrhs,
                   const Basis<T>* __restrict__ bsp)
@@ -39,7 +39,7 @@ order_item_kernel(const BItem* __restrict__ items, const BMesh* __restrict__ mes
     const CoefReload<T> cs{as_constant(bsp)};
     for (int64_t it = blockIdx.x; it < n; it += gridDim.x) {
         const BItem q = items[it];
-        batched_item<N1, V, T>(meshes[q.mesh], q.eb, nrhs, cs, lds);
+        batched_item<N1, V, T, false, G>(meshes[q.mesh], q.eb, nrhs, cs, lds);
     }
 }
 
@@ -52,7 +52,7 @@ static int order_variant(int N1, int prec)
     return item_has_alt(N1) ? tune_get(N1, TUNE_BATCHED, prec).item_alt : 0;
 }
 
-template <int N1, typename T, int V>
+template <int N1, typename T, int V, bool G>
 static int order_launch(const char* ws, const BHeader& h, int64_t first, int64_t count, hipStream_t st)
 {
     const BItem* items = reinterpret_cast<const BItem*>(ws + h.off_items) + first;
@@ -64,7 +64,7 @@ static int order_launch(const char* ws, const BHeader& h, int64_t first, int64_t
         int dev = 0, c = 256, q = 0;
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev);
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&q, order_item_kernel<N1, T, V>, BShape<N1, V>::BLOCK, 0) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&q, order_item_kernel<N1, T, V, G>, BShape<N1, V>::BLOCK, 0) !=
                 hipSuccess ||
             q < 1)
             q = 1;
@@ -73,32 +73,37 @@ static int order_launch(const char* ws, const BHeader& h, int64_t first, int64_t
     }
     const int64_t cap = (int64_t)cus * per * (tu.grid_mult > 0 ? tu.grid_mult : 1);
     const unsigned grid = (unsigned)std::min<int64_t>(count, cap);
-    hipLaunchKernelGGL((order_item_kernel<N1, T, V>), dim3(grid), dim3(BShape<N1, V>::BLOCK), 0, st, items, meshes,
+    hipLaunchKernelGGL((order_item_kernel<N1, T, V, G>), dim3(grid), dim3(BShape<N1, V>::BLOCK), 0, st, items, meshes,
                        count, h.nrhs, bsp);
     return hip_check(hipGetLastError(), "batched launch");
 }
 
 template <int N1, typename T>
-static int order_launch_v(int V, const char* ws, const BHeader& h, int64_t first, int64_t count, hipStream_t st)
+static int order_launch_v(int V, bool G, const char* ws, const BHeader& h, int64_t first, int64_t count,
+                          hipStream_t st)
 {
-    return V ? order_launch<N1, T, 1>(ws, h, first, count, st) : order_launch<N1, T, 0>(ws, h, first, count, st);
+    if (G)
+        return V ? order_launch<N1, T, 1, true>(ws, h, first, count, st)
+                 : order_launch<N1, T, 0, true>(ws, h, first, count, st);
+    return V ? order_launch<N1, T, 1, false>(ws, h, first, count, st)
+             : order_launch<N1, T, 0, false>(ws, h, first, count, st);
 }
 
-// V: the shape variant the work list of this order was built with.
+// V: the shape variant the work list of this order was built with; G: the gathering form.
 template <typename T>
-static int order_dispatch(int N1, int V, const char* ws, const BHeader& h, int64_t first, int64_t count,
+static int order_dispatch(int N1, int V, bool G, const char* ws, const BHeader& h, int64_t first, int64_t count,
                           hipStream_t st)
 {
     switch (N1) {
-    case 2: return order_launch_v<2, T>(V, ws, h, first, count, st);
-    case 3: return order_launch_v<3, T>(V, ws, h, first, count, st);
-    case 4: return order_launch_v<4, T>(V, ws, h, first, count, st);
-    case 5: return order_launch_v<5, T>(V, ws, h, first, count, st);
-    case 6: return order_launch_v<6, T>(V, ws, h, first, count, st);
-    case 7: return order_launch_v<7, T>(V, ws, h, first, count, st);
-    case 8: return order_launch_v<8, T>(V, ws, h, first, count, st);
-    case 9: return order_launch_v<9, T>(V, ws, h, first, count, st);
-    default: return order_launch_v<10, T>(V, ws, h, first, count, st);
+    case 2: return order_launch_v<2, T>(V, G, ws, h, first, count, st);
+    case 3: return order_launch_v<3, T>(V, G, ws, h, first, count, st);
+    case 4: return order_launch_v<4, T>(V, G, ws, h, first, count, st);
+    case 5: return order_launch_v<5, T>(V, G, ws, h, first, count, st);
+    case 6: return order_launch_v<6, T>(V, G, ws, h, first, count, st);
+    case 7: return order_launch_v<7, T>(V, G, ws, h, first, count, st);
+    case 8: return order_launch_v<8, T>(V, G, ws, h, first, count, st);
+    case 9: return order_launch_v<9, T>(V, G, ws, h, first, count, st);
+    default: return order_launch_v<10, T>(V, G, ws, h, first, count, st);
     }
 }
 
@@ -302,9 +307,11 @@ static int batched_noalloc(int n_mesh, const ax_problem* meshes, int nrhs, int p
     for (int N1 = 2; N1 <= kBMaxN1; ++N1) {
         if (plan.order_count[N1] == 0) continue;
         if (prec == AX_FP64)
-            AX_TRY(order_dispatch<double>(N1, var[N1], base, h, plan.order_first[N1], plan.order_count[N1], st));
+            AX_TRY(order_dispatch<double>(N1, var[N1], false, base, h, plan.order_first[N1], plan.order_count[N1],
+                                          st));
         else
-            AX_TRY(order_dispatch<float>(N1, var[N1], base, h, plan.order_first[N1], plan.order_count[N1], st));
+            AX_TRY(order_dispatch<float>(N1, var[N1], false, base, h, plan.order_first[N1], plan.order_count[N1],
+                                         st));
     }
     return AX_OK;
 }
@@ -418,6 +425,7 @@ static int batched_prepare(int n_mesh, const ax_problem* meshes, int nrhs, int p
     AX_TRY(hip_check(hipMemcpy(workspace, host.data(), (size_t)h.bytes, hipMemcpyHostToDevice),
                      "batched workspace upload"));
     plan->n_items = n_items;
+    plan->gather = l2g ? 1 : 0;
     plan->n_mesh = n_mesh;
     plan->nrhs = nrhs;
     plan->prec = prec;
@@ -468,6 +476,7 @@ extern "C" int ax_local_batched(const ax_batch_plan* plan, const void* workspace
     for (int N1 = 2; N1 <= kBMaxN1; ++N1)
         if (plan->order_variant[N1] != 0 && plan->order_variant[N1] != 1)
             return fail(AX_ERR_ARG, "plan was not filled by ax_batched_prepare (shape variant %d)", plan->order_variant[N1]);
+    if (plan->gather != 0 && plan->gather != 1) return fail(AX_ERR_ARG, "plan was not filled by ax_batched_prepare");
     if (plan->n_items == 0) return AX_OK;
     BHeader h{};
     h.off_mesh = h.off_items = h.off_basis = 0;
@@ -483,11 +492,11 @@ extern "C" int ax_local_batched(const ax_batch_plan* plan, const void* workspace
     for (int N1 = 2; N1 <= kBMaxN1; ++N1) {
         if (plan->order_count[N1] == 0) continue;
         if (plan->prec == AX_FP64)
-            AX_TRY(order_dispatch<double>(N1, plan->order_variant[N1], (const char*)workspace, h,
-                                          plan->order_first[N1], plan->order_count[N1], st));
+            AX_TRY(order_dispatch<double>(N1, plan->order_variant[N1], plan->gather != 0, (const char*)workspace,
+                                          h, plan->order_first[N1], plan->order_count[N1], st));
         else
-            AX_TRY(order_dispatch<float>(N1, plan->order_variant[N1], (const char*)workspace, h,
-                                         plan->order_first[N1], plan->order_count[N1], st));
+            AX_TRY(order_dispatch<float>(N1, plan->order_variant[N1], plan->gather != 0, (const char*)workspace,
+                                         h, plan->order_first[N1], plan->order_count[N1], st));
     }
     return AX_OK;
 }

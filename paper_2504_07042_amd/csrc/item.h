@@ -26,8 +26,8 @@ struct BMesh {
     int N1;
     int pad;
     int64_t es;  // stride between elements of X and Y (values): N1^3, or ncol N1^3 interleaved
-    // gathering form: X is a global vector read through l2g (this mesh's part of the map, local
-    // element-major numbering), columns ldg values apart; nullptr: X is local like Y
+    // gathering form (kernels instantiated with GATHER): X is a global vector read through l2g
+    // (this mesh's part of the map, local element-major numbering), columns ldg values apart
     const int32_t* l2g;
     int64_t ldg;
 };
@@ -54,7 +54,7 @@ struct BShape {
 
 // cs: source of the basis tables (CoefResident or CoefReload)
 // PL: partial recomputation (Sec. 4.2.2), the per-node scale read from lam [E][N1^3].
-template <int N1, int V, typename T, bool PL = false, typename C>
+template <int N1, int V, typename T, bool PL = false, bool GATHER = false, typename C>
 __device__ __forceinline__ void batched_item(const BMesh& m, int64_t eb, int nrhs, const C& cs, char* lds,
                                              const T* __restrict__ lamp = nullptr)
 {
@@ -91,7 +91,7 @@ __device__ __forceinline__ void batched_item(const BMesh& m, int64_t eb, int nrh
     for (int c = 0; c < nrhs; ++c) {
         const int64_t base = (int64_t)c * m.ld + (active ? e : 0) * m.es;
         T xr[N1], x2[N1];
-        if (m.l2g) {
+        if constexpr (GATHER) {
             const int32_t* lm = m.l2g + (active ? e : 0) * NP + i + j * N1;
             int32_t gi[N1];
 #pragma unroll
