@@ -163,6 +163,20 @@ __device__ __forceinline__ void rpencil_write(T* F, int j, int k, const T* o)
 #ifndef AX_WAVE_SYNC
 #define AX_WAVE_SYNC 1
 #endif
+// Reading the s-pencil before the r-contraction of the same phase (so that its LDS latency
+// overlaps the r-contraction) costs 16 or 8 live registers.  Measured on gfx950 at N1 = 8
+// (interleaved): FP64 partial recomputation +8 %, FP32 trilinear and parallelepiped +4 %, FP64
+// trilinear -8 %, FP64 parallelepiped -2 %; the other orders within 1-2 %.  AX_S_HOIST forces it
+// on (1) or off (0) everywhere; by default it is used where it measured faster.
+#ifndef AX_S_HOIST
+#define AX_S_HOIST -1
+#endif
+template <int N1, int GEO, typename T>
+constexpr bool s_hoist()
+{
+    if constexpr (AX_S_HOIST >= 0) return AX_S_HOIST != 0;
+    return N1 == 8 && (sizeof(T) == 4 ? (GEO == GEO_TRI || GEO == GEO_PARA) : GEO == GEO_TRIL);
+}
 template <int BLOCK>
 __device__ __forceinline__ void group_sync()
 {
@@ -340,11 +354,21 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
         {
             T p[N1], o[N1];
             rpencil_read<S>(A, ra, rb, p);
-            fwd(p, o);
-            rpencil_write<S>(B, ra, rb, o);
+            if constexpr (s_hoist<N1, GEO, T>()) {
+                // the s-pencil is read before the r-contraction so that its latency overlaps it
+                T q[N1];
 #pragma unroll
-            for (int n = 0; n < N1; ++n) p[n] = A[S::pos(pa, n, pb)];
-            fwd(p, o1);
+                for (int n = 0; n < N1; ++n) q[n] = A[S::pos(pa, n, pb)];
+                fwd(p, o);
+                rpencil_write<S>(B, ra, rb, o);
+                fwd(q, o1);
+            } else {
+                fwd(p, o);
+                rpencil_write<S>(B, ra, rb, o);
+#pragma unroll
+                for (int n = 0; n < N1; ++n) p[n] = A[S::pos(pa, n, pb)];
+                fwd(p, o1);
+            }
         }
         group_sync<BLOCK>();
         // P2: x1 -> A; (per-element geometry invariants of the home column from the staged vertices)
@@ -414,11 +438,20 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
         {
             T p[N1], o[N1];
             rpencil_read<S>(B, ra, rb, p);
-            bwd(p, o);
-            rpencil_write<S>(B, ra, rb, o);
+            if constexpr (s_hoist<N1, GEO, T>()) {
+                T q[N1];
 #pragma unroll
-            for (int n = 0; n < N1; ++n) p[n] = A[S::pos(pa, n, pb)];
-            bwd(p, o1);
+                for (int n = 0; n < N1; ++n) q[n] = A[S::pos(pa, n, pb)];
+                bwd(p, o);
+                rpencil_write<S>(B, ra, rb, o);
+                bwd(q, o1);
+            } else {
+                bwd(p, o);
+                rpencil_write<S>(B, ra, rb, o);
+#pragma unroll
+                for (int n = 0; n < N1; ++n) p[n] = A[S::pos(pa, n, pb)];
+                bwd(p, o1);
+            }
 #if AX_MERGE_RS
             // each s-pencil is read and written by its own lane only
 #pragma unroll
