@@ -166,16 +166,23 @@ __device__ __forceinline__ void rpencil_write(T* F, int j, int k, const T* o)
 // Reading the s-pencil before the r-contraction of the same phase (so that its LDS latency
 // overlaps the r-contraction) costs 16 or 8 live registers.  Measured on gfx950 at N1 = 8
 // (interleaved): FP64 partial recomputation +8 %, FP32 trilinear and parallelepiped +4 %, FP64
-// trilinear -8 %, FP64 parallelepiped -2 %; the other orders within 1-2 %.  AX_S_HOIST forces it
+// trilinear -8 % in both phases, FP64 parallelepiped -2 %; the other orders within 1-2 %.  AX_S_HOIST forces it
 // on (1) or off (0) everywhere; by default it is used where it measured faster.
 #ifndef AX_S_HOIST
 #define AX_S_HOIST -1
 #endif
+// FP64 trilinear: in the forward phase only (measured +0.9 % at N1 = 8; in the transposed phase
+// -10 %)
+#ifndef AX_S_HOIST_F64_TRI
+#define AX_S_HOIST_F64_TRI 1
+#endif
+// bit 0: the forward phase, bit 1: the transposed phase
 template <int N1, int GEO, typename T>
-constexpr bool s_hoist()
+constexpr int s_hoist()
 {
-    if constexpr (AX_S_HOIST >= 0) return AX_S_HOIST != 0;
-    return N1 == 8 && (sizeof(T) == 4 ? (GEO == GEO_TRI || GEO == GEO_PARA) : GEO == GEO_TRIL);
+    if constexpr (AX_S_HOIST >= 0) return AX_S_HOIST != 0 ? 3 : 0;
+    if constexpr (N1 == 8 && sizeof(T) == 8 && GEO == GEO_TRI) return AX_S_HOIST_F64_TRI;
+    return N1 == 8 && (sizeof(T) == 4 ? (GEO == GEO_TRI || GEO == GEO_PARA) : GEO == GEO_TRIL) ? 3 : 0;
 }
 template <int BLOCK>
 __device__ __forceinline__ void group_sync()
@@ -354,7 +361,7 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
         {
             T p[N1], o[N1];
             rpencil_read<S>(A, ra, rb, p);
-            if constexpr (s_hoist<N1, GEO, T>()) {
+            if constexpr ((s_hoist<N1, GEO, T>() & 1) != 0) {
                 // the s-pencil is read before the r-contraction so that its latency overlaps it
                 T q[N1];
 #pragma unroll
@@ -438,7 +445,7 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
         {
             T p[N1], o[N1];
             rpencil_read<S>(B, ra, rb, p);
-            if constexpr (s_hoist<N1, GEO, T>()) {
+            if constexpr ((s_hoist<N1, GEO, T>() & 2) != 0) {
                 T q[N1];
 #pragma unroll
                 for (int n = 0; n < N1; ++n) q[n] = A[S::pos(pa, n, pb)];
