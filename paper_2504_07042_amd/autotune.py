@@ -124,13 +124,13 @@ def _variants(N: int, kind: int, prec: int):
     return out
 
 
-def _time_configs(fns, configs, apply, rounds=3, reps=12, warmup=4):
+def _time_configs(fns, cands, apply, rounds=3, reps=12, warmup=4):
     """Interleaved timing: each round times every config; the best round per config counts."""
     import torch
-    best = [float("inf")] * len(configs)
+    best = [float("inf")] * len(cands)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     for _ in range(rounds):
-        for q, cfg in enumerate(configs):
+        for q, cfg in enumerate(cands):
             apply(cfg)
             for w in range(warmup):
                 fns[w % len(fns)]()
@@ -207,8 +207,8 @@ def tune(orders=range(1, 16), kinds=tuple(KINDS), precs=tuple(PRECS), target_nod
                     continue
                 kind = KINDS[kname]
                 variants = _variants(N, kind, prec)
-                configs = [dict(v, grid_mult=g) for v in variants for g in GRID_MULTS]
-                configs.insert(0, dict(DEFAULT))
+                cands = [dict(v, grid_mult=g) for v in variants for g in GRID_MULTS]
+                cands.insert(0, dict(DEFAULT))
                 if kname == "batched":
                     meshes, views, outs = work["batched"]
                     plans = {}
@@ -221,21 +221,21 @@ def tune(orders=range(1, 16), kinds=tuple(KINDS), precs=tuple(PRECS), target_nod
                                           for q in range(NBUF)]
                         return [p.launch for p in plans[key]]
                     times = []
-                    for cfg in configs:
+                    for cfg in cands:
                         fns = fn_for(cfg)
                         times.append(_time_configs(fns, [cfg], lambda c: tune_set(N, kind, prec, **c))[0])
                     del plans
                 else:
-                    times = _time_configs(work[kname], configs, lambda c: tune_set(N, kind, prec, **c))
+                    times = _time_configs(work[kname], cands, lambda c: tune_set(N, kind, prec, **c))
                 t_def = times[0]
-                q = min(range(len(configs)), key=lambda i: times[i])
-                chosen = configs[q] if times[q] < (1.0 - MARGIN) * t_def else configs[0]
-                t_best = times[q] if chosen is configs[q] else t_def
+                q = min(range(len(cands)), key=lambda i: times[i])
+                chosen = cands[q] if times[q] < (1.0 - MARGIN) * t_def else cands[0]
+                t_best = times[q] if chosen is cands[q] else t_def
                 tune_set(N, kind, prec, **chosen)
                 info = tune_get(N, kind, prec)
                 ent = {"N": N, "kind": kname, "prec": pname, **{k: info[k] for k in KNOBS},
                        "kernel_used": info["kernel_used"], "elems_per_group": info["elems_per_group"],
-                       "block": info["block"], "waves": info["waves"], "variants_timed": len(configs),
+                       "block": info["block"], "waves": info["waves"], "variants_timed": len(cands),
                        "GDOFs": round(ndof / t_best / 1e9, 2), "GDOFs_default": round(ndof / t_def / 1e9, 2)}
                 entries.append(ent)
                 if verbose:
