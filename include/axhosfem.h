@@ -103,6 +103,21 @@ int ax_local_gathered(int64_t E, int N, int geom, const double* geo, const doubl
                       const void* Xg, void* Y, void* stream);
 
 /*
+ * ax_local_gathered_energy - ax_local_gathered for one FP32 column that also returns the energy
+ * of the local operator, energy[0] = sum_e X_e^T Y_e = (Q Xg)^T A_L (Q Xg) with A_L the block
+ * diagonal of Eq. (3) (when Xg vanishes on the Dirichlet nodes this is Xg^T A Xg, the p^T A p of
+ * CG, Sec. 2.1).  Each node contributes (D X)^T G (D X), formed in FP32 in the pointwise stage of
+ * the kernel; the sums over nodes of an element column are FP32, every further sum FP64 in a
+ * fixed order (reproducible run to run).  This is the FP32 inner operator of cg_solve.
+ * Xg [dev] float [n_global]; Y [dev] float [E][N1^3]; work [dev] double [E] scratch (one sum
+ * per work-group); energy [dev] double [1].  Other arguments as ax_local_gathered with nrhs = 1
+ * and prec = AX_FP32.  Errors: as ax_local_gathered; work (E > 0) or energy NULL -> AX_ERR_ARG.
+ */
+int ax_local_gathered_energy(int64_t E, int N, int geom, const double* geo, const double* D,
+                             const double* xi, const double* w, const int32_t* l2g, int64_t n_global,
+                             const float* Xg, float* Y, double* work, double* energy, void* stream);
+
+/*
  * ax_local_vector - AxLocal on a vector field (n_col = 3, Sec. 2.1: X and Y hold three columns,
  * one per component), in the component-interleaved layout X, Y [dev] [E][3][N1^3] (the three
  * components of an element contiguous).  The three components share the element's geometric

@@ -88,6 +88,7 @@ _SIGS = {
     "ax_local_precomputedG": (_int, [_i64, _int, _vp, _vp, _int, _int, _vp, _vp, _vp]),
     "ax_local_vector": (_int, [_i64, _int, _int, _vp, _vp, _vp, _vp, _int, _vp, _vp, _vp]),
     "ax_local_gathered": (_int, [_i64, _int, _int, _vp, _vp, _vp, _vp, _int, _int, _vp, _i64, _vp, _vp, _vp]),
+    "ax_local_gathered_energy": (_int, [_i64, _int, _int, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp]),
     "ax_geom_factors": (_int, [_i64, _int, _vp, _vp, _vp, _int, _vp, _vp, _vp]),
     "ax_local_partial": (_int, [_i64, _int, _vp, _vp, _vp, _vp, _vp, _int, _int, _vp, _vp, _vp]),
     "ax_geom_lambda": (_int, [_i64, _int, _vp, _vp, _vp, _int, _vp, _vp]),
@@ -233,6 +234,22 @@ def ax_local_gathered(Xg, l2g, geo, basis: Basis, geom=AX_TRILINEAR, prec=AX_FP6
                                    _np_ptr(basis.w), nrhs, prec, _dptr(l2g), ng, _dptr(Xg), _dptr(Y),
                                    _stream(stream)))
     return Y
+
+
+def ax_local_gathered_energy(Xg, l2g, geo, basis: Basis, geom=AX_TRILINEAR, stream=None):
+    """FP32 Y = AxLocal(Q Xg) for one column plus its energy sum_e X_e^T Y_e (a one-element FP64
+    device tensor); Xg [n_global] float32 device tensor.  Returns (Y [E][N1^3], energy)."""
+    import torch
+    E = geo.shape[0]
+    NP = (basis.N + 1) ** 3
+    assert Xg.dtype == torch.float32 and Xg.dim() == 1 and l2g.dtype == torch.int32 and l2g.numel() == E * NP
+    Y = torch.empty((E, NP), dtype=torch.float32, device=Xg.device)
+    work = torch.empty(max(E, 1), dtype=torch.float64, device=Xg.device)
+    energy = torch.empty(1, dtype=torch.float64, device=Xg.device)
+    _check(lib().ax_local_gathered_energy(E, basis.N, geom, _dptr(geo), _np_ptr(basis.D), _np_ptr(basis.xi),
+                                          _np_ptr(basis.w), _dptr(l2g), Xg.shape[0], _dptr(Xg), _dptr(Y),
+                                          _dptr(work), _dptr(energy), _stream(stream)))
+    return Y, energy
 
 
 def ax_local_precomputedG(X, G, basis: Basis, prec=AX_FP64, out=None, stream=None):

@@ -144,4 +144,13 @@ struct TuneEntry {
 };
 TuneEntry tune_get(int N1, int kind, int prec);
 
+// Energy partials of the CG's fused operator (gathering AxLocal, one column): each work-group
+// writes the energy sum of its elements to epart (epart_cap entries available); nparts receives
+// the number of work-groups launched.
+struct FusedOut {
+    double* epart;
+    int64_t epart_cap;
+    int64_t nparts;
+};
+
 }  // namespace ax

@@ -28,10 +28,12 @@ namespace ax {
 
 int axl_dispatch_f64(int geo_kind, int N, int64_t E, int nrhs, const double* geo, const double* Gs,
                      const double* X, double* Y, const double* D, const double* xi, const double* w,
-                     hipStream_t st, const int32_t* l2g, int64_t ldg, int64_t es, int64_t ccs);
+                     hipStream_t st, const int32_t* l2g, int64_t ldg, int64_t es, int64_t ccs,
+                     FusedOut* fo = nullptr);
 int axl_dispatch_f32(int geo_kind, int N, int64_t E, int nrhs, const double* geo, const float* Gs,
                      const float* X, float* Y, const double* D, const double* xi, const double* w,
-                     hipStream_t st, const int32_t* l2g, int64_t ldg, int64_t es, int64_t ccs);
+                     hipStream_t st, const int32_t* l2g, int64_t ldg, int64_t es, int64_t ccs,
+                     FusedOut* fo = nullptr);
 
 // values per element and column: (N + 1)^3
 static inline int64_t NPL(int N) { return (int64_t)(N + 1) * (N + 1) * (N + 1); }
@@ -60,6 +62,20 @@ int ax_local_gather(const ax_problem& p, int nrhs, int prec, const void* xg, int
     if (prec == AX_FP64)
         return axl_dispatch_f64(gk, p.N, p.E, nrhs, p.geo, nullptr, (const double*)xg, (double*)Y, p.D, p.xi, p.w, st, p.l2g, ldg, NPL(p.N), p.E * NPL(p.N));
     return axl_dispatch_f32(gk, p.N, p.E, nrhs, p.geo, nullptr, (const float*)xg, (float*)Y, p.D, p.xi, p.w, st, p.l2g, ldg, NPL(p.N), p.E * NPL(p.N));
+}
+
+// The CG's fused operator for one column: ax_local_gather that also leaves each work-group's
+// element energies X_e^T Y_e in fo->epart (their sum is p^T A p for X = Q p).  FP32.
+int ax_local_gather_fused(const ax_problem& p, const float* xg, int64_t ldg, float* yl, FusedOut* fo,
+                          hipStream_t st)
+{
+    if (p.E == 0) {
+        fo->nparts = 0;
+        return AX_OK;
+    }
+    const int gk = p.geom == AX_TRILINEAR ? GEO_TRI : GEO_PARA;
+    return axl_dispatch_f32(gk, p.N, p.E, 1, p.geo, nullptr, xg, yl, p.D, p.xi, p.w, st, p.l2g, ldg, NPL(p.N),
+                            p.E * NPL(p.N), fo);
 }
 
 // FP16-input / FP32-accumulate variants live in ax_local_f16.hip.
@@ -92,11 +108,13 @@ extern "C" int ax_local(int64_t E, int N, int geom, const double* geo, const dou
     return ax_local_f16(E, N, gk, geo, nullptr, D, xi, w, nrhs, (const float*)X, (float*)Y, st);
 }
 
-extern "C" int ax_local_gathered(int64_t E, int N, int geom, const double* geo, const double* D,
-                                 const double* xi, const double* w, int nrhs, int prec, const int32_t* l2g,
-                                 int64_t n_global, const void* Xg, void* Y, void* stream)
+// Argument checks shared by the gathering entry points; fills p (E > 0) or returns AX_OK with
+// p.E == 0 for an empty mesh.
+static int gathered_problem(int64_t E, int N, int geom, const double* geo, const double* D, const double* xi,
+                            const double* w, int nrhs, int prec, const int32_t* l2g, int64_t n_global,
+                            const void* Xg, void* Y, ax_problem& p)
 {
-    clear_error();
+    p = ax_problem{};
     AX_TRY(check_common(E, N, nrhs, prec, Xg, Y, D));
     if (prec == AX_FP16_ACC32) return fail(AX_ERR_UNSUPPORTED, "the gathering operator is FP64/FP32");
     if (geom != AX_TRILINEAR && geom != AX_PARALLELEPIPED)
@@ -107,7 +125,6 @@ extern "C" int ax_local_gathered(int64_t E, int N, int geom, const double* geo, 
     if (!geo || !l2g) return fail(AX_ERR_ARG, "geo or l2g is NULL");
     if (n_global < 1) return fail(AX_ERR_ARG, "n_global < 1");
     if (!centro_antisymmetric(N + 1, D)) return fail(AX_ERR_UNSUPPORTED, "the gathering operator needs a GLL D");
-    ax_problem p{};
     p.E = E;
     p.N = N;
     p.geom = geom;
@@ -117,7 +134,49 @@ extern "C" int ax_local_gathered(int64_t E, int N, int geom, const double* geo, 
     p.w = w;
     p.n_global = n_global;
     p.l2g = l2g;
+    return AX_OK;
+}
+
+extern "C" int ax_local_gathered(int64_t E, int N, int geom, const double* geo, const double* D,
+                                 const double* xi, const double* w, int nrhs, int prec, const int32_t* l2g,
+                                 int64_t n_global, const void* Xg, void* Y, void* stream)
+{
+    clear_error();
+    ax_problem p;
+    AX_TRY(gathered_problem(E, N, geom, geo, D, xi, w, nrhs, prec, l2g, n_global, Xg, Y, p));
+    if (p.E == 0) return AX_OK;
     return ax_local_gather(p, nrhs, prec, Xg, n_global, Y, as_stream(stream));
+}
+
+// energy = sum of parts[0, n) in a fixed order (one work-group)
+__global__ void __launch_bounds__(256)
+sum_parts_kernel(const double* __restrict__ parts, int64_t n, double* __restrict__ energy)
+{
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int64_t q = threadIdx.x; q < n; q += 256) s += parts[q];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *energy = red[0];
+}
+
+extern "C" int ax_local_gathered_energy(int64_t E, int N, int geom, const double* geo, const double* D,
+                                        const double* xi, const double* w, const int32_t* l2g, int64_t n_global,
+                                        const float* Xg, float* Y, double* work, double* energy, void* stream)
+{
+    clear_error();
+    ax_problem p;
+    AX_TRY(gathered_problem(E, N, geom, geo, D, xi, w, 1, AX_FP32, l2g, n_global, Xg, Y, p));
+    if (!energy || (E > 0 && !work)) return fail(AX_ERR_ARG, "work or energy is NULL");
+    hipStream_t st = as_stream(stream);
+    FusedOut fo{work, E, 0};
+    if (p.E > 0) AX_TRY(ax_local_gather_fused(p, Xg, n_global, Y, &fo, st));
+    hipLaunchKernelGGL(sum_parts_kernel, dim3(1), dim3(256), 0, st, work, fo.nparts, energy);
+    return hip_check(hipGetLastError(), "energy sum");
 }
 
 extern "C" int ax_local_precomputedG(int64_t E, int N, const void* G, const double* D, int nrhs,

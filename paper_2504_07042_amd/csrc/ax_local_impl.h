@@ -80,6 +80,7 @@ struct AxArgs {
     const int32_t* l2g;
     int64_t ldg;
     int64_t es, ccs;
+    double* epart;
     Basis<T> bs;
 };
 
@@ -196,16 +197,20 @@ __device__ __forceinline__ void group_sync()
     }
 }
 
-// Kernel body.  GATHER: X is a global vector [nrhs][ldg] read through the local-to-global map
-// l2g (the Q of Sec. 2.1 fused into the load), so the solver never materialises Q x.  `cs` is the
-// source of the contraction coefficients (CoefResident or CoefReload).  Local vectors: node l of
-// column c of element e at c * ccs + e * es + l (es = N1^3, ccs = E N1^3 for [nrhs][E][N1^3];
+// Kernel body.  GATHER 1: X is a global vector [nrhs][ldg] read through the local-to-global map
+// l2g (the Q of Sec. 2.1 fused into the load), so the solver never materialises Q x.  GATHER 2
+// (one column, the CG's operator): as 1, and each work-group also writes the sum of its
+// elements' energies (D X_e)^T G_e (D X_e) = X_e^T Y_e to epart[blockIdx.x], which sums to
+// p^T A p when X = Q p and p vanishes on the masked nodes.  `cs` is the source of the
+// contraction coefficients (CoefResident or CoefReload).  Local vectors: node l of column c of
+// element e at c * ccs + e * es + l (es = N1^3, ccs = E N1^3 for [nrhs][E][N1^3];
 // es = nrhs N1^3, ccs = N1^3 for the component-interleaved [E][nrhs][N1^3] of a vector field).
-template <int N1, int GEO, bool EO, bool GATHER, int EPBX, typename T, typename C>
+template <int N1, int GEO, bool EO, int GATHER, int EPBX, typename T, typename C>
 __device__ __forceinline__ void
 ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __restrict__ Gs,
               const T* __restrict__ X, T* __restrict__ Y, const Basis<T>& bs,
-              const int32_t* __restrict__ l2g, int64_t ldg, int64_t es, int64_t ccs, const C& cs)
+              const int32_t* __restrict__ l2g, int64_t ldg, int64_t es, int64_t ccs, double* __restrict__ epart,
+              const C& cs)
 {
     using S = Shape<N1, sizeof(T)>;
     using TL = Tile<N1, EPBX>;
@@ -218,11 +223,14 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
     // (xi_k, w_k) pairs: the per-lane (xi_i, w_i), (xi_j, w_j) of the home columns, and xi_k, w_k
     // of the node loop for the kernels that do not keep them in scalar registers
     __shared__ double sxw[2 * N1];
+    // GATHER 2: per-lane energy sums, kept in LDS so that they hold no register over the item
+    __shared__ double sen[GATHER == 2 ? BLOCK : 1];
     lds_poison(smem, sizeof(smem));
     lds_poison(svert, sizeof(svert));
     lds_poison(sxw, sizeof(sxw));
 
     const int tid = threadIdx.x;
+    if constexpr (GATHER == 2) sen[tid] = 0.0;
     const int slot = (TL::SLOTS == 1) ? 0 : tid / NT;
     const int lane = tid - slot * NT;
     T* __restrict__ A = smem + slot * 2 * FS;
@@ -393,19 +401,25 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
         group_sync<BLOCK>();
         // P3: pointwise factors at the home column; r -> B, s -> A, t stays in registers
         T tt[N1];
+        T ei = T(0);  // GATHER 2: this item's energy at the home column
 #pragma unroll
         for (int k = 0; k < N1; ++k) {
             const int l = S::pos(i, j, k);
             T x0 = B[l], x1 = A[l], xx2 = x2[k];
             T g[6];
+            T lam_out = T(1);  // GATHER 2: lambda applied to the outputs, after the energy
             if constexpr (GEO == GEO_TRI) {
                 T lam;
                 T tk, wk;
                 node_xw<N1, GEO, EO>(bs, sxw, k, tk, wk);
                 tri_adj<T>(tc, tk, wk, g, lam);
-                x0 *= lam;
-                x1 *= lam;
-                xx2 *= lam;
+                if constexpr (GATHER == 2) {
+                    lam_out = lam;
+                } else {
+                    x0 *= lam;
+                    x1 *= lam;
+                    xx2 *= lam;
+                }
             } else if constexpr (GEO == GEO_TRIL || GEO == GEO_HELM) {
                 T tk, wk;
                 node_xw<N1, GEO, EO>(bs, sxw, k, tk, wk);
@@ -425,10 +439,27 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
 #pragma unroll
                 for (int q = 0; q < 6; ++q) g[q] = active ? ge[q * NP] : T(0);
             }
-            B[l] = fma(g[0], x0, fma(g[1], x1, g[2] * xx2));
-            A[l] = fma(g[1], x0, fma(g[3], x1, g[4] * xx2));
-            tt[k] = fma(g[2], x0, fma(g[4], x1, g[5] * xx2));
+            if constexpr (GATHER == 2) {
+                T bo = fma(g[0], x0, fma(g[1], x1, g[2] * xx2));
+                T ao = fma(g[1], x0, fma(g[3], x1, g[4] * xx2));
+                T to = fma(g[2], x0, fma(g[4], x1, g[5] * xx2));
+                // the node's energy (D X)^T G (D X) with G = lambda g, then G (D X) itself
+                if (active) ei += lam_out * fma(x0, bo, fma(x1, ao, xx2 * to));
+                if constexpr (GEO == GEO_TRI) {
+                    bo *= lam_out;
+                    ao *= lam_out;
+                    to *= lam_out;
+                }
+                B[l] = bo;
+                A[l] = ao;
+                tt[k] = to;
+            } else {
+                B[l] = fma(g[0], x0, fma(g[1], x1, g[2] * xx2));
+                A[l] = fma(g[1], x0, fma(g[3], x1, g[4] * xx2));
+                tt[k] = fma(g[2], x0, fma(g[4], x1, g[5] * xx2));
+            }
         }
+        if constexpr (GATHER == 2) sen[tid] += (double)ei;
         T y2[N1];
         bwd(tt, y2);  // D_t^T t
         // Helmholtz: Lambda3 and this item's X at the home column for the mass term, loaded here
@@ -501,6 +532,25 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
         eb = eb_n;
         c = c_n;
     }
+    if constexpr (GATHER == 2) {
+        // the work-group's energy: wave sums, then the waves in order (a fixed combination)
+        double en = sen[tid];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) en += __shfl_xor(en, off);
+        if constexpr (BLOCK == 64) {
+            if (tid == 0) epart[blockIdx.x] = en;
+        } else {
+            __shared__ double ered[BLOCK / 64];
+            if ((tid & 63) == 0) ered[tid >> 6] = en;
+            __syncthreads();
+            if (tid == 0) {
+                double s = 0.0;
+#pragma unroll
+                for (int q = 0; q < BLOCK / 64; ++q) s += ered[q];
+                epart[blockIdx.x] = s;
+            }
+        }
+    }
 }
 
 template <int N1, int GEO, typename T>
@@ -511,26 +561,30 @@ constexpr int min_waves()
 
 // Entry points: the tables of orders that fit the scalar register file stay resident; the
 // others are reloaded per output row through the kernel-argument segment (one struct argument).
-template <int N1, int GEO, bool EO, bool GATHER, int EPBX, typename T>
+template <int N1, int GEO, bool EO, int GATHER, int EPBX, typename T>
 __global__ void __launch_bounds__((Tile<N1, EPBX>::BLOCK), (min_waves<N1, GEO, T>()))
 ax_local_kernel(int64_t E, int nrhs, const double* __restrict__ geo, const T* __restrict__ Gs,
                 const T* __restrict__ X, T* __restrict__ Y, const Basis<T> bs,
-                const int32_t* __restrict__ l2g, int64_t ldg, int64_t es, int64_t ccs)
+                const int32_t* __restrict__ l2g, int64_t ldg, int64_t es, int64_t ccs, double* __restrict__ epart)
 {
-    ax_local_body<N1, GEO, EO, GATHER, EPBX, T>(E, nrhs, geo, Gs, X, Y, bs, l2g, ldg, es, ccs, CoefResident<T>{bs});
+    ax_local_body<N1, GEO, EO, GATHER, EPBX, T>(E, nrhs, geo, Gs, X, Y, bs, l2g, ldg, es, ccs, epart,
+                                                CoefResident<T>{bs});
 }
 
-template <int N1, int GEO, bool EO, bool GATHER, int EPBX, typename T>
+template <int N1, int GEO, bool EO, int GATHER, int EPBX, typename T>
 __global__ void __launch_bounds__((Tile<N1, EPBX>::BLOCK), (min_waves<N1, GEO, T>()))
 ax_local_kernel_rl(const AxArgs<T> ka)
 {
     const CoefReload<T> cs = karg_coefs<T, AxArgs<T>>();
-    ax_local_body<N1, GEO, EO, GATHER, EPBX, T>(ka.E, ka.nrhs, ka.geo, ka.Gs, ka.X, ka.Y, ka.bs, ka.l2g, ka.ldg, ka.es, ka.ccs, cs);
+    ax_local_body<N1, GEO, EO, GATHER, EPBX, T>(ka.E, ka.nrhs, ka.geo, ka.Gs, ka.X, ka.Y, ka.bs, ka.l2g, ka.ldg, ka.es,
+                                                ka.ccs, ka.epart, cs);
 }
 
-template <int N1, int GEO, bool EO, bool GATHER, int EPBX, typename T>
+// fo (GATHER 2 only): the energy partials; fo->nparts gets the grid size.
+template <int N1, int GEO, bool EO, int GATHER, int EPBX, typename T>
 static int launch_tile(int64_t E, int nrhs, const double* geo, const T* Gs, const T* X, T* Y, const Basis<T>& bs,
-                       int grid_mult, hipStream_t st, const int32_t* l2g, int64_t ldg, int64_t es, int64_t ccs)
+                       int grid_mult, hipStream_t st, const int32_t* l2g, int64_t ldg, int64_t es, int64_t ccs,
+                       FusedOut* fo = nullptr)
 {
     using TL = Tile<N1, EPBX>;
     static int per = 0;  // resident work-groups per CU for this instantiation
@@ -555,13 +609,21 @@ static int launch_tile(int64_t E, int nrhs, const double* geo, const T* Gs, cons
     const int64_t cap = (int64_t)cus * per * (grid_mult > 0 ? grid_mult : 1);
     const int64_t blocks = nblk < cap ? nblk : cap;
     if (blocks > 0x7fffffff) return fail(AX_ERR_UNSUPPORTED, "too many elements for one launch");
+    double* epart = nullptr;
+    if constexpr (GATHER == 2) {
+        if (!fo || !fo->epart) return fail(AX_ERR_ARG, "internal: fused AxLocal without its energy partials");
+        if (blocks > fo->epart_cap) return fail(AX_ERR_ARG, "internal: energy partials hold %lld, need %lld",
+                                                (long long)fo->epart_cap, (long long)blocks);
+        epart = fo->epart;
+        fo->nparts = blocks;
+    }
     if constexpr (reload_coefs<N1, GEO, T>()) {
-        const AxArgs<T> ka{E, nrhs, geo, Gs, X, Y, l2g, ldg, es, ccs, bs};
+        const AxArgs<T> ka{E, nrhs, geo, Gs, X, Y, l2g, ldg, es, ccs, epart, bs};
         hipLaunchKernelGGL((ax_local_kernel_rl<N1, GEO, EO, GATHER, EPBX, T>), dim3((unsigned)blocks),
                            dim3(TL::BLOCK), 0, st, ka);
     } else {
         hipLaunchKernelGGL((ax_local_kernel<N1, GEO, EO, GATHER, EPBX, T>), dim3((unsigned)blocks), dim3(TL::BLOCK),
-                           0, st, E, nrhs, geo, Gs, X, Y, bs, l2g, ldg, es, ccs);
+                           0, st, E, nrhs, geo, Gs, X, Y, bs, l2g, ldg, es, ccs, epart);
     }
     return hip_check(hipGetLastError(), "ax_local launch");
 }
@@ -576,7 +638,7 @@ int tri_item_dispatch_f32(int N1, int64_t E, int nrhs, const double* verts, cons
 template <int N1, int GEO, typename T>
 static int launch_n1(int64_t E, int nrhs, const double* geo, const T* Gs, const T* X, T* Y,
                      const double* D, const double* xi, const double* w, hipStream_t st,
-                     const int32_t* l2g, int64_t ldg, int64_t es, int64_t ccs)
+                     const int32_t* l2g, int64_t ldg, int64_t es, int64_t ccs, FusedOut* fo)
 {
     using S = Shape<N1>;
     Basis<T> bs;
@@ -586,8 +648,17 @@ static int launch_n1(int64_t E, int nrhs, const double* geo, const T* Gs, const 
     const TuneEntry tu = tune_get(N1, tune_kind_of(GEO), sizeof(T) == 8 ? AX_FP64 : AX_FP32);
     if (l2g) {
         if (!eo) return fail(AX_ERR_UNSUPPORTED, "gathering AxLocal needs a GLL differentiation matrix");
-        if constexpr (GEO == GEO_TRI || GEO == GEO_PARA)
-            return launch_tile<N1, GEO, true, true, S::EPB, T>(E, nrhs, geo, Gs, X, Y, bs, tu.grid_mult, st, l2g, ldg, es, ccs);
+        if constexpr (GEO == GEO_TRI || GEO == GEO_PARA) {
+            if (fo) {
+                // energies fused in FP32 only: in FP64 the kernel's extra register pressure cost as
+                // much as the p read it saves in Q^T
+                if constexpr (sizeof(T) == 4)
+                    return launch_tile<N1, GEO, true, 2, S::EPB, T>(E, nrhs, geo, Gs, X, Y, bs, tu.grid_mult, st, l2g,
+                                                                    ldg, es, ccs, fo);
+                return fail(AX_ERR_UNSUPPORTED, "internal: the fused operator is FP32");
+            }
+            return launch_tile<N1, GEO, true, 1, S::EPB, T>(E, nrhs, geo, Gs, X, Y, bs, tu.grid_mult, st, l2g, ldg, es, ccs);
+        }
         return fail(AX_ERR_UNSUPPORTED, "gathering AxLocal needs on-the-fly factors");
     }
     // the per-item kernel where the tuning table (or the measured default) picks it
@@ -617,11 +688,12 @@ static int launch_n1(int64_t E, int nrhs, const double* geo, const T* Gs, const 
 template <int GEO, typename T>
 static int dispatch(int N, int64_t E, int nrhs, const double* geo, const T* Gs, const T* X, T* Y,
                     const double* D, const double* xi, const double* w, hipStream_t st,
-                    const int32_t* l2g, int64_t ldg, int64_t es, int64_t ccs)
+                    const int32_t* l2g, int64_t ldg, int64_t es, int64_t ccs, FusedOut* fo)
 {
+    if (fo && (!l2g || nrhs != 1)) return fail(AX_ERR_ARG, "internal: the fused operator takes one gathered column");
     switch (N + 1) {
 #define AX_CASE(n1) \
-    case n1: return launch_n1<n1, GEO, T>(E, nrhs, geo, Gs, X, Y, D, xi, w, st, l2g, ldg, es, ccs);
+    case n1: return launch_n1<n1, GEO, T>(E, nrhs, geo, Gs, X, Y, D, xi, w, st, l2g, ldg, es, ccs, fo);
         AX_CASE(2) AX_CASE(3) AX_CASE(4) AX_CASE(5) AX_CASE(6) AX_CASE(7) AX_CASE(8) AX_CASE(9)
         AX_CASE(10) AX_CASE(11) AX_CASE(12) AX_CASE(13) AX_CASE(14) AX_CASE(15) AX_CASE(16)
 #undef AX_CASE

@@ -21,10 +21,18 @@ int gs_apply(int64_t n_local, int64_t n_global, const int32_t* l2g, const int64_
              const int32_t* gidx, const uint8_t* mask, int mode, int nrhs, int dtype, const void* in,
              void* out, hipStream_t st);
 int ax_local_gather(const ax_problem& p, int nrhs, int prec, const void* xg, int64_t ldg, void* Y, hipStream_t st);
+int ax_local_gather_fused(const ax_problem& p, const float* xg, int64_t ldg, float* yl, FusedOut* fo,
+                          hipStream_t st);
 int batched_prepare_gather(int n_mesh, const ax_problem* meshes, int nrhs, int prec, const int32_t* l2g,
                            const int64_t* lbase, int64_t n_global, void* const* Y, const int64_t* ldy, void* ws,
                            size_t bytes, ax_batch_plan* plan);
 int batched_set_source(const ax_batch_plan* plan, void* ws, const void* xg, hipStream_t st);
+
+// The single-column FP32 operator of cg_solve with p^T A p summed inside the gathering AxLocal
+// (fused_operator); 0 = off.
+#ifndef AX_CG_FUSED
+#define AX_CG_FUSED 1
+#endif
 
 constexpr int kRedBlocks = 4096;  // partial sums per dot product and column (fixed grid)
 constexpr int kRedThreads = 256;
@@ -167,11 +175,15 @@ copy_pairs_kernel(CopyPair* __restrict__ cp, const int64_t* __restrict__ gptr, c
 // Ap[g] = mask ? 0 : sum of the local copies (ascending local id, the order of the plain loop)
 // and, fused, the partial sums of p . Ap over the same fixed grid as dot_partial_kernel.  Each
 // thread takes kUnroll nodes per tile so that their loads are in flight together.
-template <typename T>
+// FOLD (after the fused operator): p . Ap comes from AxLocal's per-work-group energies
+// epart[0, nparts), folded onto this fixed grid (block b takes b, b + gridDim.x, ...), so p is
+// not read.
+template <typename T, bool FOLD>
 __global__ void __launch_bounds__(kRedThreads)
 qt_dot_kernel(int64_t n_global, const CopyPair* __restrict__ cp, const int64_t* __restrict__ gptr,
               const int32_t* __restrict__ gidx, int64_t n_local, const T* __restrict__ in,
-              const T* __restrict__ pdir, T* __restrict__ out, double* __restrict__ partials)
+              const T* __restrict__ pdir, T* __restrict__ out, double* __restrict__ partials,
+              const double* __restrict__ epart, int64_t nparts)
 {
     const int c = blockIdx.y;
     const T* x = in + (int64_t)c * n_local;
@@ -225,9 +237,16 @@ qt_dot_kernel(int64_t n_global, const CopyPair* __restrict__ cp, const int64_t* 
                     for (int64_t k = b[u] + kMore; k < e[u]; ++k) s += x[gidx[k]];
                 }
                 o[g] = s;
-                acc = fma((double)pd[g], (double)s, acc);
+                if constexpr (!FOLD) acc = fma((double)pd[g], (double)s, acc);
             }
         }
+    }
+    if constexpr (FOLD) {
+        if (threadIdx.x == 0) {
+            for (int64_t q = blockIdx.x; q < nparts; q += gridDim.x) acc += epart[q];
+            partials[c * kRedBlocks + blockIdx.x] = acc;
+        }
+        return;
     }
     __shared__ double red[kRedThreads];
     red[threadIdx.x] = acc;
@@ -475,9 +494,12 @@ struct CgWork {
     CopyPair* pairs;               // [n_global]
     CgScal *sc, *sc_in;            // outer / inner scalar state [nrhs]
     int* flag;                     // masked right-hand-side check
+    double* epart;                 // fused operator: per-work-group energies [fused_e] (or NULL)
 };
 
-static void carve(Carver& cv, int64_t nl, int64_t ng, int nrhs, bool mixed, bool pre, CgWork& w)
+// fused_e > 0: room for the fused single-column operator of a mesh of fused_e elements
+static void carve(Carver& cv, int64_t nl, int64_t ng, int nrhs, bool mixed, bool pre, CgWork& w,
+                  int64_t fused_e = 0)
 {
     w.r = cv.take<double>(ng * nrhs);
     w.p = cv.take<double>(ng * nrhs);
@@ -502,6 +524,7 @@ static void carve(Carver& cv, int64_t nl, int64_t ng, int nrhs, bool mixed, bool
     w.sc = cv.take<CgScal>(nrhs);
     w.sc_in = cv.take<CgScal>(nrhs);
     w.flag = cv.take<int>(1);
+    w.epart = fused_e > 0 ? cv.take<double>(fused_e) : nullptr;
 }
 
 // The assembled operator y = mask o Q^T AxLocal(Q x) over one mesh (ax_local) or over the
@@ -522,6 +545,8 @@ struct Operator {
     bool batched_gather = false;    // the batched plans read the global vector through l2g
     const double* dinv64 = nullptr;  // Jacobi preconditioner (NULL: none)
     const float* dinv32 = nullptr;
+    double* epart = nullptr;           // fused single-column operator (NULL: not used)
+    int64_t epart_cap = 0;
 };
 
 template <typename T>
@@ -615,6 +640,20 @@ static int poll(const CgScal* sc, int nrhs, std::vector<CgScal>& h, hipStream_t 
 // vectors of 46 MB: 8% more time merged), so there x stays in update_dot.
 static bool merged_x_update(int64_t vector_bytes) { return vector_bytes > (int64_t)64 << 20; }
 
+// The fused operator (one column, single mesh, FP32 gathering AxLocal): AxLocal also sums
+// p^T A p as the elements' energies (D X_e)^T G_e (D X_e), so Q^T does not read p.  Measured at
+// N = 7, 32^3: FP32 AxLocal 63.8 -> 64.1 us, Q^T 70.2 -> 65.1 us per application (FP32-inner CG
+// 0.400 -> 0.393 s).  In FP64 the energies pushed the kernel's register use into spills (90 ->
+// 102 us, the same again saved in Q^T), so FP64 keeps the dot in Q^T.  Writing the nodes with a
+// single unmasked copy (the element interiors) straight from AxLocal to the global vector, so
+// that Q^T visits only the shared nodes, measured slower still (FP64 CG 0.551 -> 0.638 s): the
+// reload of the map before the stores serialises the item's memory traffic and the stores
+// diverge per node.
+static bool fused_operator(const Operator& op, int prec)
+{
+    return AX_CG_FUSED && op.epart && op.p && prec == AX_FP32 && centro_antisymmetric(op.p->N + 1, op.p->D);
+}
+
 // One block of kPoll CG iterations (device scalars only: capturable).
 template <typename TX, typename T>
 static int cg_block(const Operator& op, int nrhs, int prec, TX* x, T* r, T* p, T* Ap, T* pl, T* wl,
@@ -624,10 +663,24 @@ static int cg_block(const Operator& op, int nrhs, int prec, TX* x, T* r, T* p, T
     const dim3 g(vgrid(ng), nrhs);
     const T* dinv = op_dinv<T>(op);
     const bool merged = merged_x_update(ng * nrhs * (int64_t)sizeof(T));
+    const bool fused = nrhs == 1 && fused_operator(op, prec);
     for (int q = 0; q < count; ++q) {
-        AX_TRY(apply_local<T>(op, nrhs, prec, p, pl, wl, st));
-        hipLaunchKernelGGL(qt_dot_kernel<T>, dim3(kRedBlocks, nrhs), dim3(kRedThreads), 0, st, ng, op.pairs,
-                           op.gptr, op.gidx, op.n_local, wl, p, Ap, partials);
+        if (fused) {
+            if constexpr (sizeof(T) == 4) {
+                // AxLocal also leaves the energies whose sum is p^T A p
+                FusedOut fo{op.epart, op.epart_cap, 0};
+                AX_TRY(ax_local_gather_fused(*op.p, p, ng, wl, &fo, st));
+                hipLaunchKernelGGL((qt_dot_kernel<T, true>), dim3(kRedBlocks, nrhs), dim3(kRedThreads), 0, st, ng,
+                                   op.pairs, op.gptr, op.gidx, op.n_local, wl, p, Ap, partials, op.epart,
+                                   fo.nparts);
+            } else {
+                return fail(AX_ERR_ARG, "internal: the fused operator is FP32");
+            }
+        } else {
+            AX_TRY(apply_local<T>(op, nrhs, prec, p, pl, wl, st));
+            hipLaunchKernelGGL((qt_dot_kernel<T, false>), dim3(kRedBlocks, nrhs), dim3(kRedThreads), 0, st, ng,
+                               op.pairs, op.gptr, op.gidx, op.n_local, wl, p, Ap, partials, nullptr, 0);
+        }
         AX_TRY(scal(partials, sc, 1, nrhs, st));
         if (merged)
             hipLaunchKernelGGL((update_dot_kernel<TX, T, false>), dim3(kRedBlocks, nrhs), dim3(kRedThreads), 0,
@@ -964,6 +1017,12 @@ static int finish(int status, ax_cg_report* rep, const std::chrono::steady_clock
     return status;
 }
 
+// Elements of room for the fused single-column operator (0: the solve does not use it)
+static int64_t fused_elements(const ax_problem* p, int nrhs, const ax_cg_opts* o)
+{
+    return (AX_CG_FUSED && nrhs == 1 && p->E > 0 && o->inner_prec == AX_FP32) ? p->E : 0;
+}
+
 }  // namespace ax
 
 using namespace ax;
@@ -976,7 +1035,8 @@ extern "C" int cg_workspace_bytes(const ax_problem* p, int nrhs, const ax_cg_opt
     const int N1 = p->N + 1;
     Carver cv{nullptr, 0, 0};
     CgWork w;
-    carve(cv, p->E * N1 * N1 * N1, p->n_global, nrhs, o->inner_prec != AX_FP64, o->precond == AX_PRECOND_JACOBI, w);
+    carve(cv, p->E * N1 * N1 * N1, p->n_global, nrhs, o->inner_prec != AX_FP64, o->precond == AX_PRECOND_JACOBI, w,
+          fused_elements(p, nrhs, o));
     *bytes = cv.used + 256;
     return AX_OK;
 }
@@ -1002,7 +1062,8 @@ extern "C" int cg_solve(const ax_problem* p, int nrhs, const double* b, double* 
     const int64_t nl = p->E * N1 * N1 * N1;
     Carver cv{(char*)(((uintptr_t)o->workspace + 255) & ~uintptr_t(255)), 0, o->workspace_bytes - 256};
     CgWork w;
-    carve(cv, nl, p->n_global, nrhs, o->inner_prec != AX_FP64, o->precond == AX_PRECOND_JACOBI, w);
+    carve(cv, nl, p->n_global, nrhs, o->inner_prec != AX_FP64, o->precond == AX_PRECOND_JACOBI, w,
+          fused_elements(p, nrhs, o));
     Operator op;
     op.n_local = nl;
     op.n_global = p->n_global;
@@ -1014,6 +1075,10 @@ extern "C" int cg_solve(const ax_problem* p, int nrhs, const double* b, double* 
     hipLaunchKernelGGL(copy_pairs_kernel, dim3(vgrid(p->n_global)), dim3(256), 0, st, w.pairs, p->gptr, p->gidx,
                        p->mask, p->n_global);
     op.pairs = w.pairs;
+    if (w.epart) {
+        op.epart = w.epart;
+        op.epart_cap = p->E;
+    }
     AX_TRY(check_masked_rhs(b, op.mask, op.n_global, nrhs, w.flag, st));
     if (w.dinv) {
         AX_TRY(ax_local_diag(p->E, p->N, p->geom, p->geo, p->D, p->xi, p->w, w.wl, st));

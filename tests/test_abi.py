@@ -301,3 +301,25 @@ def test_tuning_cache_load_is_tolerant(ax, tmp_path):
     finally:
         autotune.tune_set(5, K, P, **{k: before[k] for k in autotune.KNOBS})
     assert autotune.tune_get(5, K, P) == before
+
+
+def test_gathered_energy_validation(ax):
+    """The energy variant of the gathering operator rejects its own missing buffers (and the
+    gathering operator's bad arguments) before any launch."""
+    L = ax.lib()
+    b = ax.Basis(3)
+    D, xi, w = ax._np_ptr(b.D), ax._np_ptr(b.xi), ax._np_ptr(b.w)
+    v = ctypes.c_void_p
+
+    def call(E=4, work=56, energy=64, l2g=8, ng=10, Xg=16, Y=24, N=3):
+        return L.ax_local_gathered_energy(E, N, ax.AX_TRILINEAR, v(32), D, xi, w, v(l2g) if l2g else None, ng,
+                                          v(Xg) if Xg else None, v(Y) if Y else None, v(work) if work else None,
+                                          v(energy) if energy else None, None)
+
+    assert call(energy=0) == ax.AX_ERR_ARG
+    assert call(work=0) == ax.AX_ERR_ARG
+    assert call(l2g=0) == ax.AX_ERR_ARG
+    assert call(ng=0) == ax.AX_ERR_ARG
+    assert call(Xg=16, Y=16) == ax.AX_ERR_ARG
+    assert call(N=0) == ax.AX_ERR_UNSUPPORTED
+    assert len(L.ax_last_error()) > 0

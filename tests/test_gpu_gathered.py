@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_util import check_bound, check_fp64, cond_j_per_element, fp32_bound, report, sample_elements
+from gpu_util import U32, check_bound, check_fp64, cond_j_per_element, fp32_bound, report, sample_elements
 from paper_2504_07042_amd import meshgen
 
 pytestmark = pytest.mark.gpu
@@ -108,3 +108,88 @@ def test_gathered_validation(ax):
                                None) == ax.AX_ERR_UNSUPPORTED
     assert L.ax_local_gathered(4, 3, 0, v(8), D, xi, w, 1, ax.AX_FP64, v(8), 10, v(16), v(16), None) == ax.AX_ERR_ARG
     assert L.ax_local_gathered(0, 3, 0, None, D, xi, w, 1, ax.AX_FP64, None, 10, None, None, None) == ax.AX_OK
+
+
+def _energy_factor(N, kappa):
+    """Bound factor of the FP32 energy sum_e X_e^T Y_e, in units of sum_e |X_e|^T env_e =
+    sum over nodes of (|D||X|)^T |G| (|D||X|): each node's (D X)^T G (D X) carries the operator's
+    FP32 forward error (fp32_bound) plus N1 u32 for the FP32 sum over an element column; the
+    further sums are FP64."""
+    return fp32_bound(N, kappa) + (N + 1) * U32
+
+
+def _energy_ref(D, G, Xloc):
+    """sum_e X_e^T AxLocal(X_e) and its envelope sum_e |X_e|^T env_e from the oracle (Eq. 3)."""
+    Yref, env = oracle.ax_local(D, G, Xloc), oracle.ax_envelope(D, G, Xloc)
+    return float(np.sum(Xloc * Yref)), float(np.sum(np.abs(Xloc) * env)), Yref, env
+
+
+@pytest.mark.parametrize("geom", ["tri", "para"])
+@pytest.mark.parametrize("N", [1, 2, 3, 5, 7, 8, 9, 11, 12, 15])
+def test_gathered_energy_small(ax, N, geom):
+    """The CG's FP32 inner operator with p^T A p summed in the kernel: Y against the oracle under
+    the FP32 bound, the energy against sum_e X_e^T AxLocal(X_e) under its own bound.  The orders
+    cover one- and several-wave work-groups (the cross-wave sum of the energies)."""
+    import torch
+    dims = (4, 3, 3)
+    if geom == "tri":
+        m = meshgen.jittered_hex(*dims, alpha=0.15, seed=900 + N)
+    else:
+        m, _ = meshgen.parallelepiped_hex(*dims, seed=N + 50)
+    l2g, ng, _ = meshgen.global_numbering(*dims, N)
+    xg = np.random.default_rng(N + 5).uniform(-1, 1, ng).astype(np.float32)
+    b = ax.Basis(N)
+    V = _dev(m.verts)
+    geo = V if geom == "tri" else ax.parallelepiped_factors(V)
+    G_ = ax.AX_TRILINEAR if geom == "tri" else ax.AX_PARALLELEPIPED
+    Y, en = ax.ax_local_gathered_energy(_dev(xg), _dev(l2g), geo, b, G_)
+    torch.cuda.synchronize()
+    xi, w, D = oracle.gll(N)
+    G, _, _ = oracle.geom_factors(m.verts, N, xi, w)
+    Xloc = oracle.gs_q(l2g, xg.astype(np.float64)).reshape(1, m.E, -1)
+    e_ref, e_env, Yref, env = _energy_ref(D, G, Xloc)
+    kappa = cond_j_per_element(m.verts, N)
+    tag = f"gathered energy N={N} {geom}"
+    check_bound(Y.double().cpu().numpy()[None], Yref, env, fp32_bound(N, kappa)[None, :, None], tag=tag)
+    err = abs(float(en.item()) - e_ref)
+    bound = float(_energy_factor(N, kappa.max())) * e_env
+    report(tag + " energy", energy=e_ref, err_over_env=err / e_env, fraction_of_bound=err / bound)
+    assert e_ref > 0.0
+    assert err <= bound, (en.item(), e_ref, err, bound)
+
+
+def test_gathered_energy_cg_workload(ax):
+    """The FP32 inner operator at the CG's size (N = 7, 32^3, 11.4 M global nodes; every
+    work-group takes several elements): the energy over the whole mesh against the oracle,
+    evaluated in element chunks, and Y on sampled elements."""
+    import torch
+    N, dims = 7, (32, 32, 32)
+    m = meshgen.jittered_hex(*dims, alpha=0.10, seed=4)
+    l2g, ng, _ = meshgen.global_numbering(*dims, N)
+    xg = np.random.default_rng(17).uniform(-1, 1, ng).astype(np.float32)
+    b = ax.Basis(N)
+    Y, en = ax.ax_local_gathered_energy(_dev(xg), _dev(l2g), _dev(m.verts), b, ax.AX_TRILINEAR)
+    torch.cuda.synchronize()
+    xi, w, D = oracle.gll(N)
+    NP = (N + 1) ** 3
+    L = l2g.reshape(m.E, NP)
+    e_ref = e_env = 0.0
+    kmax = 1.0
+    for e0 in range(0, m.E, 4096):
+        sl = slice(e0, min(e0 + 4096, m.E))
+        G, _, _ = oracle.geom_factors(m.verts[sl], N, xi, w)
+        er, ee, _, _ = _energy_ref(D, G, xg.astype(np.float64)[L[sl]][None])
+        e_ref += er
+        e_env += ee
+        kmax = max(kmax, float(cond_j_per_element(m.verts[sl], N).max()))
+    sel = sample_elements(m.E, 64, seed=12)
+    kappa = cond_j_per_element(m.verts[sel], N)
+    G, _, _ = oracle.geom_factors(m.verts[sel], N, xi, w)
+    Xs = xg.astype(np.float64)[L[sel]][None]
+    Yref, env = oracle.ax_local(D, G, Xs), oracle.ax_envelope(D, G, Xs)
+    check_bound(Y[torch.from_numpy(sel).cuda()].double().cpu().numpy()[None], Yref, env,
+                fp32_bound(N, kappa)[None, :, None], tag="gathered energy CG workload (sampled Y)")
+    err = abs(float(en.item()) - e_ref)
+    bound = float(_energy_factor(N, kmax)) * e_env
+    report("gathered energy CG workload", energy=e_ref, err_over_env=err / e_env, fraction_of_bound=err / bound)
+    assert err <= bound, (en.item(), e_ref, err, bound)
