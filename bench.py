@@ -395,7 +395,7 @@ def batched_run(ax, meshgen, dev, nrhs=8, steps=5, warmup=2, check_with_oracle=T
 
         wall_l, per_l = time_steps(per_mesh, steps, warmup, 1)
         from paper_2504_07042_amd import item_shape_of
-        shapes = {f"N={N1 - 1}": item_shape_of(N1, bat.plan.order_variant[N1])
+        shapes = {f"N={N1 - 1}": item_shape_of(N1, bat.plan.order_variant[N1], prec)
                   for N1 in range(2, 11) if bat.plan.order_count[N1] > 0}
         res[pname] = {"batched_graph_GDOFs": round(dofs / per_b.mean() / 1e9, 1),
                       "per_mesh_launches_GDOFs": round(dofs / per_l.mean() / 1e9, 1),

@@ -143,7 +143,9 @@ int ax_local_vector(int64_t E, int N, int geom, const double* geo, const double*
  *              one) or AX_KERNEL_ITEM (the per-item kernel: element groups handed out one at a
  *              time, tables reloaded per output row); ITEM exists for the trilinear full form
  *              (every order) and the partial form (N >= 8) on GLL bases: elsewhere the tile
- *              kernel runs.  Ignored for AX_TUNE_BATCHED (always per-item).
+ *              kernel runs.  AX_TUNE_BATCHED: AX_KERNEL_TILE runs the tile kernel (default
+ *              shape) over the work list where the order has one (FP64 N <= 6, FP32 N <= 9),
+ *              AUTO and ITEM the per-item kernel.
  *   tile_alt   tile kernel: 0 default elements per work-group, 1 the alternative shape;
  *   item_alt   per-item kernels (single-mesh and batched): 0 a 256-lane work-group, 1 the
  *              order's alternative shape (N <= 12; see elems_per_group and block);
@@ -423,7 +425,8 @@ typedef struct {
     int gather;       /* 0 (internal use: 1 for the solver's plans reading a global vector) */
     int64_t order_first[11];  /* items of order N1 = N + 1 (2..10): [order_first[N1], +order_count[N1]) */
     int64_t order_count[11];
-    int order_variant[11];    /* work-group shape of order N1 (ax_tune.item_alt at prepare time) */
+    int order_variant[11];    /* kernel and work-group shape of order N1 at prepare time: 0, 1 the
+                                 per-item shapes (ax_tune.item_alt), 2 the tile kernel */
 } ax_batch_plan;
 
 int ax_batched_workspace_bytes(int n_mesh, const ax_problem* meshes, size_t* bytes);

@@ -489,19 +489,24 @@ class BatchedAxLocal:
         _check(lib().ax_local_batched(ctypes.byref(self.plan), _dptr(self.ws), _stream(stream)))
 
 
-def item_shape_of(N1: int, variant: int) -> dict:
-    """Work-group shape of the per-item kernels of order N1 - 1 in a shape variant (0 or 1)."""
-    t = AxTune(kernel=AX_KERNEL_ITEM, item_alt=int(variant), grid_mult=2)
+def item_shape_of(N1: int, variant: int, prec=AX_FP64) -> dict:
+    """Work-group shape of the batched kernels of order N1 - 1 in a plan's shape variant (0 or 1
+    the per-item shapes, 2 the tile kernel) and precision."""
+    if int(variant) == 2:
+        t = AxTune(kernel=AX_KERNEL_TILE, grid_mult=2)
+    else:
+        t = AxTune(kernel=AX_KERNEL_ITEM, item_alt=int(variant), grid_mult=2)
     saved = AxTune()
     L = lib()
     kind = AX_TUNE_BATCHED if N1 <= 10 else AX_TUNE_TRILINEAR
-    _check(L.ax_tune_get(N1 - 1, kind, AX_FP64, ctypes.byref(saved)))
+    _check(L.ax_tune_get(N1 - 1, kind, prec, ctypes.byref(saved)))
     try:
-        _check(L.ax_tune_set(N1 - 1, kind, AX_FP64, ctypes.byref(t)))
-        _check(L.ax_tune_get(N1 - 1, kind, AX_FP64, ctypes.byref(t)))
+        _check(L.ax_tune_set(N1 - 1, kind, prec, ctypes.byref(t)))
+        _check(L.ax_tune_get(N1 - 1, kind, prec, ctypes.byref(t)))
     finally:
-        _check(L.ax_tune_set(N1 - 1, kind, AX_FP64, ctypes.byref(saved)))
-    return {"elems_per_group": t.elems_per_group, "block": t.block}
+        _check(L.ax_tune_set(N1 - 1, kind, prec, ctypes.byref(saved)))
+    return {"kernel": "tile" if t.kernel_used == AX_KERNEL_TILE else "item",
+            "elems_per_group": t.elems_per_group, "block": t.block}
 
 
 def probe_copy(src, dst, stream=None):

@@ -108,8 +108,7 @@ def _variants(N: int, kind: int, prec: int):
     saved = tune_get(N, kind, prec)
     out, seen = [], set()
     try:
-        kernels = (AX_KERNEL_ITEM,) if kind == AX_TUNE_BATCHED else (AX_KERNEL_TILE, AX_KERNEL_ITEM)
-        for kern, ta, ia, wa in itertools.product(kernels, (0, 1), (0, 1), (0, 1)):
+        for kern, ta, ia, wa in itertools.product((AX_KERNEL_TILE, AX_KERNEL_ITEM), (0, 1), (0, 1), (0, 1)):
             tune_set(N, kind, prec, kernel=kern, tile_alt=ta, item_alt=ia, waves_alt=wa)
             r = tune_get(N, kind, prec)
             if r["kernel_used"] != kern:
@@ -144,6 +143,7 @@ def _time_configs(fns, cands, apply, rounds=3, reps=12, warmup=4):
 
 
 NBUF = 4          # rotating X/Y pairs
+BATCH_COLS = 8    # columns of the batched workload
 
 
 def _workloads(N, prec, target_nodes, kinds):
@@ -181,15 +181,18 @@ def _workloads(N, prec, target_nodes, kinds):
         del l0, l1
         work["helmholtz"] = [lambda q=q: ax_local_helmholtz(Xs[q], V, L23, b, prec, out=Ys[q]) for q in range(NBUF)]
     if "batched" in kinds and N <= 9:
-        # eight meshes of this order of uneven size (the batched kernels' work lists)
+        # eight meshes of this order of uneven size (the batched kernels' work lists) with
+        # BATCH_COLS columns, as the batched benchmark runs them
         sizes = [max(1, m.E * f // 36) for f in (8, 7, 6, 5, 4, 3, 2, 1)]
         meshes, off = [], 0
         for s in sizes:
             meshes.append((V[off:off + s], b))
             off += s
-        views = [[x[:, a:a + s] for a, s in zip(itertools.accumulate([0] + sizes[:-1]), sizes)] for x in Xs]
-        outs = [[y[:, a:a + s] for a, s in zip(itertools.accumulate([0] + sizes[:-1]), sizes)] for y in Ys]
-        work["batched"] = (meshes, views, outs)
+        Xb = [meshgen.random_nodal_device(m.E, N, BATCH_COLS, seed=N + q, dtype=dt) for q in range(NBUF)]
+        Yb = [torch.empty_like(x) for x in Xb]
+        views = [[x[:, a:a + s] for a, s in zip(itertools.accumulate([0] + sizes[:-1]), sizes)] for x in Xb]
+        outs = [[y[:, a:a + s] for a, s in zip(itertools.accumulate([0] + sizes[:-1]), sizes)] for y in Yb]
+        work["batched"] = (meshes, views, outs, BATCH_COLS)
     return m.E * NP, work
 
 
@@ -210,13 +213,14 @@ def tune(orders=range(1, 16), kinds=tuple(KINDS), precs=tuple(PRECS), target_nod
                 cands = [dict(v, grid_mult=g) for v in variants for g in GRID_MULTS]
                 cands.insert(0, dict(DEFAULT))
                 if kname == "batched":
-                    meshes, views, outs = work["batched"]
+                    meshes, views, outs, ncol = work["batched"]
                     plans = {}
 
                     def fn_for(cfg):
-                        key = cfg["item_alt"]
+                        # a plan keeps the kernel and shape it was prepared with: one per variant
+                        key = (cfg["kernel"], cfg["item_alt"])
                         if key not in plans:
-                            tune_set(N, kind, prec, item_alt=key)
+                            tune_set(N, kind, prec, kernel=cfg["kernel"], item_alt=cfg["item_alt"])
                             plans[key] = [BatchedAxLocal(meshes, list(views[q]), list(outs[q]), prec)
                                           for q in range(NBUF)]
                         return [p.launch for p in plans[key]]
@@ -228,6 +232,9 @@ def tune(orders=range(1, 16), kinds=tuple(KINDS), precs=tuple(PRECS), target_nod
                 else:
                     times = _time_configs(work[kname], cands, lambda c: tune_set(N, kind, prec, **c))
                 t_def = times[0]
+                if kname == "batched":
+                    times = [t / ncol for t in times]   # per column, as ndof counts one
+                    t_def = times[0]
                 q = min(range(len(cands)), key=lambda i: times[i])
                 chosen = cands[q] if times[q] < (1.0 - MARGIN) * t_def else cands[0]
                 t_best = times[q] if chosen is cands[q] else t_def

@@ -109,11 +109,14 @@ extern "C" int ax_tune_get(int N, int kind, int prec, ax_tune* t)
     const int N1 = N + 1;
     const bool fp32 = prec == AX_FP32;
     const TuneEntry e = tune_get(N1, kind, prec);
-    const int geo = kind == TUNE_TRI ? GEO_TRI : kind == TUNE_PARTIAL ? GEO_TRIL : kind == TUNE_PARA ? GEO_PARA
-                  : kind == TUNE_STORED ? GEO_STORED : GEO_HELM;
-    const bool item = kind == TUNE_BATCHED ||
-                      (item_available(N1, geo) &&
-                       (e.kernel == AX_KERNEL_ITEM || (e.kernel == AX_KERNEL_AUTO && item_default(N1, geo, fp32))));
+    const int geo = (kind == TUNE_TRI || kind == TUNE_BATCHED) ? GEO_TRI : kind == TUNE_PARTIAL ? GEO_TRIL
+                  : kind == TUNE_PARA ? GEO_PARA : kind == TUNE_STORED ? GEO_STORED : GEO_HELM;
+    // the batched kernels: the per-item kernel unless the entry asks for the tile kernel and the
+    // order has one (it takes the default tile shape)
+    const bool item = kind == TUNE_BATCHED
+                          ? !(e.kernel == AX_KERNEL_TILE && batched_tile_available(N1, fp32))
+                          : (item_available(N1, geo) &&
+                             (e.kernel == AX_KERNEL_ITEM || (e.kernel == AX_KERNEL_AUTO && item_default(N1, geo, fp32))));
     *t = ax_tune{e.kernel, e.tile_alt, e.item_alt, e.waves_alt, e.grid_mult, 0, 0, 0, 0};
     t->kernel_used = item ? AX_KERNEL_ITEM : AX_KERNEL_TILE;
     if (item) {
@@ -122,7 +125,7 @@ extern "C" int ax_tune_get(int N, int kind, int prec, ax_tune* t)
         t->block = sh.block;
         t->waves = kind == TUNE_BATCHED ? batch_waves(fp32) : item_waves(N1, fp32, geo == GEO_TRIL, e.waves_alt);
     } else {
-        t->elems_per_group = tile_epb(N1, e.tile_alt != 0);
+        t->elems_per_group = tile_epb(N1, kind != TUNE_BATCHED && e.tile_alt != 0);
         t->block = ((t->elems_per_group * N1 * N1 + 63) / 64) * 64;
         t->waves = tile_waves(N1, geo, fp32);
     }

@@ -92,6 +92,12 @@ constexpr bool item_default(int N1, int geo, bool fp32)
     return (geo == GEO_TRI && N1 >= AX_ITEM_LO && N1 != 8) || (geo == GEO_TRIL && N1 >= 9);
 }
 
+// Orders with a batched tile kernel (the single-mesh tile body walking the batch's work list):
+// FP64 up to N1 = 7, FP32 up to N1 = 10.  At FP64 N1 >= 8 the work-list addressing on top of the
+// resident tables spills (N1 = 8: 472 bytes of scratch; 45 against 214 GDOF/s for the per-item
+// kernel on sixteen order-7 meshes of 512 to 32768 elements, 8 columns).
+constexpr bool batched_tile_available(int N1, bool fp32) { return fp32 ? N1 <= 10 : N1 <= 7; }
+
 // Register budget of the batched per-order kernels: FP32 fits five waves per SIMD.
 #ifndef AX_BATCH_MINW_F32
 #define AX_BATCH_MINW_F32 5

@@ -197,6 +197,13 @@ __device__ __forceinline__ void group_sync()
     }
 }
 
+// Element groups of one mesh walked in order (group g holds elements [g EPB, g EPB + EPB)): the
+// single-mesh launches.  The batched launches pass a work list of (mesh, group) items over many
+// meshes of one order instead (kList), which supplies each group's addresses.
+struct OneMeshWalk {
+    static constexpr bool kList = false;
+};
+
 // Kernel body.  GATHER 1: X is a global vector [nrhs][ldg] read through the local-to-global map
 // l2g (the Q of Sec. 2.1 fused into the load), so the solver never materialises Q x.  GATHER 2
 // (one column, the CG's operator): as 1, and each work-group also writes the sum of its
@@ -205,13 +212,16 @@ __device__ __forceinline__ void group_sync()
 // contraction coefficients (CoefResident or CoefReload).  Local vectors: node l of column c of
 // element e at c * ccs + e * es + l (es = N1^3, ccs = E N1^3 for [nrhs][E][N1^3];
 // es = nrhs N1^3, ccs = N1^3 for the component-interleaved [E][nrhs][N1^3] of a vector field).
-template <int N1, int GEO, bool EO, int GATHER, int EPBX, typename T, typename C>
+// With a work list `wl` (W::kList, trilinear only, es = N1^3) the element groups and their
+// addresses come from the list; E, geo, X, Y, l2g, ldg and ccs are then unused.
+template <int N1, int GEO, bool EO, int GATHER, int EPBX, typename T, typename C, typename W = OneMeshWalk>
 __device__ __forceinline__ void
 ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __restrict__ Gs,
               const T* __restrict__ X, T* __restrict__ Y, const Basis<T>& bs,
               const int32_t* __restrict__ l2g, int64_t ldg, int64_t es, int64_t ccs, double* __restrict__ epart,
-              const C& cs)
+              const C& cs, const W& wl = W{})
 {
+    static_assert(!W::kList || GEO == GEO_TRI, "work lists carry trilinear meshes");
     using S = Shape<N1, sizeof(T)>;
     using TL = Tile<N1, EPBX>;
     constexpr int NT = S::NT, FS = S::FS, NP = S::NP, EPB = TL::EPB;
@@ -238,7 +248,11 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
     const int i = lane % N1, j = lane / N1;    // home lane: node column (i, j, :)
     const int pa = S::spa(lane), pb = S::spb(lane);  // s-pencil lane (i, k)
     const int ra = S::rpa(lane), rb = S::rpb(lane);  // r-pencil lane (j, k)
-    const int64_t nblk = (E + EPB - 1) / EPB;
+    int64_t nblk;
+    if constexpr (W::kList)
+        nblk = wl.groups();
+    else
+        nblk = (E + EPB - 1) / EPB;
     if (tid < 2 * N1) sxw[tid] = (tid & 1) ? bs.w[tid >> 1] : bs.xi[tid >> 1];
     group_sync<BLOCK>();   // sxw is read by every wave from the first element on
     // the D-contractions: forward (D) and transposed (D^T), on the matrix cores or the vector ALU
@@ -268,7 +282,12 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
     // 32-bit lane offset; a group past the end is clamped to group 0 and slots past the last
     // element read the group's first element (results of such slots are never stored).
     auto clamp_group = [&](int64_t ebq) -> int64_t { return ebq < nblk ? ebq : 0; };
-    auto slot_active = [&](int64_t g) -> bool { return (slot < EPB) && (g * EPB + slot < E); };
+    auto slot_active = [&](int64_t g) -> bool {
+        if constexpr (W::kList)
+            return (slot < EPB) && wl.has(g, slot);
+        else
+            return (slot < EPB) && (g * EPB + slot < E);
+    };
     // byte offset of node (i, j, 0) of this lane's element from the group's first node
     auto home_off = [&](bool act) -> uint32_t {
         return (uint32_t)(((act ? slot * es : 0) + i + j * N1) * (int64_t)sizeof(T));
@@ -277,15 +296,26 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
         const int64_t g = clamp_group(ebq);
         const uint32_t lo = home_off(slot_active(g));
         if constexpr (GATHER) {
-            const int32_t* mb = l2g + g * EPB * NP;
+            const int32_t* mb;
+            const T* xc;
+            if constexpr (W::kList) {
+                mb = wl.map(g);
+                xc = wl.template xglob<T>(g, cq);
+            } else {
+                mb = l2g + g * EPB * NP;
+                xc = X + (int64_t)cq * ldg;
+            }
             int32_t gi[N1];
 #pragma unroll
             for (int k = 0; k < N1; ++k) gi[k] = *at_bytes(mb, lo / sizeof(T) * 4 + k * NT * 4);
-            const T* xc = X + (int64_t)cq * ldg;
 #pragma unroll
             for (int k = 0; k < N1; ++k) dst[k] = xc[gi[k]];
         } else {
-            const T* src = X + (int64_t)cq * ccs + g * EPB * es;
+            const T* src;
+            if constexpr (W::kList)
+                src = wl.template xsrc<T>(g, cq);
+            else
+                src = X + (int64_t)cq * ccs + g * EPB * es;
 #pragma unroll
             for (int k = 0; k < N1; ++k) dst[k] = *at_bytes(src, lo + k * NT * (uint32_t)sizeof(T));
         }
@@ -293,8 +323,15 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
     auto load_v = [&](int64_t ebq, double* dst) {
         if constexpr (is_trilinear(GEO)) {
             const int64_t g = clamp_group(ebq);
-            const double* src = geo + g * EPB * 24;
-            const int64_t lim = (E - g * EPB) * 24;   // vertex words left from the group start
+            const double* src;
+            int64_t lim;   // vertex words left from the group start
+            if constexpr (W::kList) {
+                src = wl.verts(g);
+                lim = wl.left(g) * 24;
+            } else {
+                src = geo + g * EPB * 24;
+                lim = (E - g * EPB) * 24;
+            }
 #pragma unroll
             for (int q = 0; q < VPT; ++q) {
                 const int idx = tid + q * BLOCK;
@@ -501,7 +538,11 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
 #pragma unroll
             for (int k = 0; k < N1; ++k) y2[k] = fma(l3v[k], xv[k], y2[k]);
         }
-        T* yb = Y + (int64_t)c * ccs + eb * EPB * es;
+        T* yb;
+        if constexpr (W::kList)
+            yb = wl.template ydst<T>(eb, c);
+        else
+            yb = Y + (int64_t)c * ccs + eb * EPB * es;
         const uint32_t lo = home_off(true);
 #if AX_MERGE_RS
         // P5: Y = (D_r^T r + D_s^T s) + D_t^T t

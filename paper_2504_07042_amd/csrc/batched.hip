@@ -16,6 +16,7 @@
 #include <mutex>
 #include <vector>
 
+#include "ax_local_impl.h"
 #include "item.h"
 
 namespace ax {
@@ -43,13 +44,127 @@ order_item_kernel(const BItem* __restrict__ items, const BMesh* __restrict__ mes
     }
 }
 
+// The work list walked by the tile kernel (shape variant kTileVariant): group g is item
+// items[g], an element group of EPB elements of one mesh; every mesh of the list has the order
+// of the launch and es = N1^3.
+template <int EPB, int NP>
+struct MeshListWalk {
+    static constexpr bool kList = true;
+    const BItem* __restrict__ items;
+    const BMesh* __restrict__ meshes;
+    int64_t n;
+    __device__ __forceinline__ int64_t groups() const { return n; }
+    __device__ __forceinline__ bool has(int64_t g, int slot) const
+    {
+        const BItem it = items[g];
+        return (int64_t)it.eb * EPB + slot < meshes[it.mesh].E;
+    }
+    __device__ __forceinline__ int64_t left(int64_t g) const
+    {
+        const BItem it = items[g];
+        return meshes[it.mesh].E - (int64_t)it.eb * EPB;
+    }
+    __device__ __forceinline__ const double* verts(int64_t g) const
+    {
+        const BItem it = items[g];
+        return meshes[it.mesh].verts + (int64_t)it.eb * EPB * 24;
+    }
+    template <typename T>
+    __device__ __forceinline__ const T* xsrc(int64_t g, int c) const
+    {
+        const BItem it = items[g];
+        const BMesh& m = meshes[it.mesh];
+        return static_cast<const T*>(m.X) + (int64_t)c * m.ld + (int64_t)it.eb * EPB * NP;
+    }
+    __device__ __forceinline__ const int32_t* map(int64_t g) const
+    {
+        const BItem it = items[g];
+        return meshes[it.mesh].l2g + (int64_t)it.eb * EPB * NP;
+    }
+    template <typename T>
+    __device__ __forceinline__ const T* xglob(int64_t g, int c) const
+    {
+        const BMesh& m = meshes[items[g].mesh];
+        return static_cast<const T*>(m.X) + (int64_t)c * m.ldg;
+    }
+    template <typename T>
+    __device__ __forceinline__ T* ydst(int64_t g, int c) const
+    {
+        const BItem it = items[g];
+        const BMesh& m = meshes[it.mesh];
+        return static_cast<T*>(m.Y) + (int64_t)c * m.ld + (int64_t)it.eb * EPB * NP;
+    }
+};
+
+// Per-order persistent kernel over the items [0, n) of one order with the prefetching tile body
+// of the single-mesh launches (one item ahead, across meshes): the kernel the single-mesh tuning
+// picks at the orders where it beats the per-item one.
+template <int N1, typename T, bool G>
+__global__ void __launch_bounds__((Tile<N1, Shape<N1>::EPB>::BLOCK), (min_waves<N1, GEO_TRI, T>()))
+order_tile_kernel(const BItem* __restrict__ items, const BMesh* __restrict__ meshes, int64_t n, int nrhs,
+                  const Basis<T>* __restrict__ bsp)
+{
+    constexpr int EPB = Shape<N1>::EPB, NP = N1 * N1 * N1;
+    static_assert(batched_tile_available(N1, sizeof(T) == 4), "no batched tile kernel at this order");
+    const MeshListWalk<EPB, NP> wl{items, meshes, n};
+    const Basis<T>& bs = *bsp;
+    ax_local_body<N1, GEO_TRI, true, G ? 1 : 0, EPB, T>(0, nrhs, nullptr, nullptr, nullptr, nullptr, bs, nullptr, 0,
+                                                         NP, 0, nullptr, CoefResident<T>{bs}, wl);
+}
+
+// Shape variant of the tile kernel (0 and 1 are the per-item shapes of item_shape).
+constexpr int kTileVariant = 2;
+
+static int tile_items_epb(int N1)
+{
+    switch (N1) {
+    case 2: return Shape<2>::EPB;
+    case 3: return Shape<3>::EPB;
+    case 4: return Shape<4>::EPB;
+    case 5: return Shape<5>::EPB;
+    case 6: return Shape<6>::EPB;
+    case 7: return Shape<7>::EPB;
+    case 8: return Shape<8>::EPB;
+    case 9: return Shape<9>::EPB;
+    default: return Shape<10>::EPB;
+    }
+}
+
 // Elements per item of order N1 in shape variant V.
-static int order_epb(int N1, int V) { return item_shape(N1, V).epb; }
+static int order_epb(int N1, int V) { return V == kTileVariant ? tile_items_epb(N1) : item_shape(N1, V).epb; }
 
 // The shape variant the tuning table selects for the batched kernel of order N1.
 static int order_variant(int N1, int prec)
 {
-    return item_has_alt(N1) ? tune_get(N1, TUNE_BATCHED, prec).item_alt : 0;
+    const TuneEntry t = tune_get(N1, TUNE_BATCHED, prec);
+    if (t.kernel == AX_KERNEL_TILE && batched_tile_available(N1, prec == AX_FP32)) return kTileVariant;
+    return item_has_alt(N1) ? t.item_alt : 0;
+}
+
+template <int N1, typename T, bool G>
+static int order_tile_launch(const char* ws, const BHeader& h, int64_t first, int64_t count, hipStream_t st)
+{
+    const BItem* items = reinterpret_cast<const BItem*>(ws + h.off_items) + first;
+    const BMesh* meshes = reinterpret_cast<const BMesh*>(ws + h.off_mesh);
+    const Basis<T>* bsp = reinterpret_cast<const Basis<T>*>(ws + h.off_basis) + (N1 - 2);
+    const TuneEntry tu = tune_get(N1, TUNE_BATCHED, sizeof(T) == 8 ? AX_FP64 : AX_FP32);
+    constexpr int BLOCK = Tile<N1, Shape<N1>::EPB>::BLOCK;
+    static int per = 0, cus = 0;
+    if (per == 0) {
+        int dev = 0, c = 256, q = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&q, order_tile_kernel<N1, T, G>, BLOCK, 0) != hipSuccess ||
+            q < 1)
+            q = 1;
+        cus = c;
+        per = q;
+    }
+    const int64_t cap = (int64_t)cus * per * (tu.grid_mult > 0 ? tu.grid_mult : 1);
+    const unsigned grid = (unsigned)std::min<int64_t>(count, cap);
+    hipLaunchKernelGGL((order_tile_kernel<N1, T, G>), dim3(grid), dim3(BLOCK), 0, st, items, meshes, count, h.nrhs,
+                       bsp);
+    return hip_check(hipGetLastError(), "batched tile launch");
 }
 
 template <int N1, typename T, int V, bool G>
@@ -82,6 +197,12 @@ template <int N1, typename T>
 static int order_launch_v(int V, bool G, const char* ws, const BHeader& h, int64_t first, int64_t count,
                           hipStream_t st)
 {
+    if (V == kTileVariant) {
+        if constexpr (batched_tile_available(N1, sizeof(T) == 4))
+            return G ? order_tile_launch<N1, T, true>(ws, h, first, count, st)
+                     : order_tile_launch<N1, T, false>(ws, h, first, count, st);
+        return fail(AX_ERR_ARG, "no batched tile kernel at N1 = %d in this precision", N1);
+    }
     if (G)
         return V ? order_launch<N1, T, 1, true>(ws, h, first, count, st)
                  : order_launch<N1, T, 0, true>(ws, h, first, count, st);
@@ -114,7 +235,8 @@ static int64_t n_items_of(int n_mesh, const ax_problem* meshes, int prec)
     int64_t n = 0;
     for (int q = 0; q < n_mesh; ++q) {
         const int N1 = meshes[q].N + 1;
-        const int e = prec < 0 ? std::min(order_epb(N1, 0), order_epb(N1, 1)) : order_epb(N1, order_variant(N1, prec));
+        const int e = prec < 0 ? std::min({order_epb(N1, 0), order_epb(N1, 1), order_epb(N1, kTileVariant)})
+                               : order_epb(N1, order_variant(N1, prec));
         n += (meshes[q].E + e - 1) / e;
     }
     return n;
@@ -474,7 +596,7 @@ extern "C" int ax_local_batched(const ax_batch_plan* plan, const void* workspace
     if (!plan || !workspace) return fail(AX_ERR_ARG, "plan or workspace is NULL");
     if (plan->prec != AX_FP64 && plan->prec != AX_FP32) return fail(AX_ERR_ARG, "plan was not filled by ax_batched_prepare");
     for (int N1 = 2; N1 <= kBMaxN1; ++N1)
-        if (plan->order_variant[N1] != 0 && plan->order_variant[N1] != 1)
+        if (plan->order_variant[N1] < 0 || plan->order_variant[N1] > kTileVariant)
             return fail(AX_ERR_ARG, "plan was not filled by ax_batched_prepare (shape variant %d)", plan->order_variant[N1]);
     if (plan->gather != 0 && plan->gather != 1) return fail(AX_ERR_ARG, "plan was not filled by ax_batched_prepare");
     if (plan->n_items == 0) return AX_OK;

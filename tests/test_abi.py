@@ -130,7 +130,19 @@ def test_tuning_roundtrip(ax):
         assert len(v) == 5 and len({tuple(sorted(d.items())) for d in v}) == 5
         assert sum(d["kernel"] == ax.AX_KERNEL_ITEM for d in v) == 4
         assert len(autotune._variants(11, ax.AX_TUNE_STORED, ax.AX_FP32)) == 1
-        assert len(autotune._variants(3, ax.AX_TUNE_BATCHED, ax.AX_FP64)) == 2
+        # batched: two per-item shapes, plus the tile kernel over the work list where the order has
+        # one (FP64 up to N = 6)
+        assert len(autotune._variants(3, ax.AX_TUNE_BATCHED, ax.AX_FP64)) == 3
+        assert len(autotune._variants(7, ax.AX_TUNE_BATCHED, ax.AX_FP64)) == 2
+        assert len(autotune._variants(7, ax.AX_TUNE_BATCHED, ax.AX_FP32)) == 3
+        saved_b = {prec: autotune.tune_get(7, ax.AX_TUNE_BATCHED, prec) for prec in (ax.AX_FP64, ax.AX_FP32)}
+        autotune.tune_set(7, ax.AX_TUNE_BATCHED, ax.AX_FP32, kernel=ax.AX_KERNEL_TILE)
+        t = autotune.tune_get(7, ax.AX_TUNE_BATCHED, ax.AX_FP32)
+        assert (t["kernel_used"], t["elems_per_group"], t["block"]) == (ax.AX_KERNEL_TILE, 1, 64)
+        autotune.tune_set(7, ax.AX_TUNE_BATCHED, ax.AX_FP64, kernel=ax.AX_KERNEL_TILE)
+        assert autotune.tune_get(7, ax.AX_TUNE_BATCHED, ax.AX_FP64)["kernel_used"] == ax.AX_KERNEL_ITEM
+        for prec, sv in saved_b.items():
+            autotune.tune_set(7, ax.AX_TUNE_BATCHED, prec, **{k: sv[k] for k in autotune.KNOBS})
     finally:
         autotune.tune_set(7, K, P, **{k: before[k] for k in autotune.KNOBS})
     assert autotune.tune_get(7, K, P) == before

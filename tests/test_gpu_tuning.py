@@ -2,7 +2,8 @@
 kernel (tile or per-item; work-group shape; register budget; persistent grid) is checked against
 the oracle, and variants of one kernel against each other bit for bit (they differ only in how
 elements are grouped and scheduled, not in the arithmetic per element).  The batched kernels'
-two work-group shapes likewise."""
+two per-item work-group shapes likewise, and their tile kernel over the work list against the
+single-mesh tile kernel."""
 import numpy as np
 import pytest
 
@@ -99,14 +100,22 @@ def test_batched_shapes(ax, prec):
         if P == ax.AX_FP32:
             fac.append(fp32_bound(N, cond_j_per_element(m.verts, N))[None, :, None])
     saved = {N: autotune.tune_get(N, ax.AX_TUNE_BATCHED, P) for N in range(1, 10)}
+    saved_tri = {N: autotune.tune_get(N, ax.AX_TUNE_TRILINEAR, P) for N in range(1, 10)}
     outs = {}
     try:
-        for alt in (0, 1):
+        # shape variants 0 and 1 of the per-item kernel, 2 the tile kernel over the work list
+        for alt in (0, 1, 2):
             for N in range(1, 10):
-                autotune.tune_set(N, ax.AX_TUNE_BATCHED, P, item_alt=alt)
+                if alt == 2:
+                    autotune.tune_set(N, ax.AX_TUNE_BATCHED, P, kernel=ax.AX_KERNEL_TILE, item_alt=0, grid_mult=1)
+                else:
+                    autotune.tune_set(N, ax.AX_TUNE_BATCHED, P, kernel=ax.AX_KERNEL_AUTO, item_alt=alt)
             Y = [torch.empty_like(x) for x in X]
             plan = ax.BatchedAxLocal(meshes, X, Y, P)
-            assert list(plan.plan.order_variant)[2:11] == [alt] * 9
+            # the tile kernel exists up to N = 6 in FP64 and N = 9 in FP32 (per-item shape 0 beyond)
+            top = 6 if P == ax.AX_FP64 else 9
+            want = [alt] * 9 if alt < 2 else [2 if N <= top else 0 for N in range(1, 10)]
+            assert list(plan.plan.order_variant)[2:11] == want
             plan.launch()
             torch.cuda.synchronize()
             outs[alt] = [y.double().cpu().numpy() for y in Y]
@@ -116,8 +125,19 @@ def test_batched_shapes(ax, prec):
                     check_fp64(outs[alt][q], Yref[q], env[q], tag=tag)
                 else:
                     check_bound(outs[alt][q], Yref[q], env[q], fac[q], tag=tag)
+        # the tile kernel over the work list computes each element exactly as the single-mesh
+        # tile kernel does
+        for N in range(1, 10):
+            autotune.tune_set(N, ax.AX_TUNE_TRILINEAR, P, kernel=ax.AX_KERNEL_TILE, tile_alt=0)
+        for q, (N, _) in enumerate(specs):
+            if N > top:
+                continue
+            Ys = ax.ax_local(X[q], meshes[q][0], meshes[q][1], ax.AX_TRILINEAR, P)
+            assert np.array_equal(outs[2][q], Ys.double().cpu().numpy()), q
     finally:
         for N, s in saved.items():
             autotune.tune_set(N, ax.AX_TUNE_BATCHED, P, **{k: s[k] for k in autotune.KNOBS})
+        for N, s in saved_tri.items():
+            autotune.tune_set(N, ax.AX_TUNE_TRILINEAR, P, **{k: s[k] for k in autotune.KNOBS})
     for a, b in zip(outs[0], outs[1]):
         assert np.array_equal(a, b)
