@@ -197,6 +197,10 @@ __device__ __forceinline__ void group_sync()
     }
 }
 
+#ifndef AX_GATHER_XCD
+#define AX_GATHER_XCD 1
+#endif
+
 // Element groups of one mesh walked in order (group g holds elements [g EPB, g EPB + EPB)): the
 // single-mesh launches.  The batched launches pass a work list of (mesh, group) items over many
 // meshes of one order instead (kList), which supplies each group's addresses.
@@ -353,7 +357,14 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
         }
     };
 
-    int64_t eb = blockIdx.x;
+    // The gathering forms read shared nodes through l2g: elements adjacent in the mesh touch the
+    // same cache lines of the global vector, so the work-groups of one XCD (one L2) take runs of
+    // consecutive element groups (xcd_tile) instead of every eighth one.
+    int64_t eb;
+    if constexpr (GATHER != 0 && AX_GATHER_XCD)
+        eb = xcd_tile(blockIdx.x, gridDim.x);
+    else
+        eb = blockIdx.x;
     int c = 0;
     T xr[N1];
     double vr[VPT > 0 ? VPT : 1];

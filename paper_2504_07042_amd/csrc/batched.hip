@@ -38,7 +38,10 @@ order_item_kernel(const BItem* __restrict__ items, const BMesh* __restrict__ mes
     __shared__ __attribute__((aligned(16))) char lds[BShape<N1, V>::template lds_bytes<T>()];
     lds_poison(lds, sizeof(lds));
     const CoefReload<T> cs{as_constant(bsp)};
-    for (int64_t it = blockIdx.x; it < n; it += gridDim.x) {
+    // the gathering form: runs of consecutive items (neighbouring elements, which read the same
+    // cache lines of the global vector) on the work-groups of one XCD
+    const int64_t it0 = (G && AX_GATHER_XCD) ? xcd_tile(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+    for (int64_t it = it0; it < n; it += gridDim.x) {
         const BItem q = items[it];
         batched_item<N1, V, T, false, G>(meshes[q.mesh], q.eb, nrhs, cs, lds);
     }

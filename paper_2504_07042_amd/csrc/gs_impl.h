@@ -45,20 +45,4 @@ __device__ __forceinline__ void gather_sums(const IP* __restrict__ gptr, const i
 // nodes (or local entries) per thread and tile in the gather-scatter kernels
 constexpr int kUnroll = 4;
 
-// XCD-aware tile order.  Work-groups are dispatched round-robin over the 8 XCDs of the chip,
-// each with its own L2, so tile b and tile b + 1 (which gather from the same cache lines of the
-// source vector) would land on different L2s.  Tile index of work-group b: within each window of
-// 8 S tiles, the work-groups of one XCD (b = x, x + 8, ...) take S consecutive tiles, so
-// neighbouring tiles share an L2 while the 8 XCDs still stream from one region of memory at a
-// time.  Work-groups past the last whole window keep the plain order.
-#ifndef AX_XCD_CHUNK
-#define AX_XCD_CHUNK 64
-#endif
-__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t G)
-{
-    constexpr int64_t kXcd = 8, S = AX_XCD_CHUNK, W = kXcd * S;
-    if (b >= (G / W) * W) return b;
-    return (b / W) * W + (b % kXcd) * S + (b / kXcd) % S;
-}
-
 }  // namespace ax
