@@ -174,10 +174,14 @@ copy_pairs_kernel(CopyPair* __restrict__ cp, const int64_t* __restrict__ gptr, c
 
 // Ap[g] = mask ? 0 : sum of the local copies (ascending local id, the order of the plain loop)
 // and, fused, the partial sums of p . Ap over the same fixed grid as dot_partial_kernel.  Each
-// thread takes kUnroll nodes per tile so that their loads are in flight together.
+// thread takes kQtUnroll nodes per tile so that their loads are in flight together.
 // FOLD (after the fused operator): p . Ap comes from AxLocal's per-work-group energies
 // epart[0, nparts), folded onto this fixed grid (block b takes b, b + gridDim.x, ...), so p is
 // not read.
+#ifndef AX_QT_UNROLL
+#define AX_QT_UNROLL 4
+#endif
+constexpr int kQtUnroll = AX_QT_UNROLL;
 template <typename T, bool FOLD>
 __global__ void __launch_bounds__(kRedThreads)
 qt_dot_kernel(int64_t n_global, const CopyPair* __restrict__ cp, const int64_t* __restrict__ gptr,
@@ -196,18 +200,18 @@ qt_dot_kernel(int64_t n_global, const CopyPair* __restrict__ cp, const int64_t* 
 #define AX_QT_XCD 0
 #endif
     const int64_t tile0 = AX_QT_XCD ? xcd_tile(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
-    for (int64_t g0 = tile0 * kRedThreads * kUnroll + threadIdx.x; g0 < n_global;
-         g0 += (int64_t)gridDim.x * kRedThreads * kUnroll) {
-        CopyPair q[kUnroll];
+    for (int64_t g0 = tile0 * kRedThreads * kQtUnroll + threadIdx.x; g0 < n_global;
+         g0 += (int64_t)gridDim.x * kRedThreads * kQtUnroll) {
+        CopyPair q[kQtUnroll];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
+        for (int u = 0; u < kQtUnroll; ++u) {
             const int64_t g = g0 + u * kRedThreads;
             q[u] = g < n_global ? cp[g] : CopyPair{-1, -1};
         }
-        T v0[kUnroll], v1[kUnroll];
-        int64_t b[kUnroll], e[kUnroll];
+        T v0[kQtUnroll], v1[kQtUnroll];
+        int64_t b[kQtUnroll], e[kQtUnroll];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
+        for (int u = 0; u < kQtUnroll; ++u) {
             v0[u] = q[u].first >= 0 ? x[q[u].first] : T(0);
             v1[u] = q[u].second >= 0 ? x[q[u].second] : T(0);
             const bool many = q[u].second == -2;
@@ -215,7 +219,7 @@ qt_dot_kernel(int64_t n_global, const CopyPair* __restrict__ cp, const int64_t* 
             e[u] = many ? gptr[g0 + u * kRedThreads + 1] : 0;
         }
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
+        for (int u = 0; u < kQtUnroll; ++u) {
             const int64_t g = g0 + u * kRedThreads;
             if (g < n_global) {
                 T s = T(0) + v0[u];
