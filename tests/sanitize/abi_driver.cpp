@@ -123,6 +123,20 @@ int main()
     EXPECT(ax_parallelepiped_factors(-2, (double*)P(8), (double*)P(16), nullptr), AX_ERR_ARG);
     EXPECT(ax_parallelepiped_factors(0, nullptr, nullptr, nullptr), AX_OK);
     EXPECT(ax_node_coords(2, 3, (double*)P(8), nullptr, (double*)P(16), nullptr), AX_ERR_ARG);
+    // the gathering operator and its energy form reject bad arguments before any launch
+    const int32_t* map = (const int32_t*)P(32);
+    EXPECT(ax_local_gathered(4, 3, AX_TRILINEAR, (double*)P(8), D, xi, w, 1, AX_FP64, nullptr, 10, P(16), P(24),
+                             nullptr), AX_ERR_ARG);
+    EXPECT(ax_local_gathered(4, 3, AX_TRILINEAR, (double*)P(8), D, xi, w, 1, AX_FP16_ACC32, map, 10, P(16), P(24),
+                             nullptr), AX_ERR_UNSUPPORTED);
+    EXPECT(ax_local_gathered(0, 3, AX_TRILINEAR, nullptr, D, xi, w, 1, AX_FP64, nullptr, 10, nullptr, nullptr,
+                             nullptr), AX_OK);
+    EXPECT(ax_local_gathered_energy(4, 3, AX_TRILINEAR, (double*)P(8), D, xi, w, map, 10, (const float*)P(16),
+                                    (float*)P(24), (double*)P(40), nullptr, nullptr), AX_ERR_ARG);
+    EXPECT(ax_local_gathered_energy(4, 3, AX_TRILINEAR, (double*)P(8), D, xi, w, map, 10, (const float*)P(16),
+                                    (float*)P(24), nullptr, (double*)P(48), nullptr), AX_ERR_ARG);
+    EXPECT(ax_local_gathered_energy(4, 3, AX_TRILINEAR, (double*)P(8), D, xi, w, map, 0, (const float*)P(16),
+                                    (float*)P(24), (double*)P(40), (double*)P(48), nullptr), AX_ERR_ARG);
     int64_t bad = 7;
     double dmin = 0;
     EXPECT(ax_check_mesh(0, 3, nullptr, xi, &bad, &dmin, nullptr), AX_OK);
