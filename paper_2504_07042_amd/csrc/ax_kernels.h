@@ -93,9 +93,10 @@ constexpr bool item_default(int N1, int geo, bool fp32)
 }
 
 // Orders with a batched tile kernel (the single-mesh tile body walking the batch's work list):
-// FP64 up to N1 = 7, FP32 up to N1 = 10.  At FP64 N1 >= 8 the work-list addressing on top of the
-// resident tables spills (N1 = 8: 472 bytes of scratch; 45 against 214 GDOF/s for the per-item
-// kernel on sixteen order-7 meshes of 512 to 32768 elements, 8 columns).
+// FP64 up to N1 = 7, FP32 up to N1 = 10.  At FP64 N1 >= 8 the kernel spills (N1 = 8: 464-496
+// bytes of scratch with the tables resident, read through the constant address space or reloaded
+// per row, whether or not the item descriptors are re-read at each use; 45 against 214 GDOF/s for
+// the per-item kernel on sixteen order-7 meshes of 512 to 32768 elements, 8 columns).
 constexpr bool batched_tile_available(int N1, bool fp32) { return fp32 ? N1 <= 10 : N1 <= 7; }
 
 // Register budget of the batched per-order kernels: FP32 fits five waves per SIMD.
@@ -253,6 +254,23 @@ struct CoefReload {
         asm volatile("" : "+s"(q));
         return CoefReload{q};
     }
+    __device__ __forceinline__ T D(int q) const { return k->D[q]; }
+    __device__ __forceinline__ T P(int q) const { return k->P[q]; }
+    __device__ __forceinline__ T M(int q) const { return k->M[q]; }
+    __device__ __forceinline__ T Cm(int q) const { return k->Cm[q]; }
+    __device__ __forceinline__ T Rm(int q) const { return k->Rm[q]; }
+    __device__ __forceinline__ double xi(int q) const { return k->xi[q]; }
+    __device__ __forceinline__ double w(int q) const { return k->w[q]; }
+};
+
+// Basis tables in device memory read through the constant address space and left to the
+// compiler to keep in scalar registers or reload (loads there are invariant, so it can
+// rematerialise them under register pressure instead of spilling): the resident tables of a
+// kernel that receives them by pointer.
+template <typename T>
+struct CoefConst {
+    KargPtr<Basis<T>> k;
+    __device__ __forceinline__ CoefConst row() const { return *this; }
     __device__ __forceinline__ T D(int q) const { return k->D[q]; }
     __device__ __forceinline__ T P(int q) const { return k->P[q]; }
     __device__ __forceinline__ T M(int q) const { return k->M[q]; }

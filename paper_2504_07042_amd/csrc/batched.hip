@@ -49,7 +49,9 @@ order_item_kernel(const BItem* __restrict__ items, const BMesh* __restrict__ mes
 
 // The work list walked by the tile kernel (shape variant kTileVariant): group g is item
 // items[g], an element group of EPB elements of one mesh; every mesh of the list has the order
-// of the launch and es = N1^3.
+// of the launch and es = N1^3.  Each lookup re-reads the item's descriptor (scalar loads; the
+// group index is laundered so that the compiler does not keep descriptors live across the
+// item's phases: FP32 N1 = 8 then fits 127 VGPRs without scratch).
 template <int EPB, int NP>
 struct MeshListWalk {
     static constexpr bool kList = true;
@@ -59,22 +61,26 @@ struct MeshListWalk {
     __device__ __forceinline__ int64_t groups() const { return n; }
     __device__ __forceinline__ bool has(int64_t g, int slot) const
     {
+        asm volatile("" : "+s"(g));
         const BItem it = items[g];
         return (int64_t)it.eb * EPB + slot < meshes[it.mesh].E;
     }
     __device__ __forceinline__ int64_t left(int64_t g) const
     {
+        asm volatile("" : "+s"(g));
         const BItem it = items[g];
         return meshes[it.mesh].E - (int64_t)it.eb * EPB;
     }
     __device__ __forceinline__ const double* verts(int64_t g) const
     {
+        asm volatile("" : "+s"(g));
         const BItem it = items[g];
         return meshes[it.mesh].verts + (int64_t)it.eb * EPB * 24;
     }
     template <typename T>
     __device__ __forceinline__ const T* xsrc(int64_t g, int c) const
     {
+        asm volatile("" : "+s"(g));
         const BItem it = items[g];
         const BMesh& m = meshes[it.mesh];
         return static_cast<const T*>(m.X) + (int64_t)c * m.ld + (int64_t)it.eb * EPB * NP;
@@ -93,6 +99,7 @@ struct MeshListWalk {
     template <typename T>
     __device__ __forceinline__ T* ydst(int64_t g, int c) const
     {
+        asm volatile("" : "+s"(g));
         const BItem it = items[g];
         const BMesh& m = meshes[it.mesh];
         return static_cast<T*>(m.Y) + (int64_t)c * m.ld + (int64_t)it.eb * EPB * NP;
@@ -112,7 +119,7 @@ order_tile_kernel(const BItem* __restrict__ items, const BMesh* __restrict__ mes
     const MeshListWalk<EPB, NP> wl{items, meshes, n};
     const Basis<T>& bs = *bsp;
     ax_local_body<N1, GEO_TRI, true, G ? 1 : 0, EPB, T>(0, nrhs, nullptr, nullptr, nullptr, nullptr, bs, nullptr, 0,
-                                                         NP, 0, nullptr, CoefResident<T>{bs}, wl);
+                                                         NP, 0, nullptr, CoefConst<T>{as_constant(bsp)}, wl);
 }
 
 // Shape variant of the tile kernel (0 and 1 are the per-item shapes of item_shape).

@@ -120,10 +120,11 @@ def test_tuning_roundtrip(ax):
         assert autotune.tune_get(7, ax.AX_TUNE_PARTIAL, P)["kernel_used"] == ax.AX_KERNEL_TILE
         autotune.tune_set(7, ax.AX_TUNE_PARTIAL, P, kernel=ax.AX_KERNEL_AUTO)
         # batched: per-item, shape per order
-        autotune.tune_set(3, ax.AX_TUNE_BATCHED, ax.AX_FP32, item_alt=1)
+        saved3 = autotune.tune_get(3, ax.AX_TUNE_BATCHED, ax.AX_FP32)
+        autotune.tune_set(3, ax.AX_TUNE_BATCHED, ax.AX_FP32, kernel=ax.AX_KERNEL_AUTO, item_alt=1)
         t = autotune.tune_get(3, ax.AX_TUNE_BATCHED, ax.AX_FP32)
         assert (t["kernel_used"], t["elems_per_group"], t["block"], t["waves"]) == (ax.AX_KERNEL_ITEM, 8, 128, 5)
-        autotune.tune_set(3, ax.AX_TUNE_BATCHED, ax.AX_FP32, item_alt=0)
+        autotune.tune_set(3, ax.AX_TUNE_BATCHED, ax.AX_FP32, **{k: saved3[k] for k in autotune.KNOBS})
         # the variants the tuner enumerates at N1 = 12: one tile shape (no alternative there) and
         # the per-item kernel in two shapes times two register budgets
         v = autotune._variants(11, K, ax.AX_FP32)
