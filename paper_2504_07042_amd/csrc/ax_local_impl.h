@@ -213,7 +213,7 @@ struct OneMeshWalk {
 // (one column, the CG's operator): as 1, and each work-group also writes the sum of its
 // elements' energies (D X_e)^T G_e (D X_e) = X_e^T Y_e to epart[blockIdx.x], which sums to
 // p^T A p when X = Q p and p vanishes on the masked nodes.  `cs` is the source of the
-// contraction coefficients (CoefResident or CoefReload).  Local vectors: node l of column c of
+// contraction coefficients (CoefResident, CoefReload or CoefConst).  Local vectors: node l of column c of
 // element e at c * ccs + e * es + l (es = N1^3, ccs = E N1^3 for [nrhs][E][N1^3];
 // es = nrhs N1^3, ccs = N1^3 for the component-interleaved [E][nrhs][N1^3] of a vector field).
 // With a work list `wl` (W::kList, trilinear only, es = N1^3) the element groups and their

@@ -87,12 +87,14 @@ struct MeshListWalk {
     }
     __device__ __forceinline__ const int32_t* map(int64_t g) const
     {
+        asm volatile("" : "+s"(g));
         const BItem it = items[g];
         return meshes[it.mesh].l2g + (int64_t)it.eb * EPB * NP;
     }
     template <typename T>
     __device__ __forceinline__ const T* xglob(int64_t g, int c) const
     {
+        asm volatile("" : "+s"(g));
         const BMesh& m = meshes[items[g].mesh];
         return static_cast<const T*>(m.X) + (int64_t)c * m.ldg;
     }
@@ -107,8 +109,8 @@ struct MeshListWalk {
 };
 
 // Per-order persistent kernel over the items [0, n) of one order with the prefetching tile body
-// of the single-mesh launches (one item ahead, across meshes): the kernel the single-mesh tuning
-// picks at the orders where it beats the per-item one.
+// of the single-mesh launches (one item ahead, across meshes), for the orders whose batched
+// tuning entry asks for it (kernel = TILE).
 template <int N1, typename T, bool G>
 __global__ void __launch_bounds__((Tile<N1, Shape<N1>::EPB>::BLOCK), (min_waves<N1, GEO_TRI, T>()))
 order_tile_kernel(const BItem* __restrict__ items, const BMesh* __restrict__ meshes, int64_t n, int nrhs,
