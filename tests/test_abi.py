@@ -336,3 +336,19 @@ def test_gathered_energy_validation(ax):
     assert call(Xg=16, Y=16) == ax.AX_ERR_ARG
     assert call(N=0) == ax.AX_ERR_UNSUPPORTED
     assert len(L.ax_last_error()) > 0
+
+
+def test_recorded_measurements_match_the_sources():
+    """The shipped launch-variant cache and the headline kernel's recorded HBM traffic were both
+    measured on the kernel sources as they are: a change to those sources must be followed by a
+    re-run of the tuner and of the FETCH_SIZE / WRITE_SIZE passes (the bench line would otherwise
+    report a stale cache and a null traffic figure)."""
+    import sys
+    from paper_2504_07042_amd import autotune
+    assert autotune.cache_status() == "current"
+    sys.path.insert(0, ROOT)
+    import bench
+    traffic = bench.measured_traffic(7, 32768)
+    assert traffic is not None
+    # calibrated bytes per launch within 2 % of the algorithmic 32768 x 8384 B
+    assert abs(traffic / (32768 * 8384) - 1.0) < 0.02
