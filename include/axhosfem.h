@@ -144,8 +144,9 @@ int ax_local_vector(int64_t E, int N, int geom, const double* geo, const double*
  *              time, tables reloaded per output row); ITEM exists for the trilinear full form
  *              (every order) and the partial form (N >= 8) on GLL bases: elsewhere the tile
  *              kernel runs.  AX_TUNE_BATCHED: AX_KERNEL_TILE runs the tile kernel (default
- *              shape) over the work list where the order has one (FP64 N <= 6, FP32 N <= 9),
- *              AUTO and ITEM the per-item kernel.
+ *              shape): with tile_alt 0 over the work list where the order has that form (FP64
+ *              N <= 6, FP32 N <= 9), with tile_alt 1 over mesh slices (each work-group walks one
+ *              mesh, every order); AUTO and ITEM the per-item kernel.
  *   tile_alt   tile kernel: 0 default elements per work-group, 1 the alternative shape;
  *   item_alt   per-item kernels (single-mesh and batched): 0 a 256-lane work-group, 1 the
  *              order's alternative shape (N <= 12; see elems_per_group and block);
@@ -426,7 +427,8 @@ typedef struct {
     int64_t order_first[11];  /* items of order N1 = N + 1 (2..10): [order_first[N1], +order_count[N1]) */
     int64_t order_count[11];
     int order_variant[11];    /* kernel and work-group shape of order N1 at prepare time: 0, 1 the
-                                 per-item shapes (ax_tune.item_alt), 2 the tile kernel */
+                                 per-item shapes (ax_tune.item_alt), 2 the tile kernel over the
+                                 work list, 3 the tile kernel over mesh slices */
 } ax_batch_plan;
 
 int ax_batched_workspace_bytes(int n_mesh, const ax_problem* meshes, size_t* bytes);

@@ -491,9 +491,9 @@ class BatchedAxLocal:
 
 def item_shape_of(N1: int, variant: int, prec=AX_FP64) -> dict:
     """Work-group shape of the batched kernels of order N1 - 1 in a plan's shape variant (0 or 1
-    the per-item shapes, 2 the tile kernel) and precision."""
-    if int(variant) == 2:
-        t = AxTune(kernel=AX_KERNEL_TILE, grid_mult=2)
+    the per-item shapes, 2 the tile kernel over the work list, 3 over mesh slices) and precision."""
+    if int(variant) in (2, 3):
+        t = AxTune(kernel=AX_KERNEL_TILE, tile_alt=int(variant) - 2, grid_mult=2)
     else:
         t = AxTune(kernel=AX_KERNEL_ITEM, item_alt=int(variant), grid_mult=2)
     saved = AxTune()
@@ -505,8 +505,8 @@ def item_shape_of(N1: int, variant: int, prec=AX_FP64) -> dict:
         _check(L.ax_tune_get(N1 - 1, kind, prec, ctypes.byref(t)))
     finally:
         _check(L.ax_tune_set(N1 - 1, kind, prec, ctypes.byref(saved)))
-    return {"kernel": "tile" if t.kernel_used == AX_KERNEL_TILE else "item",
-            "elems_per_group": t.elems_per_group, "block": t.block}
+    kernel = "item" if t.kernel_used != AX_KERNEL_TILE else ("tile slices" if int(variant) == 3 else "tile")
+    return {"kernel": kernel, "elems_per_group": t.elems_per_group, "block": t.block}
 
 
 def probe_copy(src, dst, stream=None):

@@ -113,7 +113,9 @@ def _variants(N: int, kind: int, prec: int):
             r = tune_get(N, kind, prec)
             if r["kernel_used"] != kern:
                 continue
-            key = (r["kernel_used"], r["elems_per_group"], r["block"], r["waves"])
+            key = (r["kernel_used"], r["elems_per_group"], r["block"], r["waves"],
+                   # batched: the tile kernel walks the work list (tile_alt 0) or mesh slices (1)
+                   ta if kind == AX_TUNE_BATCHED and kern == AX_KERNEL_TILE else 0)
             if key in seen:
                 continue
             seen.add(key)
@@ -218,9 +220,10 @@ def tune(orders=range(1, 16), kinds=tuple(KINDS), precs=tuple(PRECS), target_nod
 
                     def fn_for(cfg):
                         # a plan keeps the kernel and shape it was prepared with: one per variant
-                        key = (cfg["kernel"], cfg["item_alt"])
+                        key = (cfg["kernel"], cfg["item_alt"], cfg["tile_alt"])
                         if key not in plans:
-                            tune_set(N, kind, prec, kernel=cfg["kernel"], item_alt=cfg["item_alt"])
+                            tune_set(N, kind, prec, kernel=cfg["kernel"], item_alt=cfg["item_alt"],
+                                     tile_alt=cfg["tile_alt"])
                             plans[key] = [BatchedAxLocal(meshes, list(views[q]), list(outs[q]), prec)
                                           for q in range(NBUF)]
                         return [p.launch for p in plans[key]]

@@ -111,10 +111,11 @@ extern "C" int ax_tune_get(int N, int kind, int prec, ax_tune* t)
     const TuneEntry e = tune_get(N1, kind, prec);
     const int geo = (kind == TUNE_TRI || kind == TUNE_BATCHED) ? GEO_TRI : kind == TUNE_PARTIAL ? GEO_TRIL
                   : kind == TUNE_PARA ? GEO_PARA : kind == TUNE_STORED ? GEO_STORED : GEO_HELM;
-    // the batched kernels: the per-item kernel unless the entry asks for the tile kernel and the
-    // order has one (it takes the default tile shape)
+    // the batched kernels: the per-item kernel unless the entry asks for the tile kernel (it takes
+    // the default tile shape; tile_alt 0 walks the work list where the order has that form,
+    // tile_alt 1 gives each work-group a slice of one mesh)
     const bool item = kind == TUNE_BATCHED
-                          ? !(e.kernel == AX_KERNEL_TILE && batched_tile_available(N1, fp32))
+                          ? !(e.kernel == AX_KERNEL_TILE && (e.tile_alt != 0 || batched_tile_available(N1, fp32)))
                           : (item_available(N1, geo) &&
                              (e.kernel == AX_KERNEL_ITEM || (e.kernel == AX_KERNEL_AUTO && item_default(N1, geo, fp32))));
     *t = ax_tune{e.kernel, e.tile_alt, e.item_alt, e.waves_alt, e.grid_mult, 0, 0, 0, 0};

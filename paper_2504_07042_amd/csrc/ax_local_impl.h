@@ -202,10 +202,13 @@ __device__ __forceinline__ void group_sync()
 #endif
 
 // Element groups of one mesh walked in order (group g holds elements [g EPB, g EPB + EPB)): the
-// single-mesh launches.  The batched launches pass a work list of (mesh, group) items over many
-// meshes of one order instead (kList), which supplies each group's addresses.
+// single-mesh launches, work-group b taking groups b, b + gridDim.x, ...  The batched launches
+// pass either a work list of (mesh, group) items over many meshes of one order (kList), which
+// supplies each group's addresses, or a slice of one mesh (kSlice: the work-group takes groups
+// first, first + stride, ... of the mesh given to it).
 struct OneMeshWalk {
     static constexpr bool kList = false;
+    static constexpr bool kSlice = false;
 };
 
 // Kernel body.  GATHER 1: X is a global vector [nrhs][ldg] read through the local-to-global map
@@ -361,7 +364,9 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
     // same cache lines of the global vector, so the work-groups of one XCD (one L2) take runs of
     // consecutive element groups (xcd_tile) instead of every eighth one.
     int64_t eb;
-    if constexpr (GATHER != 0 && AX_GATHER_XCD)
+    if constexpr (W::kSlice)
+        eb = wl.first;
+    else if constexpr (GATHER != 0 && AX_GATHER_XCD)
         eb = xcd_tile(blockIdx.x, gridDim.x);
     else
         eb = blockIdx.x;
@@ -381,7 +386,11 @@ ax_local_body(int64_t E, int nrhs, const double* __restrict__ geo, const T* __re
         const bool active = slot_active(eb);
         const int64_t e = eb * EPB + slot;
         const bool last_col = (c + 1 == nrhs);
-        const int64_t eb_n = last_col ? eb + gridDim.x : eb;
+        int64_t eb_n;
+        if constexpr (W::kSlice)
+            eb_n = last_col ? eb + wl.stride : eb;
+        else
+            eb_n = last_col ? eb + gridDim.x : eb;
         const int c_n = last_col ? 0 : c + 1;
         if constexpr (GEO == GEO_PARA) {
             if (c == 0) {

@@ -55,6 +55,7 @@ order_item_kernel(const BItem* __restrict__ items, const BMesh* __restrict__ mes
 template <int EPB, int NP>
 struct MeshListWalk {
     static constexpr bool kList = true;
+    static constexpr bool kSlice = false;
     const BItem* __restrict__ items;
     const BMesh* __restrict__ meshes;
     int64_t n;
@@ -124,8 +125,95 @@ order_tile_kernel(const BItem* __restrict__ items, const BMesh* __restrict__ mes
                                                          NP, 0, nullptr, CoefConst<T>{as_constant(bsp)}, wl);
 }
 
-// Shape variant of the tile kernel (0 and 1 are the per-item shapes of item_shape).
+// One mesh's share of a slice launch: groups first, first + stride, ... of the mesh.
+struct MeshSliceWalk {
+    static constexpr bool kList = false;
+    static constexpr bool kSlice = true;
+    int64_t first, stride;
+};
+
+// The slice form: each work-group is given one mesh of the order (items[blockIdx.x] = (mesh, w),
+// the mesh's work-groups numbered w = 0 .. wgs - 1) and walks that mesh's element groups exactly
+// as the single-mesh tile kernel does, the mesh's descriptor read once.  Nothing of the work list
+// stays live over an item, so the kernel has the single-mesh kernel's register footprint at every
+// order (the list form spills at FP64 N1 >= 8).
+template <int N1, typename T, bool G>
+__global__ void __launch_bounds__((Tile<N1, Shape<N1>::EPB>::BLOCK), (min_waves<N1, GEO_TRI, T>()))
+order_slice_kernel(const BItem* __restrict__ items, const BMesh* __restrict__ meshes, int nrhs,
+                   const Basis<T>* __restrict__ bsp)
+{
+    constexpr int EPB = Shape<N1>::EPB, NP = N1 * N1 * N1;
+    const BItem sl = items[blockIdx.x];
+    const BMesh m = meshes[sl.mesh];
+    const MeshSliceWalk wl{sl.eb, m.wgs};
+    const Basis<T>& bs = *bsp;
+    ax_local_body<N1, GEO_TRI, true, G ? 1 : 0, EPB, T>(m.E, nrhs, m.verts, nullptr, static_cast<const T*>(m.X),
+                                                         static_cast<T*>(m.Y), bs, G ? m.l2g : nullptr, m.ldg, NP, m.ld,
+                                                         nullptr, CoefConst<T>{as_constant(bsp)}, wl);
+}
+
+// Shape variants of the batched launches: 0 and 1 the per-item shapes of item_shape, 2 the tile
+// kernel over the work list, 3 the tile kernel over mesh slices.
 constexpr int kTileVariant = 2;
+constexpr int kSliceVariant = 3;
+
+// Resident work-groups per CU of the slice kernel of order N1 (once per instantiation).
+template <int N1, typename T, bool G>
+static int slice_per_cu()
+{
+    static int per = 0;
+    if (per == 0) {
+        int q = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&q, order_slice_kernel<N1, T, G>,
+                                                         Tile<N1, Shape<N1>::EPB>::BLOCK, 0) != hipSuccess ||
+            q < 1)
+            q = 1;
+        per = q;
+    }
+    return per;
+}
+
+template <typename T, bool G>
+static int slice_per_cu_of(int N1)
+{
+    switch (N1) {
+    case 2: return slice_per_cu<2, T, G>();
+    case 3: return slice_per_cu<3, T, G>();
+    case 4: return slice_per_cu<4, T, G>();
+    case 5: return slice_per_cu<5, T, G>();
+    case 6: return slice_per_cu<6, T, G>();
+    case 7: return slice_per_cu<7, T, G>();
+    case 8: return slice_per_cu<8, T, G>();
+    case 9: return slice_per_cu<9, T, G>();
+    default: return slice_per_cu<10, T, G>();
+    }
+}
+
+// Work-groups of a slice launch of order N1: the tuned multiple of the resident capacity, at
+// most one per element group; split over the meshes in proportion to their element groups (at
+// least one each, at most one per group).  groups[q] in, wgs[q] out (n meshes; no allocation);
+// returns the total.
+static int64_t slice_split(int N1, int prec, bool gather, const int64_t* groups, int64_t* wgs, int n)
+{
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        cus = 256;
+    (void)hipGetLastError();
+    const int per = prec == AX_FP64 ? (gather ? slice_per_cu_of<double, true>(N1) : slice_per_cu_of<double, false>(N1))
+                                    : (gather ? slice_per_cu_of<float, true>(N1) : slice_per_cu_of<float, false>(N1));
+    const int gm = tune_get(N1, TUNE_BATCHED, prec).grid_mult;
+    int64_t total = 0;
+    for (int q = 0; q < n; ++q) total += groups[q];
+    const int64_t cap = std::min<int64_t>(total, (int64_t)cus * per * (gm > 0 ? gm : 1));
+    int64_t sum = 0;
+    for (int q = 0; q < n; ++q) {
+        const double share = total > 0 ? (double)cap * (double)groups[q] / (double)total : 0.0;
+        wgs[q] = std::max<int64_t>(1, std::min<int64_t>(groups[q], (int64_t)std::llround(share)));
+        sum += wgs[q];
+    }
+    return sum;
+}
 
 static int tile_items_epb(int N1)
 {
@@ -143,12 +231,16 @@ static int tile_items_epb(int N1)
 }
 
 // Elements per item of order N1 in shape variant V.
-static int order_epb(int N1, int V) { return V == kTileVariant ? tile_items_epb(N1) : item_shape(N1, V).epb; }
+static int order_epb(int N1, int V)
+{
+    return (V == kTileVariant || V == kSliceVariant) ? tile_items_epb(N1) : item_shape(N1, V).epb;
+}
 
 // The shape variant the tuning table selects for the batched kernel of order N1.
 static int order_variant(int N1, int prec)
 {
     const TuneEntry t = tune_get(N1, TUNE_BATCHED, prec);
+    if (t.kernel == AX_KERNEL_TILE && t.tile_alt) return kSliceVariant;
     if (t.kernel == AX_KERNEL_TILE && batched_tile_available(N1, prec == AX_FP32)) return kTileVariant;
     return item_has_alt(N1) ? t.item_alt : 0;
 }
@@ -205,10 +297,25 @@ static int order_launch(const char* ws, const BHeader& h, int64_t first, int64_t
     return hip_check(hipGetLastError(), "batched launch");
 }
 
+template <int N1, typename T, bool G>
+static int order_slice_launch(const char* ws, const BHeader& h, int64_t first, int64_t count, hipStream_t st)
+{
+    const BItem* items = reinterpret_cast<const BItem*>(ws + h.off_items) + first;
+    const BMesh* meshes = reinterpret_cast<const BMesh*>(ws + h.off_mesh);
+    const Basis<T>* bsp = reinterpret_cast<const Basis<T>*>(ws + h.off_basis) + (N1 - 2);
+    if (count > 0x7fffffff) return fail(AX_ERR_UNSUPPORTED, "too many work-groups for one launch");
+    hipLaunchKernelGGL((order_slice_kernel<N1, T, G>), dim3((unsigned)count), dim3(Tile<N1, Shape<N1>::EPB>::BLOCK), 0,
+                       st, items, meshes, h.nrhs, bsp);
+    return hip_check(hipGetLastError(), "batched slice launch");
+}
+
 template <int N1, typename T>
 static int order_launch_v(int V, bool G, const char* ws, const BHeader& h, int64_t first, int64_t count,
                           hipStream_t st)
 {
+    if (V == kSliceVariant)
+        return G ? order_slice_launch<N1, T, true>(ws, h, first, count, st)
+                 : order_slice_launch<N1, T, false>(ws, h, first, count, st);
     if (V == kTileVariant) {
         if constexpr (batched_tile_available(N1, sizeof(T) == 4))
             return G ? order_tile_launch<N1, T, true>(ws, h, first, count, st)
@@ -401,6 +508,13 @@ static int batched_noalloc(int n_mesh, const ax_problem* meshes, int nrhs, int p
         });
         plan.order_first[N1] = next;
         const int e = order_epb(N1, var[N1]);
+        // slice form: each mesh's work-group count (stack arrays: this path allocates nothing)
+        int64_t sgroups[kScratchMaxMeshes], swgs[kScratchMaxMeshes];
+        const bool slices = var[N1] == kSliceVariant && cnt > 0;
+        if (slices) {
+            for (int c = 0; c < cnt; ++c) sgroups[c] = (meshes[idx[c]].E + e - 1) / e;
+            slice_split(N1, prec, false, sgroups, swgs, cnt);
+        }
         for (int c0 = 0; c0 < cnt; c0 += kFillChunk) {
             MeshFill f{};
             int64_t gmax = 1;
@@ -409,9 +523,10 @@ static int batched_noalloc(int n_mesh, const ax_problem* meshes, int nrhs, int p
                 const ax_problem& p = meshes[idx[c0 + c]];
                 const int64_t np = (int64_t)N1 * N1 * N1;
                 f.id[c] = idx[c0 + c];
-                f.m[c] = BMesh{p.E, col_stride ? col_stride[f.id[c]] : p.E * np, p.geo, X[f.id[c]], Y[f.id[c]], N1, 0,
-                               np};
-                f.groups[c] = (p.E + e - 1) / e;
+                f.m[c] = BMesh{p.E, col_stride ? col_stride[f.id[c]] : p.E * np, p.geo, X[f.id[c]], Y[f.id[c]], N1,
+                               slices ? (int)swgs[c0 + c] : 0, np};
+                // items: the mesh's element groups, or its work-groups in the slice form
+                f.groups[c] = slices ? swgs[c0 + c] : (p.E + e - 1) / e;
                 f.item_base[c] = next;
                 next += f.groups[c];
                 gmax = std::max(gmax, f.groups[c]);
@@ -534,15 +649,27 @@ static int batched_prepare(int n_mesh, const ax_problem* meshes, int nrhs, int p
         std::stable_sort(order.begin(), order.end());
         plan->order_first[N1] = (int64_t)items.size();
         const int e = order_epb(N1, plan->order_variant[N1]);
-        for (auto& o : order) {
-            const int64_t groups = (meshes[o.second].E + e - 1) / e;
-            for (int64_t g = 0; g < groups; ++g) items.push_back(BItem{o.second, (int)g});
+        if (plan->order_variant[N1] == kSliceVariant && !order.empty()) {
+            // slices: work-group w of mesh q is item (q, w); the mesh records its work-group count
+            std::vector<int64_t> groups, wgs(order.size());
+            for (auto& o : order) groups.push_back((meshes[o.second].E + e - 1) / e);
+            slice_split(N1, prec, l2g != nullptr, groups.data(), wgs.data(), (int)order.size());
+            for (size_t k = 0; k < order.size(); ++k) {
+                bm[order[k].second].wgs = (int)wgs[k];
+                for (int64_t w = 0; w < wgs[k]; ++w) items.push_back(BItem{order[k].second, (int)w});
+            }
+        } else {
+            for (auto& o : order) {
+                const int64_t groups = (meshes[o.second].E + e - 1) / e;
+                for (int64_t g = 0; g < groups; ++g) items.push_back(BItem{o.second, (int)g});
+            }
         }
         plan->order_count[N1] = (int64_t)items.size() - plan->order_first[N1];
     }
     std::memcpy(host.data(), &h, sizeof(h));
     if (n_mesh) std::memcpy(host.data() + h.off_mesh, bm.data(), sizeof(BMesh) * n_mesh);
-    if (n_items) std::memcpy(host.data() + h.off_items, items.data(), sizeof(BItem) * n_items);
+    // (slice orders use fewer items than the element groups the layout was sized for)
+    if (!items.empty()) std::memcpy(host.data() + h.off_items, items.data(), sizeof(BItem) * items.size());
     // GLL tables of every order used, indexed by N1 - 2
     for (int q = 0; q < n_mesh; ++q) {
         const int N1 = meshes[q].N + 1;
@@ -608,7 +735,7 @@ extern "C" int ax_local_batched(const ax_batch_plan* plan, const void* workspace
     if (!plan || !workspace) return fail(AX_ERR_ARG, "plan or workspace is NULL");
     if (plan->prec != AX_FP64 && plan->prec != AX_FP32) return fail(AX_ERR_ARG, "plan was not filled by ax_batched_prepare");
     for (int N1 = 2; N1 <= kBMaxN1; ++N1)
-        if (plan->order_variant[N1] < 0 || plan->order_variant[N1] > kTileVariant)
+        if (plan->order_variant[N1] < 0 || plan->order_variant[N1] > kSliceVariant)
             return fail(AX_ERR_ARG, "plan was not filled by ax_batched_prepare (shape variant %d)", plan->order_variant[N1]);
     if (plan->gather != 0 && plan->gather != 1) return fail(AX_ERR_ARG, "plan was not filled by ax_batched_prepare");
     if (plan->n_items == 0) return AX_OK;

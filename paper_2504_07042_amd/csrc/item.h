@@ -24,7 +24,7 @@ struct BMesh {
     const void* X;
     void* Y;
     int N1;
-    int pad;
+    int wgs;     // slice form of the batched tile kernel: work-groups given to this mesh
     int64_t es;  // stride between elements of X and Y (values): N1^3, or ncol N1^3 interleaved
     // gathering form (kernels instantiated with GATHER): X is a global vector read through l2g
     // (this mesh's part of the map, local element-major numbering), columns ldg values apart

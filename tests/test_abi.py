@@ -131,17 +131,20 @@ def test_tuning_roundtrip(ax):
         assert len(v) == 5 and len({tuple(sorted(d.items())) for d in v}) == 5
         assert sum(d["kernel"] == ax.AX_KERNEL_ITEM for d in v) == 4
         assert len(autotune._variants(11, ax.AX_TUNE_STORED, ax.AX_FP32)) == 1
-        # batched: two per-item shapes, plus the tile kernel over the work list where the order has
-        # one (FP64 up to N = 6)
-        assert len(autotune._variants(3, ax.AX_TUNE_BATCHED, ax.AX_FP64)) == 3
-        assert len(autotune._variants(7, ax.AX_TUNE_BATCHED, ax.AX_FP64)) == 2
-        assert len(autotune._variants(7, ax.AX_TUNE_BATCHED, ax.AX_FP32)) == 3
+        # batched: two per-item shapes, the tile kernel over mesh slices, and over the work list
+        # where the order has that form (FP64 up to N = 6)
+        assert len(autotune._variants(3, ax.AX_TUNE_BATCHED, ax.AX_FP64)) == 4
+        assert len(autotune._variants(7, ax.AX_TUNE_BATCHED, ax.AX_FP64)) == 3
+        assert len(autotune._variants(7, ax.AX_TUNE_BATCHED, ax.AX_FP32)) == 4
         saved_b = {prec: autotune.tune_get(7, ax.AX_TUNE_BATCHED, prec) for prec in (ax.AX_FP64, ax.AX_FP32)}
-        autotune.tune_set(7, ax.AX_TUNE_BATCHED, ax.AX_FP32, kernel=ax.AX_KERNEL_TILE)
+        autotune.tune_set(7, ax.AX_TUNE_BATCHED, ax.AX_FP32, kernel=ax.AX_KERNEL_TILE, tile_alt=0)
         t = autotune.tune_get(7, ax.AX_TUNE_BATCHED, ax.AX_FP32)
         assert (t["kernel_used"], t["elems_per_group"], t["block"]) == (ax.AX_KERNEL_TILE, 1, 64)
-        autotune.tune_set(7, ax.AX_TUNE_BATCHED, ax.AX_FP64, kernel=ax.AX_KERNEL_TILE)
+        autotune.tune_set(7, ax.AX_TUNE_BATCHED, ax.AX_FP64, kernel=ax.AX_KERNEL_TILE, tile_alt=0)
         assert autotune.tune_get(7, ax.AX_TUNE_BATCHED, ax.AX_FP64)["kernel_used"] == ax.AX_KERNEL_ITEM
+        autotune.tune_set(7, ax.AX_TUNE_BATCHED, ax.AX_FP64, kernel=ax.AX_KERNEL_TILE, tile_alt=1)
+        t = autotune.tune_get(7, ax.AX_TUNE_BATCHED, ax.AX_FP64)
+        assert (t["kernel_used"], t["elems_per_group"], t["block"]) == (ax.AX_KERNEL_TILE, 1, 64)
         for prec, sv in saved_b.items():
             autotune.tune_set(7, ax.AX_TUNE_BATCHED, prec, **{k: sv[k] for k in autotune.KNOBS})
     finally:

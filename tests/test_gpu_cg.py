@@ -151,20 +151,20 @@ def test_graph_replay_equals_eager(ax):
     assert torch.equal(xg, xe)
 
 
-@pytest.mark.parametrize("kernel", ["auto", "tile"])
+@pytest.mark.parametrize("kernel", ["auto", "tile", "slices"])
 @pytest.mark.parametrize("inner", ["fp64", "fp32"])
 def test_batched_cg_union(ax, inner, kernel):
     """CG over the block-diagonal union of meshes of different order, with one batched AxLocal
-    launch per step (the per-item kernels or, forced, the tile kernel over the work list, both
-    gathering the global vector); the oracle recomputes every mesh's residual of the GPU
-    solution."""
+    launch per step (the per-item kernels or, forced, the tile kernel over the work list or over
+    mesh slices, all gathering the global vector); the oracle recomputes every mesh's residual of
+    the GPU solution."""
     import torch
     from paper_2504_07042_amd import autotune
     precs = (ax.AX_FP64, ax.AX_FP32)
     saved = {(N, P): autotune.tune_get(N, ax.AX_TUNE_BATCHED, P) for N in range(1, 10) for P in precs}
-    if kernel == "tile":
+    if kernel != "auto":
         for (N, P) in saved:
-            autotune.tune_set(N, ax.AX_TUNE_BATCHED, P, kernel=ax.AX_KERNEL_TILE)
+            autotune.tune_set(N, ax.AX_TUNE_BATCHED, P, kernel=ax.AX_KERNEL_TILE, tile_alt=int(kernel == "slices"))
     try:
         _batched_cg_union(ax, inner)
     finally:

@@ -2,8 +2,8 @@
 kernel (tile or per-item; work-group shape; register budget; persistent grid) is checked against
 the oracle, and variants of one kernel against each other bit for bit (they differ only in how
 elements are grouped and scheduled, not in the arithmetic per element).  The batched kernels'
-two per-item work-group shapes likewise, and their tile kernel over the work list against the
-single-mesh tile kernel."""
+two per-item work-group shapes likewise, and their tile kernel (over the work list and over mesh
+slices) against the single-mesh tile kernel."""
 import numpy as np
 import pytest
 
@@ -103,18 +103,22 @@ def test_batched_shapes(ax, prec):
     saved_tri = {N: autotune.tune_get(N, ax.AX_TUNE_TRILINEAR, P) for N in range(1, 10)}
     outs = {}
     try:
-        # shape variants 0 and 1 of the per-item kernel, 2 the tile kernel over the work list
-        for alt in (0, 1, 2):
+        # shape variants 0 and 1 of the per-item kernel, 2 the tile kernel over the work list, 3 the
+        # tile kernel over mesh slices
+        for alt in (0, 1, 2, 3):
             for N in range(1, 10):
                 if alt == 2:
-                    autotune.tune_set(N, ax.AX_TUNE_BATCHED, P, kernel=ax.AX_KERNEL_TILE, item_alt=0, grid_mult=1)
+                    autotune.tune_set(N, ax.AX_TUNE_BATCHED, P, kernel=ax.AX_KERNEL_TILE, tile_alt=0, item_alt=0,
+                                      grid_mult=1)
+                elif alt == 3:
+                    autotune.tune_set(N, ax.AX_TUNE_BATCHED, P, kernel=ax.AX_KERNEL_TILE, tile_alt=1, grid_mult=1)
                 else:
                     autotune.tune_set(N, ax.AX_TUNE_BATCHED, P, kernel=ax.AX_KERNEL_AUTO, item_alt=alt)
             Y = [torch.empty_like(x) for x in X]
             plan = ax.BatchedAxLocal(meshes, X, Y, P)
             # the tile kernel exists up to N = 6 in FP64 and N = 9 in FP32 (per-item shape 0 beyond)
             top = 6 if P == ax.AX_FP64 else 9
-            want = [alt] * 9 if alt < 2 else [2 if N <= top else 0 for N in range(1, 10)]
+            want = [2 if N <= top else 0 for N in range(1, 10)] if alt == 2 else [alt] * 9
             assert list(plan.plan.order_variant)[2:11] == want
             plan.launch()
             torch.cuda.synchronize()
@@ -130,10 +134,10 @@ def test_batched_shapes(ax, prec):
         for N in range(1, 10):
             autotune.tune_set(N, ax.AX_TUNE_TRILINEAR, P, kernel=ax.AX_KERNEL_TILE, tile_alt=0)
         for q, (N, _) in enumerate(specs):
-            if N > top:
-                continue
-            Ys = ax.ax_local(X[q], meshes[q][0], meshes[q][1], ax.AX_TRILINEAR, P)
-            assert np.array_equal(outs[2][q], Ys.double().cpu().numpy()), q
+            Ys = ax.ax_local(X[q], meshes[q][0], meshes[q][1], ax.AX_TRILINEAR, P).double().cpu().numpy()
+            assert np.array_equal(outs[3][q], Ys), q
+            if N <= top:
+                assert np.array_equal(outs[2][q], Ys), q
     finally:
         for N, s in saved.items():
             autotune.tune_set(N, ax.AX_TUNE_BATCHED, P, **{k: s[k] for k in autotune.KNOBS})

@@ -30,11 +30,28 @@ def _batch(ax, specs, nrhs, dtype, seed):
     return meshes, X
 
 
+@pytest.mark.parametrize("form", ["tuned", "slices"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_noalloc_matches_workspace_path(ax, prec):
+def test_noalloc_matches_workspace_path(ax, prec, form):
+    """`form`: the launch variants of the tuning table, or every order forced to the tile kernel
+    over mesh slices (each mesh's work-group count then comes from the same split in both
+    paths)."""
+    from paper_2504_07042_amd import autotune
+    p = ax.AX_FP64 if prec == "fp64" else ax.AX_FP32
+    saved = {N: autotune.tune_get(N, ax.AX_TUNE_BATCHED, p) for N in (3, 5, 7, 9)}
+    if form == "slices":
+        for N in saved:
+            autotune.tune_set(N, ax.AX_TUNE_BATCHED, p, kernel=ax.AX_KERNEL_TILE, tile_alt=1)
+    try:
+        _noalloc_vs_workspace(ax, prec, p)
+    finally:
+        for N, sv in saved.items():
+            autotune.tune_set(N, ax.AX_TUNE_BATCHED, p, **{k: sv[k] for k in autotune.KNOBS})
+
+
+def _noalloc_vs_workspace(ax, prec, p):
     import torch
     dtype = torch.float64 if prec == "fp64" else torch.float32
-    p = ax.AX_FP64 if prec == "fp64" else ax.AX_FP32
     big = [(3, (9, 8, 7)), (5, (6, 5, 5)), (7, (5, 4, 4)), (9, (3, 4, 3)), (3, (2, 2, 1)), (7, (7, 6, 5))]
     small = [(5, (2, 3, 2)), (3, (1, 1, 3))]
     for call, specs in enumerate((big, small)):
